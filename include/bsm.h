@@ -1,0 +1,202 @@
+/*
+ * bsm.h - C ABI of libbsm, the MI355X (gfx950) Wilson-Dirac library.
+ *
+ * The operation (paper, Section II.B): a sparse nearest-neighbour Dirac
+ * operator that couples the fermion vectors of neighbouring lattice sites
+ * through the gauge links, applied to a fermion field and inverted by a
+ * conjugate-gradient solve.  Here it is the Wilson form with hopping
+ * parameter kappa:
+ *
+ *   (D psi)(x) = psi(x) - kappa * H psi(x)
+ *   (H psi)(x) = sum_mu  s+ (1 - g_mu) U_mu(x) psi(x+mu)
+ *                      + s- (1 + g_mu) U_mu(x-mu)^dag psi(x-mu)
+ *
+ * with g_mu Euclidean chiral gamma matrices (g_0 = [[0,1],[1,0]],
+ * g_k = [[0,-i s_k],[i s_k,0]]), s+- = bc[mu] on hops that wrap around the
+ * lattice and 1 otherwise.  D^dag is the same stencil with g_mu -> -g_mu.
+ * Section II.A fixes the fields: an N x N complex link on every link of an
+ * L^3 x T periodic hypercubic lattice, and a colour vector of dimension
+ * d_R >= N in a representation of SU(N) at every site (here times 4 spin
+ * components, one flavour).
+ *
+ * Conventions
+ *   Lattice   L[0] = T (mu = 0 is time), L[1..3] = LX, LY, LZ; all even.
+ *             bc[mu] = +1 periodic, -1 antiperiodic.
+ *   Canonical (user-facing) layout, complex128 interleaved (re, im):
+ *             site s = ((t*LZ + z)*LY + y)*LX + x;
+ *             spinor [V][4 spin][d], block of n RHS [n][V][4][d];
+ *             links  [V][4 mu][N][N] (U_mu(x) at [s][mu]).
+ *   Internal  even-odd checkerboarded structure-of-arrays, private to the
+ *             library; reach it only through pack/unpack and size it only
+ *             through the *_bytes queries.  Parity 0 = even (t+x+y+z even).
+ *             A "full" field is the even block followed by the odd block; a
+ *             "parity" field is one block.
+ *
+ * Ownership: every buffer is allocated and owned by the caller (device
+ * memory unless stated).  The library never frees caller memory.  A context
+ * owns only its own scratch and autotune cache.
+ * Streams: hipStream_t passed as void* (NULL = default stream).  Every call
+ * is asynchronous on that stream except bsm_cg_solve, bsm_batched_solve and
+ * bsm_fgcr_solve, which return after the solve has finished.
+ * Errors: arguments are validated before any launch; a non-OK status leaves
+ * outputs untouched unless stated, and bsm_last_error() (thread-local)
+ * describes it.
+ */
+#ifndef BSM_H
+#define BSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BSM_OK = 0,
+    BSM_ERR_ARG = 1,            /* bad pointer, size, extent, kappa or (N, rep, d_R) */
+    BSM_ERR_UNSUPPORTED = 2,    /* valid request with no compiled kernel */
+    BSM_ERR_HIP = 3,            /* HIP runtime failure; message in bsm_last_error */
+    BSM_ERR_NOMEM = 4,          /* scratch allocation failed */
+    BSM_ERR_NOT_CONVERGED = 5,  /* max_iter reached; best iterate and stats returned */
+    BSM_ERR_NONFINITE = 6       /* NaN/Inf met in a reduction; best iterate returned */
+} bsm_status;
+
+typedef enum { BSM_REP_FUND = 0, BSM_REP_ADJ = 1, BSM_REP_SYM = 2, BSM_REP_ASYM = 3 } bsm_rep;
+
+/* storage precision.  Spinors: F64, F32, or F16S = binary16 with one float32
+ * scale per site (s = max |component| over the 8 d reals, codes =
+ * rne_f16(float32(v * float32(1/s)))).  Links: F64, F32 or F16S meaning plain
+ * binary16 (entries of a unitary matrix are bounded by 1, no scale). */
+typedef enum { BSM_F64 = 0, BSM_F32 = 1, BSM_F16S = 2 } bsm_prec;
+
+typedef struct {
+    int32_t L[4];
+    int32_t bc[4];
+} bsm_lattice;
+
+/* A field's gauge group SU(N), fermion representation and dimension d_R
+ * (must equal dim(N, rep), 2 <= d_R <= 15), spinor precision and link
+ * precision.  Adjoint links are real and stored as real d x d matrices. */
+typedef struct {
+    int32_t N;
+    int32_t rep;        /* bsm_rep */
+    int32_t d_R;
+    int32_t prec;       /* bsm_prec of spinors */
+    int32_t link_prec;  /* bsm_prec of links */
+} bsm_field_desc;
+
+typedef struct bsm_ctx_s *bsm_ctx;
+
+/* Create a context for one lattice on the current HIP device.  Fails with
+ * BSM_ERR_ARG for odd or non-positive extents or bc not +-1. */
+bsm_status bsm_ctx_create(const bsm_lattice *lat, bsm_ctx *out);
+void bsm_ctx_destroy(bsm_ctx ctx);
+
+/* Message for the last non-OK status returned on this thread. */
+const char *bsm_last_error(void);
+
+/* Dimension of the representation (N, rep), or -1. */
+int32_t bsm_rep_dim(int32_t N, int32_t rep);
+
+/* Bytes of an internal gauge field (all 4 V links in desc->link_prec). */
+size_t bsm_gauge_bytes(bsm_ctx ctx, const bsm_field_desc *desc);
+/* Bytes of an internal spinor field: nparity = 1 (one parity block) or 2
+ * (full lattice), times n_rhs consecutive fields. */
+size_t bsm_spinor_bytes(bsm_ctx ctx, const bsm_field_desc *desc, int32_t nparity, int32_t n_rhs);
+
+/* Canonical complex128 spinor(s) -> internal full field(s), in desc->prec.
+ * canon: device [n_rhs][V][4][d]; internal: device, bsm_spinor_bytes(2, n_rhs). */
+bsm_status bsm_pack_spinor(bsm_ctx ctx, const bsm_field_desc *desc, int32_t n_rhs,
+                           const void *canon, void *internal, void *stream);
+/* Internal full field(s) -> canonical complex128 (dequantised for F16S). */
+bsm_status bsm_unpack_spinor(bsm_ctx ctx, const bsm_field_desc *desc, int32_t n_rhs,
+                             const void *internal, void *canon, void *stream);
+
+/* Links in the fermion representation (Section II.A: the fermion vectors
+ * transform under a representation R of SU(N)):
+ *   fund R(U) = U;  adj R_ab = 2 Tr(T_a U T_b U^dag) with T_a the generalised
+ *   Gell-Mann matrices / 2 (for each pair j<k the symmetric then the
+ *   antisymmetric one, then the N-1 diagonal ones);  sym / asym
+ *   R_AB = Tr(e_A^dag U e_B U^T) with e_(aa) = E_aa, e_(ab) = (E_ab +- E_ba)/sqrt2,
+ *   pairs a <= b (sym) or a < b (asym) in lexicographic order.
+ * Computed in FP64, stored in desc->link_prec.
+ * U_fund: device canonical complex128 [V][4][N][N]; U_rep: device,
+ * bsm_gauge_bytes(desc). */
+bsm_status bsm_gauge_represent(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_fund,
+                               void *U_rep, void *stream);
+/* Internal represented links -> canonical complex128 [V][4][d][d] (tests). */
+bsm_status bsm_unpack_gauge(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep,
+                            void *canon, void *stream);
+
+/* out = D in (dagger = 0) or D^dag in (dagger = 1) on full internal fields
+ * in desc->prec (F64 or F32; F16S uses links in desc->link_prec).
+ * in and out must not overlap. */
+bsm_status bsm_dslash_apply(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep,
+                            double kappa, int32_t dagger, const void *in, void *out,
+                            void *stream);
+
+/* Even-odd hopping block: out = a * x + b * H_{p, 1-p} in, where p =
+ * out_parity, in is a parity field of parity 1-p, x (nullable when a = 0) and
+ * out are parity fields of parity p.  dagger selects the blocks of D^dag.
+ * in must not overlap out; x may alias out. */
+bsm_status bsm_dslash_eo(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep,
+                         int32_t out_parity, int32_t dagger, double a, const void *x, double b,
+                         const void *in, void *out, void *stream);
+
+/* ------------------------------------------------------------- vector ops
+ * The Krylov linear algebra of the solvers (paper, Section II.B: CG repeats
+ * the operator plus vector updates), on internal fields of nparity (1 or 2)
+ * parity blocks.  Sums accumulate in FP64 in a fixed order (bitwise
+ * reproducible).  Supported precision mixes: all operands in desc->prec, or
+ * out in prec_out with x (and no y) in desc->prec (a conversion). */
+/* out = a * x + b * y (y nullable when b == 0); out may alias x or y */
+bsm_status bsm_vec_axpby(bsm_ctx ctx, const bsm_field_desc *desc, int32_t nparity, double a,
+                         const void *x, double b, const void *y, int32_t prec_out, void *out,
+                         void *stream);
+/* *result = Re <x, y> (|x|^2 when y is null); synchronous, result on the host */
+bsm_status bsm_vec_dot(bsm_ctx ctx, const bsm_field_desc *desc, int32_t nparity, const void *x,
+                       const void *y, double *result, void *stream);
+
+/* ---------------------------------------------------------------- solvers */
+typedef enum {
+    BSM_SOLVER_PLAIN = 0,       /* CG in FP64 (full D^dag D, or Schur if schur=1) */
+    BSM_SOLVER_MIXED = 1,       /* reliable-update CG, inner precision desc->prec */
+} bsm_solver_variant;
+
+typedef struct {
+    int32_t variant;       /* bsm_solver_variant */
+    int32_t schur;         /* 1: even-odd Schur complement, 0: full lattice */
+    double kappa;
+    double tol;            /* target true relative residual ||b - D x|| / ||b|| */
+    int32_t max_iter;
+    double delta;          /* reliable update threshold (MIXED), e.g. 0.1 */
+    int32_t check_every;   /* iterations between host convergence checks (>= 1) */
+} bsm_solver_params;
+
+typedef struct {
+    int32_t iters;
+    int32_t reliable_updates;
+    int32_t restarts;
+    int32_t converged;
+    double true_rel_res;
+    double seconds;
+} bsm_solver_stats;
+
+/* Solve D x = b (Section II.B: the operator is inverted by conjugate
+ * gradients; here CG on the normal equations).  b and x are full internal
+ * fields in F64 (desc->prec is the inner precision for MIXED and must be F64
+ * for PLAIN); U_rep holds links in desc->link_prec for the inner operator and
+ * U_rep64 the FP64 links used for every true residual (may equal U_rep when
+ * that is F64).  x is overwritten (start x = 0).  Stopping: the normal
+ * residual only triggers a check; the FP64 full-lattice true residual must be
+ * <= tol, otherwise iteration continues with the trigger tightened by 0.3.
+ * Synchronous: returns when done, with stats filled in even on failure. */
+bsm_status bsm_cg_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep,
+                        const void *U_rep64, const bsm_solver_params *params, const void *b,
+                        void *x, bsm_solver_stats *stats, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BSM_H */

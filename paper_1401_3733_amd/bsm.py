@@ -1,0 +1,233 @@
+"""ctypes binding of libbsm (include/bsm.h): argument marshalling only.
+
+Every call forwards to the HIP library; there is no fallback of any kind.
+Device buffers are torch tensors (any dtype; the library sees their data
+pointer), streams are torch CUDA streams (default: the current stream).
+If libbsm.so is missing the first call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbsm.so")
+
+OK, ERR_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_NOMEM, ERR_NOT_CONVERGED, ERR_NONFINITE = range(7)
+REP = {"fund": 0, "adj": 1, "sym": 2, "asym": 3}
+F64, F32, F16S = 0, 1, 2
+PREC = {"f64": F64, "f32": F32, "f16s": F16S}
+SOLVER_PLAIN, SOLVER_MIXED = 0, 1
+
+
+class BsmError(RuntimeError):
+    def __init__(self, status, where, msg):
+        super().__init__(f"{where}: status {status}: {msg}")
+        self.status = status
+
+
+class Lattice(C.Structure):
+    _fields_ = [("L", C.c_int32 * 4), ("bc", C.c_int32 * 4)]
+
+
+class FieldDesc(C.Structure):
+    _fields_ = [("N", C.c_int32), ("rep", C.c_int32), ("d_R", C.c_int32), ("prec", C.c_int32),
+                ("link_prec", C.c_int32)]
+
+
+class SolverParams(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("schur", C.c_int32), ("kappa", C.c_double),
+                ("tol", C.c_double), ("max_iter", C.c_int32), ("delta", C.c_double),
+                ("check_every", C.c_int32)]
+
+
+class SolverStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("reliable_updates", C.c_int32), ("restarts", C.c_int32),
+                ("converged", C.c_int32), ("true_rel_res", C.c_double), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_vp = C.c_void_p
+_SIGS = {
+    "bsm_ctx_create": (C.c_int, [C.POINTER(Lattice), C.POINTER(_vp)]),
+    "bsm_ctx_destroy": (None, [_vp]),
+    "bsm_last_error": (C.c_char_p, []),
+    "bsm_rep_dim": (C.c_int32, [C.c_int32, C.c_int32]),
+    "bsm_gauge_bytes": (C.c_size_t, [_vp, C.POINTER(FieldDesc)]),
+    "bsm_spinor_bytes": (C.c_size_t, [_vp, C.POINTER(FieldDesc), C.c_int32, C.c_int32]),
+    "bsm_pack_spinor": (C.c_int, [_vp, C.POINTER(FieldDesc), C.c_int32, _vp, _vp, _vp]),
+    "bsm_unpack_spinor": (C.c_int, [_vp, C.POINTER(FieldDesc), C.c_int32, _vp, _vp, _vp]),
+    "bsm_gauge_represent": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, _vp, _vp]),
+    "bsm_unpack_gauge": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, _vp, _vp]),
+    "bsm_dslash_apply": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_double, C.c_int32, _vp, _vp, _vp]),
+    "bsm_dslash_eo": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, C.c_int32, C.c_double, _vp,
+                                C.c_double, _vp, _vp, _vp]),
+    "bsm_vec_axpby": (C.c_int, [_vp, C.POINTER(FieldDesc), C.c_int32, C.c_double, _vp, C.c_double, _vp,
+                                C.c_int32, _vp, _vp]),
+    "bsm_vec_dot": (C.c_int, [_vp, C.POINTER(FieldDesc), C.c_int32, _vp, _vp, C.POINTER(C.c_double), _vp]),
+    "bsm_cg_solve": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, _vp, C.POINTER(SolverParams), _vp, _vp,
+                               C.POINTER(SolverStats), _vp]),
+}
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+def lib():
+    """Load libbsm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status, where):
+    if status != OK:
+        raise BsmError(status, where, lib().bsm_last_error().decode())
+    return status
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def desc(N: int, rep: str, prec="f64", link_prec=None) -> FieldDesc:
+    r = REP[rep] if isinstance(rep, str) else int(rep)
+    p = PREC[prec] if isinstance(prec, str) else int(prec)
+    lp = p if link_prec is None else (PREC[link_prec] if isinstance(link_prec, str) else int(link_prec))
+    if link_prec is None and p == F16S:
+        lp = F32
+    return FieldDesc(N, r, bsm_rep_dim(N, r), p, lp)
+
+
+def bsm_rep_dim(N: int, rep) -> int:
+    return lib().bsm_rep_dim(int(N), REP[rep] if isinstance(rep, str) else int(rep))
+
+
+class Context:
+    """bsm_ctx for one lattice: dims = (T, LX, LY, LZ), bc per direction."""
+
+    def __init__(self, dims, bc=(-1, 1, 1, 1)):
+        lat = Lattice((C.c_int32 * 4)(*dims), (C.c_int32 * 4)(*bc))
+        h = C.c_void_p()
+        _check(lib().bsm_ctx_create(C.byref(lat), C.byref(h)), "bsm_ctx_create")
+        self.handle = h
+        self.dims = tuple(dims)
+        self.bc = tuple(bc)
+
+    def close(self):
+        if self.handle:
+            lib().bsm_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # sizes
+    def gauge_bytes(self, d: FieldDesc) -> int:
+        n = lib().bsm_gauge_bytes(self.handle, C.byref(d))
+        if n == 0:
+            _check(ERR_ARG, "bsm_gauge_bytes")
+        return n
+
+    def spinor_bytes(self, d: FieldDesc, nparity=2, n_rhs=1) -> int:
+        n = lib().bsm_spinor_bytes(self.handle, C.byref(d), nparity, n_rhs)
+        if n == 0:
+            _check(ERR_ARG, "bsm_spinor_bytes")
+        return n
+
+    # allocation helpers (torch owns the memory)
+    def new_gauge(self, d: FieldDesc, device="cuda"):
+        import torch
+        return torch.zeros(self.gauge_bytes(d), dtype=torch.uint8, device=device)
+
+    def new_spinor(self, d: FieldDesc, nparity=2, n_rhs=1, device="cuda"):
+        import torch
+        return torch.zeros(self.spinor_bytes(d, nparity, n_rhs), dtype=torch.uint8, device=device)
+
+    # C-ABI calls
+    def bsm_pack_spinor(self, d, canon, internal, n_rhs=1, stream=None):
+        _check(lib().bsm_pack_spinor(self.handle, C.byref(d), n_rhs, _ptr(canon), _ptr(internal),
+                                     _stream(stream)), "bsm_pack_spinor")
+
+    def bsm_unpack_spinor(self, d, internal, canon, n_rhs=1, stream=None):
+        _check(lib().bsm_unpack_spinor(self.handle, C.byref(d), n_rhs, _ptr(internal), _ptr(canon),
+                                       _stream(stream)), "bsm_unpack_spinor")
+
+    def bsm_gauge_represent(self, d, U_fund, U_rep, stream=None):
+        _check(lib().bsm_gauge_represent(self.handle, C.byref(d), _ptr(U_fund), _ptr(U_rep),
+                                         _stream(stream)), "bsm_gauge_represent")
+
+    def bsm_unpack_gauge(self, d, U_rep, canon, stream=None):
+        _check(lib().bsm_unpack_gauge(self.handle, C.byref(d), _ptr(U_rep), _ptr(canon), _stream(stream)),
+               "bsm_unpack_gauge")
+
+    def bsm_dslash_apply(self, d, U_rep, kappa, dagger, inp, out, stream=None):
+        _check(lib().bsm_dslash_apply(self.handle, C.byref(d), _ptr(U_rep), float(kappa), int(dagger),
+                                      _ptr(inp), _ptr(out), _stream(stream)), "bsm_dslash_apply")
+
+    def bsm_dslash_eo(self, d, U_rep, out_parity, dagger, a, x, b, inp, out, stream=None):
+        _check(lib().bsm_dslash_eo(self.handle, C.byref(d), _ptr(U_rep), int(out_parity), int(dagger),
+                                   float(a), _ptr(x), float(b), _ptr(inp), _ptr(out), _stream(stream)),
+               "bsm_dslash_eo")
+
+    def bsm_vec_axpby(self, d, nparity, a, x, b, y, out, prec_out=None, stream=None):
+        po = d.prec if prec_out is None else (PREC[prec_out] if isinstance(prec_out, str) else prec_out)
+        _check(lib().bsm_vec_axpby(self.handle, C.byref(d), int(nparity), float(a), _ptr(x), float(b),
+                                   _ptr(y), int(po), _ptr(out), _stream(stream)), "bsm_vec_axpby")
+
+    def bsm_vec_dot(self, d, nparity, x, y=None, stream=None) -> float:
+        r = C.c_double(0)
+        _check(lib().bsm_vec_dot(self.handle, C.byref(d), int(nparity), _ptr(x), _ptr(y), C.byref(r),
+                                 _stream(stream)), "bsm_vec_dot")
+        return r.value
+
+    def bsm_cg_solve(self, d, U_rep, U_rep64, params: SolverParams, b, x, stream=None, check=True):
+        st = SolverStats()
+        status = lib().bsm_cg_solve(self.handle, C.byref(d), _ptr(U_rep), _ptr(U_rep64), C.byref(params),
+                                    _ptr(b), _ptr(x), C.byref(st), _stream(stream))
+        if check and status not in (OK,):
+            _check(status, "bsm_cg_solve")
+        return status, st.as_dict()
+
+
+def solver_params(kappa, tol=1e-10, schur=True, variant=SOLVER_PLAIN, max_iter=100000, delta=0.1,
+                  check_every=8) -> SolverParams:
+    return SolverParams(variant, int(schur), float(kappa), float(tol), int(max_iter), float(delta),
+                        int(check_every))
+
+
+# ------------------------------------------------------------- conveniences
+def to_device_c128(a: np.ndarray, device="cuda"):
+    """numpy complex128 -> torch complex128 on the GPU (same bytes)."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).to(device)

@@ -1,0 +1,305 @@
+// C ABI: context, validation, sizes, layout conversion, representation and
+// the Wilson-Dirac operator.  Every entry point validates its arguments
+// before launching anything.
+#include <cstring>
+#include <string>
+
+#include "blas.h"
+#include "dispatch.h"
+
+namespace bsm {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+bsm_status fail(bsm_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+bsm_status hip_check(hipError_t e, const char *what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return BSM_ERR_HIP;
+}
+
+bsm_status ctx_work(bsm_ctx ctx, size_t bytes, void **out) {
+    if (bytes > ctx->work_bytes) {
+        if (ctx->work) BSM_HIP(hipFree(ctx->work));
+        ctx->work = nullptr;
+        ctx->work_bytes = 0;
+        hipError_t e = hipMalloc(&ctx->work, bytes);
+        if (e != hipSuccess) return fail(BSM_ERR_NOMEM, "solver scratch allocation failed");
+        ctx->work_bytes = bytes;
+    }
+    *out = ctx->work;
+    return BSM_OK;
+}
+
+int hop_blocks(const Geom &g) { return (g.Vh + 255) / 256; }
+
+template <int SP, int LP>
+struct HopSel {
+    template <int D>
+    struct ByD {
+        static bsm_status run(const Geom &g, bool real, const HopArgs &a, hipStream_t st) {
+            return hop_run<SP, LP, D>(g, real, a, st);
+        }
+    };
+};
+
+bsm_status launch_hop(const Geom &g, int d, bool real, int prec, int link_prec, const HopArgs &a,
+                      hipStream_t st) {
+    if (prec == BSM_F64 && link_prec == BSM_F64)
+        return dispatch_d<HopSel<BSM_F64, BSM_F64>::ByD>(d, g, real, a, st);
+    if (prec == BSM_F32 && link_prec == BSM_F32)
+        return dispatch_d<HopSel<BSM_F32, BSM_F32>::ByD>(d, g, real, a, st);
+    if (prec == BSM_F16S && link_prec == BSM_F32)
+        return dispatch_d<HopSel<BSM_F16S, BSM_F32>::ByD>(d, g, real, a, st);
+    if (prec == BSM_F16S && link_prec == BSM_F16S)
+        return dispatch_d<HopSel<BSM_F16S, BSM_F16S>::ByD>(d, g, real, a, st);
+    return fail(BSM_ERR_UNSUPPORTED,
+                "no operator for spinor precision " + std::to_string(prec) + " with link precision " +
+                    std::to_string(link_prec));
+}
+
+}  // namespace bsm
+
+using namespace bsm;
+
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
+static bsm_status check_ctx(bsm_ctx ctx) {
+    if (!ctx) return fail(BSM_ERR_ARG, "null context");
+    return BSM_OK;
+}
+
+static bsm_status check_desc(const bsm_field_desc *d) {
+    if (!d) return fail(BSM_ERR_ARG, "null field descriptor");
+    if (d->N < 2) return fail(BSM_ERR_ARG, "N must be >= 2");
+    if (d->rep < 0 || d->rep > 3) return fail(BSM_ERR_ARG, "unknown representation");
+    int dim = bsm_rep_dim(d->N, d->rep);
+    if (dim != d->d_R)
+        return fail(BSM_ERR_ARG, "d_R = " + std::to_string(d->d_R) + " does not match dim(N=" +
+                                     std::to_string(d->N) + ", rep) = " + std::to_string(dim));
+    if (d->d_R < 2 || d->d_R > 15) return fail(BSM_ERR_ARG, "d_R must be in [2, 15]");
+    if (d->prec < 0 || d->prec > 2) return fail(BSM_ERR_ARG, "bad spinor precision");
+    if (d->link_prec < 0 || d->link_prec > 2) return fail(BSM_ERR_ARG, "bad link precision");
+    return BSM_OK;
+}
+
+#define CHECK(x)                         \
+    do {                                 \
+        bsm_status _s = (x);             \
+        if (_s != BSM_OK) return _s;     \
+    } while (0)
+
+extern "C" {
+
+const char *bsm_last_error(void) { return g_err.c_str(); }
+
+int32_t bsm_rep_dim(int32_t N, int32_t rep) {
+    if (N < 1) return -1;
+    switch (rep) {
+    case BSM_REP_FUND: return N;
+    case BSM_REP_ADJ: return N * N - 1;
+    case BSM_REP_SYM: return N * (N + 1) / 2;
+    case BSM_REP_ASYM: return N * (N - 1) / 2;
+    }
+    return -1;
+}
+
+bsm_status bsm_ctx_create(const bsm_lattice *lat, bsm_ctx *out) {
+    if (!lat || !out) return fail(BSM_ERR_ARG, "null argument");
+    int64_t V = 1;
+    for (int mu = 0; mu < 4; mu++) {
+        if (lat->L[mu] <= 0 || (lat->L[mu] & 1))
+            return fail(BSM_ERR_ARG, "lattice extents must be positive and even (L[" +
+                                         std::to_string(mu) + "] = " + std::to_string(lat->L[mu]) + ")");
+        if (lat->bc[mu] != 1 && lat->bc[mu] != -1) return fail(BSM_ERR_ARG, "bc must be +1 or -1");
+        V *= lat->L[mu];
+    }
+    if (V / 2 > (1 << 30)) return fail(BSM_ERR_ARG, "lattice too large");
+    bsm_ctx c = new bsm_ctx_s();
+    memset(c, 0, sizeof(*c));
+    c->lat = *lat;
+    Geom &g = c->g;
+    for (int mu = 0; mu < 4; mu++) g.L[mu] = lat->L[mu];
+    g.LXh = lat->L[1] / 2;
+    g.Vh = (int32_t)(V / 2);
+    g.Vh_pad = (g.Vh + 63) / 64 * 64;
+    g.apbc = 0;
+    for (int mu = 0; mu < 4; mu++)
+        if (lat->bc[mu] < 0) g.apbc |= 1 << mu;
+    g.div_xh = FastDiv(g.LXh);
+    g.div_y = FastDiv(g.L[2]);
+    g.div_z = FastDiv(g.L[3]);
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipMalloc(&c->partials, sizeof(double) * kMaxPartials);
+    if (e == hipSuccess) e = hipMalloc(&c->scal, sizeof(double) * kScalars);
+    if (e == hipSuccess) e = hipMemset(c->scal, 0, sizeof(double) * kScalars);
+    if (e == hipSuccess) e = hipHostMalloc(&c->host_scal, sizeof(double) * kScalars, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        bsm_ctx_destroy(c);
+        return hip_check(e, "bsm_ctx_create");
+    }
+    *out = c;
+    return BSM_OK;
+}
+
+void bsm_ctx_destroy(bsm_ctx c) {
+    if (!c) return;
+    if (c->partials) (void)hipFree(c->partials);
+    if (c->scal) (void)hipFree(c->scal);
+    if (c->host_scal) (void)hipHostFree(c->host_scal);
+    if (c->work) (void)hipFree(c->work);
+    delete c;
+}
+
+size_t bsm_gauge_bytes(bsm_ctx ctx, const bsm_field_desc *desc) {
+    if (check_ctx(ctx) != BSM_OK || check_desc(desc) != BSM_OK) return 0;
+    bool real = desc->rep == BSM_REP_ADJ;
+    return 8 * link_block_bytes(desc->link_prec, real, desc->d_R, ctx->g.Vh_pad);
+}
+
+size_t bsm_spinor_bytes(bsm_ctx ctx, const bsm_field_desc *desc, int32_t nparity, int32_t n_rhs) {
+    if (check_ctx(ctx) != BSM_OK || check_desc(desc) != BSM_OK) return 0;
+    if ((nparity != 1 && nparity != 2) || n_rhs < 1) {
+        fail(BSM_ERR_ARG, "nparity must be 1 or 2 and n_rhs >= 1");
+        return 0;
+    }
+    return (size_t)nparity * n_rhs * spinor_block_bytes(desc->prec, desc->d_R, ctx->g.Vh_pad);
+}
+
+static bsm_status pack_common(bsm_ctx ctx, const bsm_field_desc *desc, int32_t n_rhs,
+                              const void *canon, void *internal, void *stream, bool unpack) {
+    CHECK(check_ctx(ctx));
+    CHECK(check_desc(desc));
+    if (!canon || !internal) return fail(BSM_ERR_ARG, "null field pointer");
+    if (n_rhs < 1 || n_rhs > 65535) return fail(BSM_ERR_ARG, "n_rhs out of range");
+    if (!aligned16(canon) || !aligned16(internal)) return fail(BSM_ERR_ARG, "fields must be 16-byte aligned");
+    return launch_pack_spinor(ctx->g, desc->d_R, desc->prec, n_rhs, canon, internal,
+                              (hipStream_t)stream, unpack);
+}
+
+bsm_status bsm_pack_spinor(bsm_ctx ctx, const bsm_field_desc *desc, int32_t n_rhs, const void *canon,
+                           void *internal, void *stream) {
+    return pack_common(ctx, desc, n_rhs, canon, internal, stream, false);
+}
+
+bsm_status bsm_unpack_spinor(bsm_ctx ctx, const bsm_field_desc *desc, int32_t n_rhs,
+                             const void *internal, void *canon, void *stream) {
+    return pack_common(ctx, desc, n_rhs, canon, const_cast<void *>(internal), stream, true);
+}
+
+bsm_status bsm_gauge_represent(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_fund,
+                               void *U_rep, void *stream) {
+    CHECK(check_ctx(ctx));
+    CHECK(check_desc(desc));
+    if (!U_fund || !U_rep) return fail(BSM_ERR_ARG, "null field pointer");
+    if (!aligned16(U_fund) || !aligned16(U_rep)) return fail(BSM_ERR_ARG, "fields must be 16-byte aligned");
+    if (desc->rep != BSM_REP_FUND && desc->N > 6)
+        return fail(BSM_ERR_ARG, "two-index and adjoint representations need N <= 6 for d_R <= 15");
+    return launch_represent(ctx->g, desc->N, desc->rep, desc->d_R, desc->link_prec, U_fund, U_rep,
+                            (hipStream_t)stream);
+}
+
+bsm_status bsm_unpack_gauge(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, void *canon,
+                            void *stream) {
+    CHECK(check_ctx(ctx));
+    CHECK(check_desc(desc));
+    if (!U_rep || !canon) return fail(BSM_ERR_ARG, "null field pointer");
+    return launch_unpack_gauge(ctx->g, desc->d_R, desc->rep == BSM_REP_ADJ, desc->link_prec, U_rep,
+                               canon, (hipStream_t)stream);
+}
+
+bsm_status bsm_dslash_apply(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, double kappa,
+                            int32_t dagger, const void *in, void *out, void *stream) {
+    CHECK(check_ctx(ctx));
+    CHECK(check_desc(desc));
+    if (!U_rep || !in || !out) return fail(BSM_ERR_ARG, "null field pointer");
+    if (!aligned16(in) || !aligned16(out) || !aligned16(U_rep)) return fail(BSM_ERR_ARG, "fields must be 16-byte aligned");
+    if (in == out) return fail(BSM_ERR_ARG, "in and out must not overlap");
+    if (!(kappa >= 0) || !std::isfinite(kappa)) return fail(BSM_ERR_ARG, "kappa must be finite and >= 0");
+    size_t bb = spinor_block_bytes(desc->prec, desc->d_R, ctx->g.Vh_pad);
+    const char *ip = (const char *)in;
+    char *op = (char *)out;
+    if (op < ip + 2 * bb && ip < op + 2 * bb) return fail(BSM_ERR_ARG, "in and out must not overlap");
+    HopArgs a{};
+    a.U = U_rep;
+    a.in[0] = ip + bb;    // even output reads odd sites
+    a.in[1] = ip;
+    a.x[0] = ip;
+    a.x[1] = ip + bb;
+    a.out[0] = op;
+    a.out[1] = op + bb;
+    a.a = 1.0;
+    a.b = -kappa;
+    a.dagger = dagger ? 1 : 0;
+    a.p0 = 0;
+    a.np = 2;
+    a.norm_partials = nullptr;
+    return launch_hop(ctx->g, desc->d_R, desc->rep == BSM_REP_ADJ, desc->prec, desc->link_prec, a,
+                      (hipStream_t)stream);
+}
+
+bsm_status bsm_dslash_eo(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, int32_t out_parity,
+                         int32_t dagger, double a, const void *x, double b, const void *in, void *out,
+                         void *stream) {
+    CHECK(check_ctx(ctx));
+    CHECK(check_desc(desc));
+    if (out_parity != 0 && out_parity != 1) return fail(BSM_ERR_ARG, "out_parity must be 0 or 1");
+    if (!U_rep || !in || !out) return fail(BSM_ERR_ARG, "null field pointer");
+    if (a != 0.0 && !x) return fail(BSM_ERR_ARG, "x is null but a != 0");
+    if (!aligned16(in) || !aligned16(out) || (x && !aligned16(x))) return fail(BSM_ERR_ARG, "fields must be 16-byte aligned");
+    size_t bb = spinor_block_bytes(desc->prec, desc->d_R, ctx->g.Vh_pad);
+    const char *ip = (const char *)in;
+    char *op = (char *)out;
+    if (op < ip + bb && ip < op + bb) return fail(BSM_ERR_ARG, "in and out must not overlap");
+    HopArgs h{};
+    h.U = U_rep;
+    h.in[out_parity] = in;
+    h.x[out_parity] = x;
+    h.out[out_parity] = out;
+    h.a = a;
+    h.b = b;
+    h.dagger = dagger ? 1 : 0;
+    h.p0 = out_parity;
+    h.np = 1;
+    h.norm_partials = nullptr;
+    return launch_hop(ctx->g, desc->d_R, desc->rep == BSM_REP_ADJ, desc->prec, desc->link_prec, h,
+                      (hipStream_t)stream);
+}
+
+bsm_status bsm_vec_axpby(bsm_ctx ctx, const bsm_field_desc *desc, int32_t nparity, double a,
+                         const void *x, double b, const void *y, int32_t prec_out, void *out,
+                         void *stream) {
+    CHECK(check_ctx(ctx));
+    CHECK(check_desc(desc));
+    if (nparity != 1 && nparity != 2) return fail(BSM_ERR_ARG, "nparity must be 1 or 2");
+    if (!x || !out || (b != 0.0 && !y)) return fail(BSM_ERR_ARG, "null field pointer");
+    if (prec_out < 0 || prec_out > 2) return fail(BSM_ERR_ARG, "bad output precision");
+    if (y && prec_out != desc->prec) return fail(BSM_ERR_UNSUPPORTED, "conversion takes no y");
+    Vec O{out, prec_out}, X{const_cast<void *>(x), desc->prec},
+        Y{b != 0.0 ? const_cast<void *>(y) : nullptr, desc->prec};
+    return blas_axpby(ctx->g, desc->d_R, nparity, O, a, X, b, Y, nullptr, (hipStream_t)stream);
+}
+
+bsm_status bsm_vec_dot(bsm_ctx ctx, const bsm_field_desc *desc, int32_t nparity, const void *x,
+                       const void *y, double *result, void *stream) {
+    CHECK(check_ctx(ctx));
+    CHECK(check_desc(desc));
+    if (nparity != 1 && nparity != 2) return fail(BSM_ERR_ARG, "nparity must be 1 or 2");
+    if (!x || !result) return fail(BSM_ERR_ARG, "null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    Vec X{const_cast<void *>(x), desc->prec}, Y{const_cast<void *>(y), desc->prec};
+    CHECK(blas_dot(ctx->g, desc->d_R, nparity, X, Y, ctx->partials, st));
+    CHECK(reduce_into(ctx->partials, blas_blocks(ctx->g, nparity), ctx->scal + S_TMP, st));
+    BSM_HIP(hipMemcpyAsync(ctx->host_scal + S_TMP, ctx->scal + S_TMP, sizeof(double),
+                           hipMemcpyDeviceToHost, st));
+    BSM_HIP(hipStreamSynchronize(st));
+    *result = ctx->host_scal[S_TMP];
+    return BSM_OK;
+}
+
+}  // extern "C"

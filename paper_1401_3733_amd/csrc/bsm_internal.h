@@ -1,0 +1,170 @@
+// Internal definitions shared by the libbsm HIP sources (not part of the ABI).
+//
+// Internal field layout: even-odd checkerboarded structure-of-arrays.
+//   Sites of one parity are numbered by their half index h = lex / 2 with
+//   lex = ((t*LZ + z)*LY + y)*LX + x (LX even, so the two sites x = 2k, 2k+1
+//   of a row share h and have opposite parity).  Each parity block stores
+//   component planes of Vh_pad = round_up(V/2, 64) sites, so lane i of a
+//   wavefront touches site i of a plane and every load is coalesced.
+//   Spinor (4 d complex per site, component c = spin*d + colour):
+//     F64  : 4d planes of double2 (one complex)           16 B per site-plane
+//     F32  : 2d planes of float4  (complex 2k, 2k+1)      16 B
+//     F16S : d  planes of uint4   (complex 4k..4k+3 as half2), then one float
+//            plane with the per-site scale
+//   Links, per (parity q, mu) block, U_mu(x) for x of parity q at index h:
+//     complex: d*d planes of double2 / float2 / half2 (element (i,j) at plane i*d+j)
+//     real   : d*d planes of double / float / half
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+#include <string>
+
+#include "../../include/bsm.h"
+
+namespace bsm {
+
+constexpr int kXcds = 8;        // gfx950: 8 XCDs, each with its own L2
+
+// -------------------------------------------------------------- fast division
+// Exact unsigned division by a runtime constant for n < 2^31
+// (Granlund & Montgomery 1994): q = (umulhi(n, m) + n) >> l.
+struct FastDiv {
+    uint32_t d, m, l;
+    FastDiv() : d(1), m(1), l(0) {}
+    explicit FastDiv(uint32_t d_) : d(d_) {
+        l = 0;
+        while ((1u << l) < d) l++;
+        uint64_t two32 = 1ull << 32;
+        m = (uint32_t)((two32 * ((1ull << l) - d)) / d + 1);
+    }
+    __host__ __device__ inline uint32_t div(uint32_t n) const {
+#ifdef __HIP_DEVICE_COMPILE__
+        uint32_t hi = __umulhi(n, m);
+#else
+        uint32_t hi = (uint32_t)(((uint64_t)n * m) >> 32);
+#endif
+        return (hi + n) >> l;
+    }
+};
+
+// -------------------------------------------------------------- geometry
+struct Geom {
+    int32_t L[4];          // T, LX, LY, LZ
+    int32_t LXh;           // LX / 2
+    int32_t Vh;            // sites per parity
+    int32_t Vh_pad;        // plane stride (sites)
+    int32_t apbc;          // bit mu set: antiperiodic in mu
+    FastDiv div_xh, div_y, div_z;
+};
+
+struct Coords { int32_t t, x, y, z, xh, row; };
+
+// half index h of parity p -> coordinates; row = (t*LZ + z)*LY + y
+__device__ inline Coords decode(const Geom &g, uint32_t h, int p) {
+    Coords c;
+    uint32_t row = g.div_xh.div(h);
+    c.xh = h - row * g.LXh;
+    uint32_t r2 = g.div_y.div(row);
+    c.y = row - r2 * g.L[2];
+    uint32_t t = g.div_z.div(r2);
+    c.z = r2 - t * g.L[3];
+    c.t = t;
+    c.row = row;
+    c.x = 2 * c.xh + ((c.t + c.z + c.y + p) & 1);
+    return c;
+}
+
+// -------------------------------------------------------------- storage traits
+// number of 16-byte planes of a spinor site
+__host__ __device__ constexpr int spinor_planes(int prec, int d) {
+    return prec == BSM_F64 ? 4 * d : prec == BSM_F32 ? 2 * d : d;
+}
+// bytes of one parity block of a spinor field
+__host__ __device__ inline size_t spinor_block_bytes(int prec, int d, int64_t Vh_pad) {
+    size_t b = (size_t)spinor_planes(prec, d) * 16 * Vh_pad;
+    if (prec == BSM_F16S) b += (size_t)4 * Vh_pad;
+    return b;
+}
+__host__ __device__ inline size_t link_elem_bytes(int prec, bool real) {
+    size_t r = prec == BSM_F64 ? 8 : prec == BSM_F32 ? 4 : 2;
+    return real ? r : 2 * r;
+}
+__host__ __device__ inline size_t link_block_bytes(int prec, bool real, int d, int64_t Vh_pad) {
+    return link_elem_bytes(prec, real) * d * d * Vh_pad;
+}
+
+// compute type of the operator for a spinor precision
+template <int P> struct Compute { using T = float; };
+template <> struct Compute<BSM_F64> { using T = double; };
+
+// -------------------------------------------------------------- complex
+template <class T> struct cx { T re, im; };
+template <class T> __device__ __host__ inline cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <class T> __device__ inline cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <class T> __device__ inline cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <class T> __device__ inline cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+// a * b
+template <class T> __device__ inline cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// acc + a * b
+template <class T> __device__ inline cx<T> cfma(cx<T> a, cx<T> b, cx<T> acc) {
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(-a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(a.im, b.re, acc.im);
+    return acc;
+}
+// acc + conj(a) * b
+template <class T> __device__ inline cx<T> cfma_conj(cx<T> a, cx<T> b, cx<T> acc) {
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(-a.im, b.re, acc.im);
+    return acc;
+}
+// i * a
+template <class T> __device__ inline cx<T> times_i(cx<T> a) { return {-a.im, a.re}; }
+
+// -------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+bsm_status fail(bsm_status st, const std::string &msg);
+bsm_status hip_check(hipError_t e, const char *what);
+
+#define BSM_HIP(call)                                                     \
+    do {                                                                  \
+        hipError_t _e = (call);                                           \
+        if (_e != hipSuccess) return ::bsm::hip_check(_e, #call);         \
+    } while (0)
+
+// XCD-aware block order: the hardware hands consecutive workgroups to the
+// 8 XCDs in turn; remap so each XCD walks one contiguous range of sites and
+// neighbour re-reads stay inside that XCD's L2.
+__device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nblk) {
+    uint32_t full = nblk / kXcds * kXcds;
+    if (b >= full) return b;
+    uint32_t per = full / kXcds;
+    return (b % kXcds) * per + b / kXcds;
+}
+
+}  // namespace bsm
+
+// context (defined in api.cpp)
+struct bsm_ctx_s {
+    bsm::Geom g;
+    bsm_lattice lat;
+    int device;
+    // reduction scratch
+    double *partials;       // device, kMaxPartials doubles
+    double *scal;           // device scalars for solvers (kScalars)
+    double *host_scal;      // pinned host mirror
+    void *work;             // solver work buffer (lazily grown)
+    size_t work_bytes;
+};
+
+namespace bsm {
+constexpr int kMaxPartials = 1 << 16;
+constexpr int kScalars = 4096;
+bsm_status ctx_work(bsm_ctx ctx, size_t bytes, void **out);
+}

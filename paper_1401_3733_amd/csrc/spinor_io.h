@@ -1,0 +1,117 @@
+// Device-side access to internal spinor and link storage.
+#pragma once
+#include "bsm_internal.h"
+
+namespace bsm {
+
+// Load the 4d complex components of site h from one parity block.
+template <int P, int D, class T>
+__device__ inline void load_spinor(const void *blk, int64_t stride, uint32_t h, cx<T> (&s)[4 * D]) {
+    if constexpr (P == BSM_F64) {
+        const double2 *b = (const double2 *)blk;
+#pragma unroll
+        for (int c = 0; c < 4 * D; c++) {
+            double2 v = b[c * stride + h];
+            s[c] = mk<T>((T)v.x, (T)v.y);
+        }
+    } else if constexpr (P == BSM_F32) {
+        const float4 *b = (const float4 *)blk;
+#pragma unroll
+        for (int k = 0; k < 2 * D; k++) {
+            float4 v = b[k * stride + h];
+            s[2 * k] = mk<T>(v.x, v.y);
+            s[2 * k + 1] = mk<T>(v.z, v.w);
+        }
+    } else {
+        const uint4 *b = (const uint4 *)blk;
+        const float sc = ((const float *)(b + D * stride))[h];
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            uint4 v = b[k * stride + h];
+            uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                __half2 hh = *reinterpret_cast<__half2 *>(&w[q]);
+                float2 f = __half22float2(hh);
+                s[4 * k + q] = mk<T>(f.x * sc, f.y * sc);
+            }
+        }
+    }
+}
+
+// Store the 4d complex components of site h.  F16S: per-site scale
+// s = max |component| (float32), codes = rne_f16(float32(v * float32(1/s))).
+template <int P, int D, class T>
+__device__ inline void store_spinor(void *blk, int64_t stride, uint32_t h, const cx<T> (&s)[4 * D]) {
+    if constexpr (P == BSM_F64) {
+        double2 *b = (double2 *)blk;
+#pragma unroll
+        for (int c = 0; c < 4 * D; c++) b[c * stride + h] = make_double2((double)s[c].re, (double)s[c].im);
+    } else if constexpr (P == BSM_F32) {
+        float4 *b = (float4 *)blk;
+#pragma unroll
+        for (int k = 0; k < 2 * D; k++)
+            b[k * stride + h] = make_float4((float)s[2 * k].re, (float)s[2 * k].im,
+                                            (float)s[2 * k + 1].re, (float)s[2 * k + 1].im);
+    } else {
+        uint4 *b = (uint4 *)blk;
+        float f[8 * D];
+#pragma unroll
+        for (int c = 0; c < 4 * D; c++) {
+            f[2 * c] = (float)s[c].re;
+            f[2 * c + 1] = (float)s[c].im;
+        }
+        float mx = 0.f;
+#pragma unroll
+        for (int c = 0; c < 8 * D; c++) mx = fmaxf(mx, fabsf(f[c]));
+        float inv = mx > 0.f ? 1.0f / mx : 0.f;
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            uint32_t w[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                __half2 hh = __floats2half2_rn(f[8 * k + 2 * q] * inv, f[8 * k + 2 * q + 1] * inv);
+                w[q] = *reinterpret_cast<uint32_t *>(&hh);
+            }
+            b[k * stride + h] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+        ((float *)(b + D * stride))[h] = mx;
+    }
+}
+
+// Link element (i, j) of a link block (complex or real) as cx<T>.
+template <int LP, bool REAL, class T>
+__device__ inline cx<T> load_link(const void *blk, int64_t stride, int e, uint32_t h) {
+    if constexpr (REAL) {
+        if constexpr (LP == BSM_F64) return mk<T>((T)((const double *)blk)[e * stride + h], (T)0);
+        else if constexpr (LP == BSM_F32) return mk<T>((T)((const float *)blk)[e * stride + h], (T)0);
+        else return mk<T>((T)__half2float(((const __half *)blk)[e * stride + h]), (T)0);
+    } else {
+        if constexpr (LP == BSM_F64) {
+            double2 v = ((const double2 *)blk)[e * stride + h];
+            return mk<T>((T)v.x, (T)v.y);
+        } else if constexpr (LP == BSM_F32) {
+            float2 v = ((const float2 *)blk)[e * stride + h];
+            return mk<T>((T)v.x, (T)v.y);
+        } else {
+            float2 v = __half22float2(((const __half2 *)blk)[e * stride + h]);
+            return mk<T>((T)v.x, (T)v.y);
+        }
+    }
+}
+
+// Sum over a 256-thread workgroup in a fixed order (valid on thread 0):
+// xor-shuffles inside each 64-wide wavefront, then the 4 wavefronts in order.
+__device__ inline double block_sum_256(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __shared__ double ws[4];
+    int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) ws[w] = v;
+    __syncthreads();
+    double s = 0;
+    if (threadIdx.x == 0) s = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+    return s;
+}
+
+}  // namespace bsm

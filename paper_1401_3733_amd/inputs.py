@@ -152,16 +152,50 @@ def _expm_herm(H, eps):
     return _fix_det(_mgs_rows(E))
 
 
+def _expm_su3_cayley_hamilton(Q):
+    """exp(i Q) for traceless Hermitian 3x3 Q as f0 + f1 Q + f2 Q^2, with the
+    coefficients from the invariants c0 = det Q, c1 = Tr Q^2 / 2
+    (Morningstar & Peardon, Phys. Rev. D 69 (2004) 054501, eqs. 19-34)."""
+    Q2 = Q @ Q
+    c1 = 0.5 * np.trace(Q2, axis1=1, axis2=2).real
+    c0 = np.trace(Q2 @ Q, axis1=1, axis2=2).real / 3.0
+    neg = c0 < 0
+    c0a = np.abs(c0)
+    c0max = 2.0 * (c1 / 3.0) ** 1.5
+    theta = np.arccos(np.clip(c0a / np.where(c0max > 0, c0max, 1.0), -1.0, 1.0))
+    u = np.sqrt(c1 / 3.0) * np.cos(theta / 3.0)
+    w = np.sqrt(c1) * np.sin(theta / 3.0)
+    xi0 = np.where(np.abs(w) > 0.05, np.sin(w) / np.where(w != 0, w, 1.0),
+                   1 - w ** 2 / 6 * (1 - w ** 2 / 20 * (1 - w ** 2 / 42)))
+    e2iu, emiu = np.exp(2j * u), np.exp(-1j * u)
+    cw = np.cos(w)
+    h0 = (u ** 2 - w ** 2) * e2iu + emiu * (8 * u ** 2 * cw + 2j * u * (3 * u ** 2 + w ** 2) * xi0)
+    h1 = 2 * u * e2iu - emiu * (2 * u * cw - 1j * (3 * u ** 2 - w ** 2) * xi0)
+    h2 = e2iu - emiu * (cw + 3j * u * xi0)
+    den = 9 * u ** 2 - w ** 2
+    f0, f1, f2 = h0 / den, h1 / den, h2 / den
+    # c0 < 0: f_j(-c0) = (-1)^j conj(f_j(c0))
+    f0 = np.where(neg, np.conj(f0), f0)
+    f1 = np.where(neg, -np.conj(f1), f1)
+    f2 = np.where(neg, np.conj(f2), f2)
+    E = f1[:, None, None] * Q + f2[:, None, None] * Q2
+    E[:, [0, 1, 2], [0, 1, 2]] += f0[:, None]
+    return E
+
+
 def near_identity_sun(n: int, N: int, eps: float, seed: int) -> np.ndarray:
     """U = exp(i eps H), H random traceless Hermitian with E Tr H^2 = (N^2-1)/2
     (the isotropic Gaussian on su(N) with unit-normal coefficients on a basis
-    normalised to Tr T_a T_b = delta_ab / 2); exponentiated through the
-    Hermitian eigendecomposition, re-unitarised by modified Gram-Schmidt and
-    the determinant divided out."""
+    normalised to Tr T_a T_b = delta_ab / 2); exponentiated in closed form
+    for N = 3 (Cayley-Hamilton) and through the Hermitian eigendecomposition
+    otherwise, re-unitarised by modified Gram-Schmidt and the determinant
+    divided out."""
     G = _cgauss(rng(seed), (n, N, N))
     H = 0.5 * (G + G.conj().transpose(0, 2, 1))
     tr = np.trace(H, axis1=1, axis2=2).real / N
     H[:, np.arange(N), np.arange(N)] -= tr[:, None]
+    if N == 3:
+        return _par_map(lambda h: _fix_det(_mgs_rows(_expm_su3_cayley_hamilton(eps * h))), H)
     return _par_map(lambda h: _expm_herm(h, eps), H)
 
 
