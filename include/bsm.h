@@ -144,6 +144,34 @@ bsm_status bsm_dslash_eo(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_
                          int32_t out_parity, int32_t dagger, double a, const void *x, double b,
                          const void *in, void *out, void *stream);
 
+/* Traversal plan of the hopping kernels for one operator type (d_R, link
+ * type, spinor and link precision) in this context.
+ *   order 0: one thread per output site, workgroups over consecutive sites,
+ *            regrouped so each XCD (own L2) walks one contiguous range;
+ *   order 1: 256-site spatial tiles, workgroups walk (t-chunk, tile, t) with
+ *            t fastest over chunks of tchunk time slices;
+ *   order 2: as order 0 without the per-XCD regrouping;
+ *   order 3: column sweep: one thread per spatial site over tchunk
+ *            consecutive time slices, time neighbours reused from registers
+ *            (d_R <= 6).
+ * Orders 1 and 3 need LX*LY*LZ/2 to be a multiple of 256 and T a multiple
+ * of tchunk; BSM_ERR_ARG otherwise.  Links are always streamed with
+ * non-temporal loads. */
+bsm_status bsm_set_hop_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t order, int32_t tchunk);
+/* us: measured time per hop of the chosen plan (0 if never tuned) */
+bsm_status bsm_get_hop_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t *order, int32_t *tchunk,
+                            float *us);
+/* Time every plan that fits this lattice on the given links (scratch
+ * spinors owned by the context) and keep the fastest for this operator type.
+ * Synchronous. */
+bsm_status bsm_autotune(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, void *stream);
+
+/* Plain device copy of bytes (multiple of 16, 16-byte aligned) with 16-byte
+ * accesses on `blocks` workgroups (<= 0: 2048); nontemporal selects streaming
+ * loads and stores.  Calibrates the achievable HBM bandwidth. */
+bsm_status bsm_stream_copy(const void *src, void *dst, size_t bytes, int32_t nontemporal,
+                           int32_t blocks, void *stream);
+
 /* ------------------------------------------------------------- vector ops
  * The Krylov linear algebra of the solvers (paper, Section II.B: CG repeats
  * the operator plus vector updates), on internal fields of nparity (1 or 2)

@@ -69,6 +69,11 @@ _SIGS = {
     "bsm_dslash_apply": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_double, C.c_int32, _vp, _vp, _vp]),
     "bsm_dslash_eo": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, C.c_int32, C.c_double, _vp,
                                 C.c_double, _vp, _vp, _vp]),
+    "bsm_set_hop_plan": (C.c_int, [_vp, C.POINTER(FieldDesc), C.c_int32, C.c_int32]),
+    "bsm_get_hop_plan": (C.c_int, [_vp, C.POINTER(FieldDesc), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_float)]),
+    "bsm_autotune": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, _vp]),
+    "bsm_stream_copy": (C.c_int, [_vp, _vp, C.c_size_t, C.c_int32, C.c_int32, _vp]),
     "bsm_vec_axpby": (C.c_int, [_vp, C.POINTER(FieldDesc), C.c_int32, C.c_double, _vp, C.c_double, _vp,
                                 C.c_int32, _vp, _vp]),
     "bsm_vec_dot": (C.c_int, [_vp, C.POINTER(FieldDesc), C.c_int32, _vp, _vp, C.POINTER(C.c_double), _vp]),
@@ -200,6 +205,19 @@ class Context:
                                    float(a), _ptr(x), float(b), _ptr(inp), _ptr(out), _stream(stream)),
                "bsm_dslash_eo")
 
+    def bsm_set_hop_plan(self, d, order, tchunk=1):
+        _check(lib().bsm_set_hop_plan(self.handle, C.byref(d), int(order), int(tchunk)), "bsm_set_hop_plan")
+
+    def bsm_get_hop_plan(self, d):
+        o, t, us = C.c_int32(), C.c_int32(), C.c_float()
+        _check(lib().bsm_get_hop_plan(self.handle, C.byref(d), C.byref(o), C.byref(t), C.byref(us)),
+               "bsm_get_hop_plan")
+        return dict(order=o.value, tchunk=t.value, us=us.value)
+
+    def bsm_autotune(self, d, U_rep, stream=None):
+        _check(lib().bsm_autotune(self.handle, C.byref(d), _ptr(U_rep), _stream(stream)), "bsm_autotune")
+        return self.bsm_get_hop_plan(d)
+
     def bsm_vec_axpby(self, d, nparity, a, x, b, y, out, prec_out=None, stream=None):
         po = d.prec if prec_out is None else (PREC[prec_out] if isinstance(prec_out, str) else prec_out)
         _check(lib().bsm_vec_axpby(self.handle, C.byref(d), int(nparity), float(a), _ptr(x), float(b),
@@ -224,6 +242,12 @@ def solver_params(kappa, tol=1e-10, schur=True, variant=SOLVER_PLAIN, max_iter=1
                   check_every=8) -> SolverParams:
     return SolverParams(variant, int(schur), float(kappa), float(tol), int(max_iter), float(delta),
                         int(check_every))
+
+
+def bsm_stream_copy(src, dst, nbytes=None, nontemporal=0, blocks=0, stream=None):
+    n = src.numel() * src.element_size() if nbytes is None else nbytes
+    _check(lib().bsm_stream_copy(_ptr(src), _ptr(dst), n, int(nontemporal), int(blocks), _stream(stream)),
+           "bsm_stream_copy")
 
 
 # ------------------------------------------------------------- conveniences

@@ -1,8 +1,10 @@
 // C ABI: context, validation, sizes, layout conversion, representation and
 // the Wilson-Dirac operator.  Every entry point validates its arguments
 // before launching anything.
+#include <cstdlib>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "blas.h"
 #include "dispatch.h"
@@ -30,6 +32,9 @@ bsm_status ctx_work(bsm_ctx ctx, size_t bytes, void **out) {
         ctx->work_bytes = 0;
         hipError_t e = hipMalloc(&ctx->work, bytes);
         if (e != hipSuccess) return fail(BSM_ERR_NOMEM, "solver scratch allocation failed");
+        // padding sites of internal fields are never written by the operator
+        // kernels and must read as zero in the vector reductions
+        BSM_HIP(hipMemset(ctx->work, 0, bytes));
         ctx->work_bytes = bytes;
     }
     *out = ctx->work;
@@ -37,6 +42,20 @@ bsm_status ctx_work(bsm_ctx ctx, size_t bytes, void **out) {
 }
 
 int hop_blocks(const Geom &g) { return (g.Vh + 255) / 256; }
+
+static bool plan_fits(const Geom &g, const HopPlan &p, int d) {
+    if (p.order == 0 || p.order == 2) return true;
+    if (p.order == 3 && d > kColMaxD) return false;
+    int64_t S3 = (int64_t)g.Vh / g.L[0];
+    return p.tchunk >= 1 && S3 % 256 == 0 && g.L[0] % p.tchunk == 0;
+}
+
+void apply_plan(bsm_ctx ctx, int d, bool real, int prec, int link_prec, HopArgs &a) {
+    HopPlan p = ctx->plans[d & 15][real ? 1 : 0][prec % 3][link_prec % 3];
+    if (!plan_fits(ctx->g, p, d)) p = HopPlan{};
+    a.order = p.order;
+    a.tchunk = p.tchunk;
+}
 
 template <int SP, int LP>
 struct HopSel {
@@ -239,6 +258,7 @@ bsm_status bsm_dslash_apply(bsm_ctx ctx, const bsm_field_desc *desc, const void 
     a.p0 = 0;
     a.np = 2;
     a.norm_partials = nullptr;
+    apply_plan(ctx, desc->d_R, desc->rep == BSM_REP_ADJ, desc->prec, desc->link_prec, a);
     return launch_hop(ctx->g, desc->d_R, desc->rep == BSM_REP_ADJ, desc->prec, desc->link_prec, a,
                       (hipStream_t)stream);
 }
@@ -267,6 +287,7 @@ bsm_status bsm_dslash_eo(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_
     h.p0 = out_parity;
     h.np = 1;
     h.norm_partials = nullptr;
+    apply_plan(ctx, desc->d_R, desc->rep == BSM_REP_ADJ, desc->prec, desc->link_prec, h);
     return launch_hop(ctx->g, desc->d_R, desc->rep == BSM_REP_ADJ, desc->prec, desc->link_prec, h,
                       (hipStream_t)stream);
 }
@@ -299,6 +320,90 @@ bsm_status bsm_vec_dot(bsm_ctx ctx, const bsm_field_desc *desc, int32_t nparity,
                            hipMemcpyDeviceToHost, st));
     BSM_HIP(hipStreamSynchronize(st));
     *result = ctx->host_scal[S_TMP];
+    return BSM_OK;
+}
+
+bsm_status bsm_set_hop_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t order, int32_t tchunk) {
+    CHECK(check_ctx(ctx));
+    CHECK(check_desc(desc));
+    HopPlan p;
+    p.order = order;
+    p.tchunk = tchunk;
+    if (order < 0 || order > 3) return fail(BSM_ERR_ARG, "order must be 0, 1, 2 or 3");
+    if (!plan_fits(ctx->g, p, desc->d_R)) return fail(BSM_ERR_ARG, "plan does not tile this lattice");
+    ctx->plans[desc->d_R][desc->rep == BSM_REP_ADJ][desc->prec][desc->link_prec] = p;
+    return BSM_OK;
+}
+
+bsm_status bsm_autotune(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, void *stream) {
+    CHECK(check_ctx(ctx));
+    CHECK(check_desc(desc));
+    if (!U_rep) return fail(BSM_ERR_ARG, "null gauge field");
+    hipStream_t st = (hipStream_t)stream;
+    const Geom &g = ctx->g;
+    const bool real = desc->rep == BSM_REP_ADJ;
+    size_t bb = spinor_block_bytes(desc->prec, desc->d_R, g.Vh_pad);
+    void *work = nullptr;
+    CHECK(ctx_work(ctx, 2 * bb, &work));
+    BSM_HIP(hipMemsetAsync(work, 0, 2 * bb, st));
+    std::vector<HopPlan> cand;
+    {
+        HopPlan p;
+        cand.push_back(p);
+        for (int order : {1, 3})
+            for (int tc : {2, 4, 8, 16, 32}) {
+                p.order = order;
+                p.tchunk = tc;
+                if (plan_fits(g, p, desc->d_R)) cand.push_back(p);
+            }
+    }
+    hipEvent_t e0, e1;
+    BSM_HIP(hipEventCreate(&e0));
+    BSM_HIP(hipEventCreate(&e1));
+    HopPlan best;
+    float best_us = 1e30f;
+    const int reps = 10;
+    for (const HopPlan &p : cand) {
+        HopArgs a{};
+        a.U = U_rep;
+        a.a = 0.0;
+        a.b = 1.0;
+        a.np = 1;
+        a.order = p.order;
+        a.tchunk = p.tchunk;
+        float ms = 0.f;
+        for (int rep = -2; rep < reps; rep++) {
+            int par = rep & 1;
+            a.p0 = par;
+            a.in[par] = (char *)work + (1 - par) * bb;
+            a.out[par] = (char *)work + par * bb;
+            if (rep == 0) BSM_HIP(hipEventRecord(e0, st));
+            CHECK(launch_hop(g, desc->d_R, real, desc->prec, desc->link_prec, a, st));
+        }
+        BSM_HIP(hipEventRecord(e1, st));
+        BSM_HIP(hipEventSynchronize(e1));
+        BSM_HIP(hipEventElapsedTime(&ms, e0, e1));
+        float us = 1000.f * ms / reps;
+        if (us < best_us) {
+            best_us = us;
+            best = p;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    best.us = best_us;
+    ctx->plans[desc->d_R][real][desc->prec][desc->link_prec] = best;
+    return BSM_OK;
+}
+
+bsm_status bsm_get_hop_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t *order, int32_t *tchunk,
+                            float *us) {
+    CHECK(check_ctx(ctx));
+    CHECK(check_desc(desc));
+    const HopPlan &p = ctx->plans[desc->d_R][desc->rep == BSM_REP_ADJ][desc->prec][desc->link_prec];
+    if (order) *order = p.order;
+    if (tchunk) *tchunk = p.tchunk;
+    if (us) *us = p.us;
     return BSM_OK;
 }
 

@@ -9,7 +9,9 @@
 
 namespace bsm {
 
-constexpr int kBlasMaxBlocks = 4096;
+// one site per thread (grid-stride only beyond kMaxPartials workgroups):
+// a grid-stride loop over few workgroups streams measurably slower
+constexpr int kBlasMaxBlocks = kMaxPartials;
 
 // chunk k = complex components 4k..4k+3 of one site, as 8 doubles
 template <int P, int D>

@@ -148,6 +148,12 @@ __device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nblk) {
     return (b % kXcds) * per + b / kXcds;
 }
 
+// hop traversal plan, chosen per (d_R, link type, precisions) by bsm_autotune
+struct HopPlan {
+    int order = 0, tchunk = 1;
+    float us = 0.f;   // measured time per hop when tuned (0: default plan)
+};
+
 }  // namespace bsm
 
 // context (defined in api.cpp)
@@ -161,6 +167,7 @@ struct bsm_ctx_s {
     double *host_scal;      // pinned host mirror
     void *work;             // solver work buffer (lazily grown)
     size_t work_bytes;
+    bsm::HopPlan plans[16][2][3][3];   // [d_R][real][spinor prec][link prec]
 };
 
 namespace bsm {

@@ -40,6 +40,7 @@ static bool trace_enabled() {
 }
 
 struct Op {
+    bsm_ctx ctx;
     Geom g;
     int d;
     bool real;
@@ -65,6 +66,7 @@ static bsm_status op_apply(const Op &o, int dagger, const void *x, void *y, bool
         a.p0 = 1; a.np = 1;
         a.in[1] = x; a.x[1] = nullptr; a.out[1] = o.tmp;
         a.a = 0.0; a.b = 1.0; a.norm_partials = nullptr;
+        apply_plan(o.ctx, o.d, o.real, o.sprec, o.lprec, a);
         bsm_status s = launch_hop(o.g, o.d, o.real, o.sprec, o.lprec, a, st);
         if (s != BSM_OK) return s;
         // y_e = x_e - kappa^2 H_eo tmp_o
@@ -74,7 +76,8 @@ static bsm_status op_apply(const Op &o, int dagger, const void *x, void *y, bool
         b.in[0] = o.tmp; b.x[0] = x; b.out[0] = y;
         b.a = 1.0; b.b = -o.kappa * o.kappa;
         b.norm_partials = norm ? o.partials : nullptr;
-        if (np) *np = hop_blocks(o.g);
+        apply_plan(o.ctx, o.d, o.real, o.sprec, o.lprec, b);
+        if (np) *np = hop_grid(o.g, b);
         return launch_hop(o.g, o.d, o.real, o.sprec, o.lprec, b, st);
     }
     size_t bb = blk(o);
@@ -86,7 +89,8 @@ static bsm_status op_apply(const Op &o, int dagger, const void *x, void *y, bool
     a.out[0] = yp; a.out[1] = yp + bb;
     a.a = 1.0; a.b = -o.kappa;
     a.norm_partials = norm ? o.partials : nullptr;
-    if (np) *np = 2 * hop_blocks(o.g);
+    apply_plan(o.ctx, o.d, o.real, o.sprec, o.lprec, a);
+    if (np) *np = hop_grid(o.g, a);
     return launch_hop(o.g, o.d, o.real, o.sprec, o.lprec, a, st);
 }
 
@@ -429,6 +433,7 @@ extern "C" bsm_status bsm_cg_solve(bsm_ctx ctx, const bsm_field_desc *desc, cons
     S.prm = prm;
     S.b = (const char *)b;
     S.x = (char *)x;
+    S.op64.ctx = ctx;
     S.op64.g = ctx->g;
     S.op64.d = S.d;
     S.op64.real = S.real;

@@ -5,25 +5,33 @@
 #pragma once
 #include "bsm_internal.h"
 
+// Bit d of BSM_DMASK selects whether d_R = d is compiled (development
+// builds may restrict it to shorten compile times; release builds keep all).
+#ifndef BSM_DMASK
+#define BSM_DMASK 0xFFFC
+#endif
+
 namespace bsm {
 
 template <template <int> class F, class... A>
 bsm_status dispatch_d(int d, A &&...args) {
+    if (d < 2 || d > 15 || !((BSM_DMASK >> d) & 1))
+        return fail(BSM_ERR_UNSUPPORTED, "no kernel compiled for d_R = " + std::to_string(d));
     switch (d) {
-    case 2: return F<2>::run(args...);
-    case 3: return F<3>::run(args...);
-    case 4: return F<4>::run(args...);
-    case 5: return F<5>::run(args...);
-    case 6: return F<6>::run(args...);
-    case 7: return F<7>::run(args...);
-    case 8: return F<8>::run(args...);
-    case 9: return F<9>::run(args...);
-    case 10: return F<10>::run(args...);
-    case 11: return F<11>::run(args...);
-    case 12: return F<12>::run(args...);
-    case 13: return F<13>::run(args...);
-    case 14: return F<14>::run(args...);
-    case 15: return F<15>::run(args...);
+    case 2: if constexpr ((BSM_DMASK >> 2) & 1) return F<2>::run(args...); break;
+    case 3: if constexpr ((BSM_DMASK >> 3) & 1) return F<3>::run(args...); break;
+    case 4: if constexpr ((BSM_DMASK >> 4) & 1) return F<4>::run(args...); break;
+    case 5: if constexpr ((BSM_DMASK >> 5) & 1) return F<5>::run(args...); break;
+    case 6: if constexpr ((BSM_DMASK >> 6) & 1) return F<6>::run(args...); break;
+    case 7: if constexpr ((BSM_DMASK >> 7) & 1) return F<7>::run(args...); break;
+    case 8: if constexpr ((BSM_DMASK >> 8) & 1) return F<8>::run(args...); break;
+    case 9: if constexpr ((BSM_DMASK >> 9) & 1) return F<9>::run(args...); break;
+    case 10: if constexpr ((BSM_DMASK >> 10) & 1) return F<10>::run(args...); break;
+    case 11: if constexpr ((BSM_DMASK >> 11) & 1) return F<11>::run(args...); break;
+    case 12: if constexpr ((BSM_DMASK >> 12) & 1) return F<12>::run(args...); break;
+    case 13: if constexpr ((BSM_DMASK >> 13) & 1) return F<13>::run(args...); break;
+    case 14: if constexpr ((BSM_DMASK >> 14) & 1) return F<14>::run(args...); break;
+    case 15: if constexpr ((BSM_DMASK >> 15) & 1) return F<15>::run(args...); break;
     }
     return fail(BSM_ERR_UNSUPPORTED, "no kernel for d_R = " + std::to_string(d));
 }
@@ -50,7 +58,33 @@ struct HopArgs {
     int dagger;
     int p0, np;                 // first output parity, number of parities (1 or 2)
     double *norm_partials;
+    // traversal plan (set by launch_hop from the context's tuning):
+    //   order 0: workgroup w covers half indices [256 w, 256 w + 256)
+    //   order 1: the half lattice is [t][s] with s < S3 = Vh / T split into
+    //            256-site tiles; workgroups walk (t-chunk, tile, t in chunk)
+    //            with t fastest, so the 8 neighbours of a site are loaded by
+    //            workgroups that run at the same time
+    //   order 2: as order 0 but workgroups are not regrouped per XCD
+    //   order 3: column sweep, one thread per spatial site over tchunk time
+    //            slices (time neighbours reused from registers)
+    // Links are always streamed with non-temporal loads (each link is used
+    // once per hop, so it should not displace spinors from L2).
+    int order, tchunk;
 };
+
+// largest d_R compiled with the column sweep (its register ring grows with d_R)
+constexpr int kColMaxD = 6;
+
+// workgroups of a hop launch under its plan (= number of norm partials)
+inline int hop_grid(const Geom &g, const HopArgs &a) {
+    int per = (g.Vh + 255) / 256;
+    if (a.order == 3) per = (g.Vh / g.L[0] / 256) * (g.L[0] / a.tchunk);
+    return per * a.np;
+}
+
+// fill a.order / a.tchunk / a.nt from the context's plan for this operator
+// (falls back to order 0 where the lattice does not tile)
+void apply_plan(bsm_ctx ctx, int d, bool real, int prec, int link_prec, HopArgs &a);
 bsm_status launch_hop(const Geom &g, int d, bool real, int prec, int link_prec, const HopArgs &a,
                       hipStream_t st);
 // one (spinor precision, link precision, d_R) instance; defined in hop.h and

@@ -67,17 +67,40 @@ __device__ inline void reconstruct(cx<T> (&acc)[4 * D], T sg, T w, const cx<T> (
     }
 }
 
-// g = U h (forward) or U^dag h (backward) for both spin components
-template <int D, bool REAL, int LP, bool BACK, class T>
-__device__ inline void link_mul(const void *blk, int64_t stride, uint32_t hl, const cx<T> (&h0)[D],
-                                const cx<T> (&h1)[D], cx<T> (&g0)[D], cx<T> (&g1)[D]) {
+// Links small enough to be loaded whole before the multiply (all loads of a
+// hop in flight together); larger ones stream row by row.
+template <int D> constexpr bool kLinkWhole = D * D <= 16;
+
+template <int D, bool REAL, int LP, bool NT, class T>
+struct LinkRegs {
+    cx<T> u[kLinkWhole<D> ? D * D : 1];
+    __device__ inline void load(const void *blk, int64_t stride, uint32_t hl) {
+        if constexpr (kLinkWhole<D>) {
+#pragma unroll
+            for (int e = 0; e < D * D; e++) u[e] = load_link<LP, REAL, T, NT>(blk, stride, e, hl);
+        }
+    }
+};
+
+// g = U h (forward) or U^dag h (backward) for both spin components; the link
+// comes from L (whole-matrix case) or is streamed from blk
+template <int D, bool REAL, int LP, bool BACK, bool NT, class T>
+__device__ inline void link_mul(const LinkRegs<D, REAL, LP, NT, T> &L, const void *blk, int64_t stride,
+                                uint32_t hl, const cx<T> (&h0)[D], const cx<T> (&h1)[D], cx<T> (&g0)[D],
+                                cx<T> (&g1)[D]) {
 #pragma unroll
     for (int i = 0; i < D; i++) { g0[i] = mk<T>(0, 0); g1[i] = mk<T>(0, 0); }
 #pragma unroll
-    for (int i = 0; i < D; i++)
+    for (int i = 0; i < D; i++) {
+        cx<T> row[D];
 #pragma unroll
         for (int j = 0; j < D; j++) {
-            cx<T> u = load_link<LP, REAL, T>(blk, stride, i * D + j, hl);
+            if constexpr (kLinkWhole<D>) row[j] = L.u[i * D + j];
+            else row[j] = load_link<LP, REAL, T, NT>(blk, stride, i * D + j, hl);
+        }
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            const cx<T> u = row[j];
             if constexpr (REAL) {
                 // real link: U_ij (forward) and U^T_ji (backward) are the same number
                 if constexpr (!BACK) {
@@ -98,56 +121,139 @@ __device__ inline void link_mul(const void *blk, int64_t stride, uint32_t hl, co
                 }
             }
         }
-}
-
-template <int MU, int D, bool REAL, int SP, int LP, class T>
-__device__ inline void hop_dir(const Geom &g, const Coords &c, int p, uint32_t h, const char *U,
-                               size_t lblk, const char *in, T eta, cx<T> (&acc)[4 * D]) {
-    const int64_t S = g.Vh_pad;
-    // coordinates in direction mu, extent
-    const int Lmu = g.L[MU];
-    const int xm = MU == 0 ? c.t : MU == 1 ? c.x : MU == 2 ? c.y : c.z;
-    const bool ap = (g.apbc >> MU) & 1;
-#pragma unroll
-    for (int dir = 0; dir < 2; dir++) {
-        const bool back = dir == 1;
-        int xn = back ? xm - 1 : xm + 1;
-        T w = (T)1;
-        if (xn == Lmu) { xn = 0; if (ap) w = (T)-1; }
-        if (xn < 0) { xn = Lmu - 1; if (ap) w = (T)-1; }
-        uint32_t hn;
-        if constexpr (MU == 1) {
-            hn = (uint32_t)c.row * g.LXh + (xn >> 1);
-        } else {
-            int t = c.t, z = c.z, y = c.y;
-            if (MU == 0) t = xn;
-            if (MU == 2) y = xn;
-            if (MU == 3) z = xn;
-            uint32_t row = ((uint32_t)t * g.L[3] + z) * g.L[2] + y;
-            hn = row * g.LXh + c.xh;
-        }
-        cx<T> s[4 * D];
-        load_spinor<SP, D, T>(in, S, hn, s);
-        const T sg = back ? -eta : eta;
-        cx<T> h0[D], h1[D], g0[D], g1[D];
-        project<MU, D, T>(s, sg, h0, h1);
-        if (!back) {
-            const char *blk = U + (size_t)(p * 4 + MU) * lblk;
-            link_mul<D, REAL, LP, false, T>(blk, S, h, h0, h1, g0, g1);
-        } else {
-            const char *blk = U + (size_t)((1 - p) * 4 + MU) * lblk;
-            link_mul<D, REAL, LP, true, T>(blk, S, hn, h0, h1, g0, g1);
-        }
-        reconstruct<MU, D, T>(acc, sg, w, g0, g1);
     }
 }
 
+// neighbour of c one step along +mu (back = false) or -mu: half index and the
+// boundary factor of the hop
+template <int MU>
+__device__ inline uint32_t neighbour(const Geom &g, const Coords &c, bool back, float &w) {
+    const int Lmu = g.L[MU];
+    const int xm = MU == 0 ? c.t : MU == 1 ? c.x : MU == 2 ? c.y : c.z;
+    int xn = back ? xm - 1 : xm + 1;
+    w = 1.f;
+    const bool ap = (g.apbc >> MU) & 1;
+    if (xn == Lmu) { xn = 0; if (ap) w = -1.f; }
+    if (xn < 0) { xn = Lmu - 1; if (ap) w = -1.f; }
+    if constexpr (MU == 1) {
+        return (uint32_t)c.row * g.LXh + (xn >> 1);
+    } else {
+        int t = c.t, z = c.z, y = c.y;
+        if (MU == 0) t = xn;
+        if (MU == 2) y = xn;
+        if (MU == 3) z = xn;
+        uint32_t row = ((uint32_t)t * g.L[3] + z) * g.L[2] + y;
+        return row * g.LXh + c.xh;
+    }
+}
+
+// one hop with the neighbour's half spinor already projected: link multiply
+// (forward link of this site, or the daggered link of the neighbour) and
+// reconstruction into acc
+// Non-temporal link loads per spinor precision (bit SP of BSM_LINK_NT).
+#ifndef BSM_LINK_NT
+#define BSM_LINK_NT 0x7
+#endif
+
+// link block and site of a hop: forward uses U_mu(x) (this site, parity p),
+// backward U_mu(x - mu) stored at the neighbour (parity 1-p)
+template <int MU, bool BACK>
+__device__ inline const char *link_block(const char *U, size_t lblk, int p) {
+    return U + (size_t)((BACK ? 1 - p : p) * 4 + MU) * lblk;
+}
+
+template <int MU, int D, bool REAL, int LP, bool BACK, class T, bool NT = true>
+__device__ inline void hop_half(const Geom &g, const LinkRegs<D, REAL, LP, NT, T> &L, const char *blk,
+                                uint32_t hl, T sg, T w, const cx<T> (&h0)[D], const cx<T> (&h1)[D],
+                                cx<T> (&acc)[4 * D]) {
+    cx<T> g0[D], g1[D];
+    link_mul<D, REAL, LP, BACK, NT, T>(L, blk, g.Vh_pad, hl, h0, h1, g0, g1);
+    reconstruct<MU, D, T>(acc, sg, w, g0, g1);
+}
+
+// both hops along mu, loading the neighbour spinors
+template <int MU, int D, bool REAL, int SP, int LP, class T>
+__device__ inline void hop_dir(const Geom &g, const Coords &c, int p, uint32_t h, const char *U,
+                               size_t lblk, const char *in, T eta, cx<T> (&acc)[4 * D]) {
+#pragma unroll
+    for (int dir = 0; dir < 2; dir++) {
+        const bool back = dir == 1;
+        float wf;
+        const uint32_t hn = neighbour<MU>(g, c, back, wf);
+        constexpr bool NT = (BSM_LINK_NT >> SP) & 1;
+        // issue the spinor and link loads of this hop before any arithmetic
+        cx<T> s[4 * D];
+        load_spinor<SP, D, T>(in, g.Vh_pad, hn, s);
+        LinkRegs<D, REAL, LP, NT, T> L;
+        const char *blk = back ? link_block<MU, true>(U, lblk, p) : link_block<MU, false>(U, lblk, p);
+        const uint32_t hl = back ? hn : h;
+        L.load(blk, g.Vh_pad, hl);
+        const T sg = back ? -eta : eta;
+        cx<T> h0[D], h1[D];
+        project<MU, D, T>(s, sg, h0, h1);
+        if (!back) hop_half<MU, D, REAL, LP, false, T, NT>(g, L, blk, hl, sg, (T)wf, h0, h1, acc);
+        else hop_half<MU, D, REAL, LP, true, T, NT>(g, L, blk, hl, sg, (T)wf, h0, h1, acc);
+    }
+}
+
+// out = a x + b acc, stored; returns |out|^2 contribution when asked
+template <int D, int SP, class T>
+__device__ inline double hop_epilogue(const Geom &g, const HopArgs &a, int p, uint32_t h, cx<T> (&acc)[4 * D]) {
+    const T bb = (T)a.b;
+#pragma unroll
+    for (int k = 0; k < 4 * D; k++) acc[k] = bb * acc[k];
+    if (a.a != 0.0) {
+        cx<T> xs[4 * D];
+        load_spinor<SP, D, T>(a.x[p], g.Vh_pad, h, xs);
+        const T aa = (T)a.a;
+#pragma unroll
+        for (int k = 0; k < 4 * D; k++) {
+            acc[k].re = fma(aa, xs[k].re, acc[k].re);
+            acc[k].im = fma(aa, xs[k].im, acc[k].im);
+        }
+    }
+    store_spinor<SP, D, T>(a.out[p], g.Vh_pad, h, acc);
+    double nrm = 0.0;
+    if (a.norm_partials) {
+#pragma unroll
+        for (int k = 0; k < 4 * D; k++)
+            nrm += (double)acc[k].re * acc[k].re + (double)acc[k].im * acc[k].im;
+    }
+    return nrm;
+}
+
+// site handled by this thread under the traversal plan (see HopArgs)
+__device__ inline uint32_t plan_site(const HopArgs &a, uint32_t bl, uint32_t S3, uint32_t ntile) {
+    if (a.order != 1) return bl * 256 + threadIdx.x;
+    const uint32_t tc = (uint32_t)a.tchunk;
+    const uint32_t per_chunk = ntile * tc;
+    const uint32_t chunk = bl / per_chunk;
+    const uint32_t rem = bl - chunk * per_chunk;
+    const uint32_t tile = rem / tc;
+    const uint32_t t = chunk * tc + (rem - tile * tc);
+    return t * S3 + tile * 256 + threadIdx.x;
+}
+
+// Waves per SIMD the compiler must allow for (caps registers); 0 = its choice.
+#ifndef BSM_HOP_WAVES
+#define BSM_HOP_WAVES 0
+#endif
+#if BSM_HOP_WAVES > 0
+#define BSM_HOP_ATTR __attribute__((amdgpu_waves_per_eu(BSM_HOP_WAVES)))
+#elif defined(BSM_HOP_VGPR)
+#define BSM_HOP_ATTR __attribute__((amdgpu_num_vgpr(BSM_HOP_VGPR)))
+#else
+#define BSM_HOP_ATTR
+#endif
+
+// one output site per thread (plans 0, 1, 2)
 template <int D, bool REAL, int SP, int LP>
-__global__ __launch_bounds__(256) void k_hop(Geom g, HopArgs a, int nblk) {
+__global__ __launch_bounds__(256) BSM_HOP_ATTR void k_hop(Geom g, HopArgs a, int nblk) {
     using T = typename Compute<SP>::T;
-    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t lb = a.order == 2 ? blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
     const int pi = lb >= (uint32_t)nblk ? 1 : 0;
-    const uint32_t h = (lb - pi * nblk) * 256 + threadIdx.x;
+    const uint32_t S3 = (uint32_t)g.Vh / (uint32_t)g.L[0];
+    const uint32_t h = plan_site(a, lb - pi * nblk, S3, S3 / 256);
     const int p = a.p0 + pi;
     const bool active = h < (uint32_t)g.Vh;
     const size_t lblk = link_block_bytes(LP, REAL, D, g.Vh_pad);
@@ -164,29 +270,99 @@ __global__ __launch_bounds__(256) void k_hop(Geom g, HopArgs a, int nblk) {
         hop_dir<1, D, REAL, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
         hop_dir<2, D, REAL, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
         hop_dir<3, D, REAL, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
-        const T bb = (T)a.b;
-#pragma unroll
-        for (int k = 0; k < 4 * D; k++) acc[k] = bb * acc[k];
-        if (a.a != 0.0) {
-            cx<T> xs[4 * D];
-            load_spinor<SP, D, T>(a.x[p], g.Vh_pad, h, xs);
-            const T aa = (T)a.a;
-#pragma unroll
-            for (int k = 0; k < 4 * D; k++) {
-                acc[k].re = fma(aa, xs[k].re, acc[k].re);
-                acc[k].im = fma(aa, xs[k].im, acc[k].im);
-            }
-        }
-        store_spinor<SP, D, T>(a.out[p], g.Vh_pad, h, acc);
-        if (a.norm_partials) {
-#pragma unroll
-            for (int k = 0; k < 4 * D; k++)
-                nrm += (double)acc[k].re * acc[k].re + (double)acc[k].im * acc[k].im;
-        }
+        nrm = hop_epilogue<D, SP, T>(g, a, p, h, acc);
     }
     if (a.norm_partials) {
         double s = block_sum_256(nrm);
         if (threadIdx.x == 0) a.norm_partials[lb] = s;
+    }
+}
+
+// Column sweep (plan 3).  A thread owns one spatial half site s and walks
+// tchunk consecutive time slices t (output site h = t S3 + s).  Its two time
+// neighbours are the input sites (t +- 1) S3 + s of the same column, so every
+// input spinor of the column is loaded once and serves the forward hop of
+// output t-1 and the backward hop of output t+1: the backward projection is
+// kept in a two-deep register ring.  Workgroups cover 256 consecutive s with
+// the spatial tile fastest, so the spatial neighbours of a time slice are
+// read by workgroups running at the same time, from contiguous memory.
+template <int D, bool REAL, int SP, int LP>
+__global__ __launch_bounds__(256) void k_hop_col(Geom g, HopArgs a, int nblk) {
+    using T = typename Compute<SP>::T;
+    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int pi = lb >= (uint32_t)nblk ? 1 : 0;
+    const uint32_t bl = lb - pi * nblk;
+    const int p = a.p0 + pi;
+    const uint32_t S3 = (uint32_t)g.Vh / (uint32_t)g.L[0];
+    const uint32_t ntile = S3 / 256;
+    const uint32_t chunk = bl / ntile;
+    const uint32_t s = (bl - chunk * ntile) * 256 + threadIdx.x;
+    const int T0 = (int)chunk * a.tchunk;
+    const int LT = g.L[0];
+    const size_t lblk = link_block_bytes(LP, REAL, D, g.Vh_pad);
+    const char *in = (const char *)a.in[p];
+    const char *U = (const char *)a.U;
+    const T eta = a.dagger ? (T)-1 : (T)1;
+    const bool apt = g.apbc & 1;
+    // spatial coordinates of the column
+    Coords c0 = decode(g, s, 0);
+    // ring: backward projections (sg = -eta) of in(t-1) and in(t)
+    cx<T> r0a[D], r0b[D], r1a[D], r1b[D];
+    {
+        cx<T> sp[4 * D];
+        const int tm = T0 == 0 ? LT - 1 : T0 - 1;
+        load_spinor<SP, D, T>(in, g.Vh_pad, (uint32_t)tm * S3 + s, sp);
+        project<0, D, T>(sp, -eta, r0a, r0b);
+        load_spinor<SP, D, T>(in, g.Vh_pad, (uint32_t)T0 * S3 + s, sp);
+        project<0, D, T>(sp, -eta, r1a, r1b);
+    }
+    double nrm = 0.0;
+    for (int k = 0; k < a.tchunk; k++) {
+        const int t = T0 + k;
+        const uint32_t h = (uint32_t)t * S3 + s;
+        Coords c = c0;
+        c.t = t;
+        c.row = ((uint32_t)t * g.L[3] + c0.z) * g.L[2] + c0.y;
+        c.x = 2 * c0.xh + ((t + c0.z + c0.y + p) & 1);
+        cx<T> acc[4 * D];
+#pragma unroll
+        for (int q = 0; q < 4 * D; q++) acc[q] = mk<T>(0, 0);
+        // time: forward neighbour in(t+1), backward from the ring
+        const int tp = t + 1 == LT ? 0 : t + 1;
+        const uint32_t hp = (uint32_t)tp * S3 + s;
+        const uint32_t hm = (uint32_t)(t == 0 ? LT - 1 : t - 1) * S3 + s;
+        cx<T> nb0[D], nb1[D];
+        {
+            cx<T> sp[4 * D], f0[D], f1[D];
+            load_spinor<SP, D, T>(in, g.Vh_pad, hp, sp);
+            const char *blk = link_block<0, false>(U, lblk, p);
+            LinkRegs<D, REAL, LP, true, T> L;
+            L.load(blk, g.Vh_pad, h);
+            project<0, D, T>(sp, eta, f0, f1);
+            project<0, D, T>(sp, -eta, nb0, nb1);
+            const T wf = (apt && t + 1 == LT) ? (T)-1 : (T)1;
+            hop_half<0, D, REAL, LP, false, T>(g, L, blk, h, eta, wf, f0, f1, acc);
+        }
+        {
+            const T wb = (apt && t == 0) ? (T)-1 : (T)1;
+            const char *blk = link_block<0, true>(U, lblk, p);
+            LinkRegs<D, REAL, LP, true, T> L;
+            L.load(blk, g.Vh_pad, hm);
+            hop_half<0, D, REAL, LP, true, T>(g, L, blk, hm, -eta, wb, r0a, r0b, acc);
+        }
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+            r0a[i] = r1a[i]; r0b[i] = r1b[i];
+            r1a[i] = nb0[i]; r1b[i] = nb1[i];
+        }
+        hop_dir<1, D, REAL, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
+        hop_dir<2, D, REAL, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
+        hop_dir<3, D, REAL, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
+        nrm += hop_epilogue<D, SP, T>(g, a, p, h, acc);
+    }
+    if (a.norm_partials) {
+        double sum = block_sum_256(nrm);
+        if (threadIdx.x == 0) a.norm_partials[lb] = sum;
     }
 }
 
@@ -195,13 +371,22 @@ __global__ __launch_bounds__(256) void k_hop(Geom g, HopArgs a, int nblk) {
 // parallel).
 template <int SP, int LP, int D>
 bsm_status hop_run(const Geom &g, bool real, const HopArgs &a, hipStream_t st) {
-    int nblk = (g.Vh + 255) / 256;
-    dim3 grid(nblk * a.np);
-    if (real) {
-        if constexpr (D == 3 || D == 8 || D == 15)
-            k_hop<D, true, SP, LP><<<grid, 256, 0, st>>>(g, a, nblk);
-        else
-            return fail(BSM_ERR_UNSUPPORTED, "real links only for adjoint d_R 3, 8, 15");
+    const int grid = hop_grid(g, a);
+    const int nblk = grid / a.np;
+    if (real && !(D == 3 || D == 8 || D == 15))
+        return fail(BSM_ERR_UNSUPPORTED, "real links only for adjoint d_R 3, 8, 15");
+    if (a.order == 3) {
+        if constexpr (D <= kColMaxD) {
+            if (real) {
+                if constexpr (D == 3 || D == 8 || D == 15) k_hop_col<D, true, SP, LP><<<grid, 256, 0, st>>>(g, a, nblk);
+            } else {
+                k_hop_col<D, false, SP, LP><<<grid, 256, 0, st>>>(g, a, nblk);
+            }
+        } else {
+            return fail(BSM_ERR_UNSUPPORTED, "column plan only for d_R <= 6");
+        }
+    } else if (real) {
+        if constexpr (D == 3 || D == 8 || D == 15) k_hop<D, true, SP, LP><<<grid, 256, 0, st>>>(g, a, nblk);
     } else {
         k_hop<D, false, SP, LP><<<grid, 256, 0, st>>>(g, a, nblk);
     }

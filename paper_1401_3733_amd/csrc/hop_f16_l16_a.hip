@@ -2,11 +2,25 @@
 #include "hop.h"
 
 namespace bsm {
+#if (BSM_DMASK >> 2) & 1
 BSM_HOP_INSTANTIATE(BSM_F16S, BSM_F16S, 2)
+#endif
+#if (BSM_DMASK >> 3) & 1
 BSM_HOP_INSTANTIATE(BSM_F16S, BSM_F16S, 3)
+#endif
+#if (BSM_DMASK >> 4) & 1
 BSM_HOP_INSTANTIATE(BSM_F16S, BSM_F16S, 4)
+#endif
+#if (BSM_DMASK >> 5) & 1
 BSM_HOP_INSTANTIATE(BSM_F16S, BSM_F16S, 5)
+#endif
+#if (BSM_DMASK >> 6) & 1
 BSM_HOP_INSTANTIATE(BSM_F16S, BSM_F16S, 6)
+#endif
+#if (BSM_DMASK >> 7) & 1
 BSM_HOP_INSTANTIATE(BSM_F16S, BSM_F16S, 7)
+#endif
+#if (BSM_DMASK >> 8) & 1
 BSM_HOP_INSTANTIATE(BSM_F16S, BSM_F16S, 8)
+#endif
 }  // namespace bsm

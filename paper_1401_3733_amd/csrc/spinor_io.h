@@ -79,10 +79,30 @@ __device__ inline void store_spinor(void *blk, int64_t stride, uint32_t h, const
     }
 }
 
-// Link element (i, j) of a link block (complex or real) as cx<T>.
-template <int LP, bool REAL, class T>
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// Link element (i, j) of a link block (complex or real) as cx<T>; NT: a
+// non-temporal (streaming) load.
+template <int LP, bool REAL, class T, bool NT = false>
 __device__ inline cx<T> load_link(const void *blk, int64_t stride, int e, uint32_t h) {
-    if constexpr (REAL) {
+    if constexpr (NT && !REAL && LP == BSM_F32) {
+        f32x2 v = __builtin_nontemporal_load((const f32x2 *)blk + e * stride + h);
+        return mk<T>((T)v.x, (T)v.y);
+    } else if constexpr (NT && !REAL && LP == BSM_F64) {
+        f64x2 v = __builtin_nontemporal_load((const f64x2 *)blk + e * stride + h);
+        return mk<T>((T)v.x, (T)v.y);
+    } else if constexpr (NT && REAL && LP == BSM_F32) {
+        float v = __builtin_nontemporal_load((const float *)blk + e * stride + h);
+        return mk<T>((T)v, (T)0);
+    } else if constexpr (NT && REAL && LP == BSM_F64) {
+        double v = __builtin_nontemporal_load((const double *)blk + e * stride + h);
+        return mk<T>((T)v, (T)0);
+    } else if constexpr (NT && !REAL && LP == BSM_F16S) {
+        uint32_t v = __builtin_nontemporal_load((const uint32_t *)blk + e * stride + h);
+        float2 f = __half22float2(*reinterpret_cast<__half2 *>(&v));
+        return mk<T>((T)f.x, (T)f.y);
+    } else if constexpr (REAL) {
         if constexpr (LP == BSM_F64) return mk<T>((T)((const double *)blk)[e * stride + h], (T)0);
         else if constexpr (LP == BSM_F32) return mk<T>((T)((const float *)blk)[e * stride + h], (T)0);
         else return mk<T>((T)__half2float(((const __half *)blk)[e * stride + h]), (T)0);

@@ -20,11 +20,24 @@ def host(t):
     return t.cpu().numpy()
 
 
+def dev_build_d():
+    """d_R values compiled in a restricted development build, or None."""
+    import os
+    stamp = os.path.join(os.path.dirname(bsm.LIB_PATH), "libbsm.dev")
+    if not os.path.exists(stamp):
+        return None
+    return {int(x) for x in open(stamp).read().split(",")}
+
+
 class Setup:
     """Context + represented links on the GPU for one lattice and (N, rep)."""
 
     def __init__(self, lat, N, rep, Uf, prec="f64", link_prec=None):
         import torch
+        ds = dev_build_d()
+        if ds is not None and bsm.bsm_rep_dim(N, rep) not in ds:
+            import pytest
+            pytest.skip(f"development build without d_R = {bsm.bsm_rep_dim(N, rep)}")
         self.lat = lat
         self.ctx = bsm.Context(lat.dims, lat.bc)
         self.desc = bsm.desc(N, rep, prec, link_prec)

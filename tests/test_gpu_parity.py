@@ -162,3 +162,41 @@ def test_dslash_deterministic():
     import torch
     torch.cuda.synchronize()
     assert torch.equal(o1, o2)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 1e-6), ("f16s", 2e-3)])
+@pytest.mark.parametrize("order,tchunk", [(0, 1), (1, 1), (1, 2), (1, 4), (2, 1), (3, 1), (3, 2), (3, 4)])
+@pytest.mark.parametrize("bc", [(-1, 1, 1, 1), (-1, -1, 1, 1)])
+def test_every_traversal_plan_gives_the_same_operator(prec, tol, order, tchunk, bc):
+    note(f"plan order={order} tchunk={tchunk} prec={prec} bc={bc}")
+    lat = gen.Lattice(4, 8, 8, 8, bc=bc)      # LX*LY*LZ/2 = 256: one tile per time slice
+    Uf = _links(lat, 3, 600)
+    S = Setup(lat, 3, "fund", Uf, prec=prec)
+    S.ctx.bsm_set_hop_plan(S.desc, order, tchunk)
+    assert S.ctx.bsm_get_hop_plan(S.desc)["order"] == order
+    psi = gen.gaussian_spinor(lat, 3, 601)
+    for dag in (0, 1):
+        out = S.ctx.new_spinor(S.desc)
+        S.ctx.bsm_dslash_apply(S.desc, S.U, KAPPA, dag, S.pack(psi), out)
+        assert rel(S.unpack(out), oracle.dslash(lat, Uf, KAPPA, psi, dagger=bool(dag))) <= tol
+    # even-odd block with the norm fused (the CG path) under this plan
+    par = oracle.parity_mask(lat)
+    inp = S.pack(psi)
+    out = S.ctx.new_spinor(S.desc)
+    S.ctx.bsm_dslash_eo(S.desc, S.U, 1, 0, 0.5, S.block(inp, 1), 2.0, S.block(inp, 0), S.block(out, 1))
+    ref = 0.5 * psi + 2.0 * oracle.hop(lat, Uf, psi, parity=1)
+    assert rel(S.unpack(out)[par == 1], ref[par == 1]) <= tol
+
+
+def test_autotune_and_plan_validation():
+    lat = gen.Lattice(4, 8, 8, 8)
+    S = Setup(lat, 3, "fund", _links(lat, 3, 602), prec="f32")
+    plan = S.ctx.bsm_autotune(S.desc, S.U)
+    assert plan["us"] > 0
+    from paper_1401_3733_amd import bsm as _b
+    with pytest.raises(_b.BsmError):
+        S.ctx.bsm_set_hop_plan(S.desc, 1, 3)         # T = 4 is not a multiple of 3
+    lat2 = gen.Lattice(4, 6, 4, 6)                     # 72 sites per slice: does not tile
+    S2 = Setup(lat2, 3, "fund", _links(lat2, 3, 603))
+    with pytest.raises(_b.BsmError):
+        S2.ctx.bsm_set_hop_plan(S2.desc, 3, 1)
