@@ -224,6 +224,44 @@ bsm_status bsm_cg_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_r
                         const void *U_rep64, const bsm_solver_params *params, const void *b,
                         void *x, bsm_solver_stats *stats, void *stream);
 
+/* ------------------------------------------------------- many right-hand sides
+ * Block fields hold up to 16 right-hand sides together (FP32, layout private)
+ * so that one link load serves all of them; available for real (adjoint)
+ * links, where the hop of 16 RHS at a site is a dense product of the d x d
+ * link with a d x 64 block of projected half spinors, done on FP32 matrix
+ * cores.  desc->rep must be BSM_REP_ADJ for the block calls below. */
+/* bytes of one full block field (both parities, 16 RHS slots) */
+size_t bsm_block_bytes(bsm_ctx ctx, const bsm_field_desc *desc);
+/* bytes of the links in block layout */
+size_t bsm_block_gauge_bytes(bsm_ctx ctx, const bsm_field_desc *desc);
+/* canonical complex128 [n_rhs][V][4][d] (n_rhs <= 16) <-> block field;
+ * pack zeroes the unused RHS slots */
+bsm_status bsm_pack_block(bsm_ctx ctx, const bsm_field_desc *desc, int32_t n_rhs, const void *canon,
+                          void *block, void *stream);
+bsm_status bsm_unpack_block(bsm_ctx ctx, const bsm_field_desc *desc, int32_t n_rhs, const void *block,
+                            void *canon, void *stream);
+/* represented links (internal layout, link_prec F64 or F32) -> block layout */
+bsm_status bsm_gauge_to_block(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, void *U_block,
+                              void *stream);
+/* Even-odd hop of every RHS slot: out_r = a_r x_r + b_r H_{p,1-p} in_r, with
+ * a, b host arrays of 16 (a nullable: x is not read), in / x / out one parity
+ * block of block fields (in must not overlap out). */
+bsm_status bsm_dslash_eo_block(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_block,
+                               int32_t out_parity, int32_t dagger, const double *a, const void *x,
+                               const double *b, const void *in, void *out, void *stream);
+/* Solve D(kappa_r) x_r = b_r for n_rhs right-hand sides with their own
+ * kappa_r (Section II.B's inversion, for a family of masses).  b and x are
+ * n_rhs consecutive full internal FP64 fields; U_rep64 are FP64 links.
+ * Adjoint links: 16 RHS at a time share every link load on matrix cores
+ * (FP32 recurrence captured as a HIP graph of check_every iterations, FP64
+ * reliable updates with threshold delta, each RHS retired once its FP64
+ * true residual <= tol).  Other representations: one mixed-precision solve
+ * per RHS at inner precision desc->prec.  stats: host array of n_rhs.
+ * Synchronous. */
+bsm_status bsm_batched_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep64,
+                             const bsm_solver_params *params, int32_t n_rhs, const double *kappas,
+                             const void *b, void *x, bsm_solver_stats *stats, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -77,6 +77,15 @@ _SIGS = {
     "bsm_vec_axpby": (C.c_int, [_vp, C.POINTER(FieldDesc), C.c_int32, C.c_double, _vp, C.c_double, _vp,
                                 C.c_int32, _vp, _vp]),
     "bsm_vec_dot": (C.c_int, [_vp, C.POINTER(FieldDesc), C.c_int32, _vp, _vp, C.POINTER(C.c_double), _vp]),
+    "bsm_block_bytes": (C.c_size_t, [_vp, C.POINTER(FieldDesc)]),
+    "bsm_block_gauge_bytes": (C.c_size_t, [_vp, C.POINTER(FieldDesc)]),
+    "bsm_pack_block": (C.c_int, [_vp, C.POINTER(FieldDesc), C.c_int32, _vp, _vp, _vp]),
+    "bsm_unpack_block": (C.c_int, [_vp, C.POINTER(FieldDesc), C.c_int32, _vp, _vp, _vp]),
+    "bsm_gauge_to_block": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, _vp, _vp]),
+    "bsm_dslash_eo_block": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, C.c_int32,
+                                      C.POINTER(C.c_double), _vp, C.POINTER(C.c_double), _vp, _vp, _vp]),
+    "bsm_batched_solve": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.POINTER(SolverParams), C.c_int32,
+                                    C.POINTER(C.c_double), _vp, _vp, C.POINTER(SolverStats), _vp]),
     "bsm_cg_solve": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, _vp, C.POINTER(SolverParams), _vp, _vp,
                                C.POINTER(SolverStats), _vp]),
 }
@@ -229,6 +238,50 @@ class Context:
                                  _stream(stream)), "bsm_vec_dot")
         return r.value
 
+    # block (multi-RHS) fields
+    def block_bytes(self, d):
+        n = lib().bsm_block_bytes(self.handle, C.byref(d))
+        if n == 0:
+            _check(ERR_UNSUPPORTED, "bsm_block_bytes")
+        return n
+
+    def new_block(self, d, device="cuda"):
+        import torch
+        return torch.zeros(self.block_bytes(d), dtype=torch.uint8, device=device)
+
+    def new_block_gauge(self, d, device="cuda"):
+        import torch
+        n = lib().bsm_block_gauge_bytes(self.handle, C.byref(d))
+        if n == 0:
+            _check(ERR_UNSUPPORTED, "bsm_block_gauge_bytes")
+        return torch.zeros(n, dtype=torch.uint8, device=device)
+
+    def bsm_pack_block(self, d, canon, block, n_rhs, stream=None):
+        _check(lib().bsm_pack_block(self.handle, C.byref(d), int(n_rhs), _ptr(canon), _ptr(block),
+                                    _stream(stream)), "bsm_pack_block")
+
+    def bsm_unpack_block(self, d, block, canon, n_rhs, stream=None):
+        _check(lib().bsm_unpack_block(self.handle, C.byref(d), int(n_rhs), _ptr(block), _ptr(canon),
+                                      _stream(stream)), "bsm_unpack_block")
+
+    def bsm_gauge_to_block(self, d, U_rep, U_block, stream=None):
+        _check(lib().bsm_gauge_to_block(self.handle, C.byref(d), _ptr(U_rep), _ptr(U_block), _stream(stream)),
+               "bsm_gauge_to_block")
+
+    def bsm_dslash_eo_block(self, d, U_block, out_parity, dagger, a, x, b, inp, out, stream=None):
+        _check(lib().bsm_dslash_eo_block(self.handle, C.byref(d), _ptr(U_block), int(out_parity), int(dagger),
+                                         _darr(a, 16), _ptr(x), _darr(b, 16), _ptr(inp), _ptr(out),
+                                         _stream(stream)), "bsm_dslash_eo_block")
+
+    def bsm_batched_solve(self, d, U_rep64, params: SolverParams, kappas, b, x, stream=None, check=True):
+        n = len(kappas)
+        st = (SolverStats * n)()
+        status = lib().bsm_batched_solve(self.handle, C.byref(d), _ptr(U_rep64), C.byref(params), n,
+                                         _darr(kappas), _ptr(b), _ptr(x), st, _stream(stream))
+        if check and status != OK:
+            _check(status, "bsm_batched_solve")
+        return status, [s.as_dict() for s in st]
+
     def bsm_cg_solve(self, d, U_rep, U_rep64, params: SolverParams, b, x, stream=None, check=True):
         st = SolverStats()
         status = lib().bsm_cg_solve(self.handle, C.byref(d), _ptr(U_rep), _ptr(U_rep64), C.byref(params),
@@ -236,6 +289,15 @@ class Context:
         if check and status not in (OK,):
             _check(status, "bsm_cg_solve")
         return status, st.as_dict()
+
+
+def _darr(vals, n=None):
+    if vals is None:
+        return None
+    vals = list(vals)
+    if n is not None:
+        vals = vals + [0.0] * (n - len(vals))
+    return (C.c_double * len(vals))(*[float(v) for v in vals])
 
 
 def solver_params(kappa, tol=1e-10, schur=True, variant=SOLVER_PLAIN, max_iter=100000, delta=0.1,

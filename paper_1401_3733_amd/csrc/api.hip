@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "blas.h"
+#include "block.h"
 #include "dispatch.h"
 
 namespace bsm {
@@ -33,8 +34,11 @@ bsm_status ctx_work(bsm_ctx ctx, size_t bytes, void **out) {
         hipError_t e = hipMalloc(&ctx->work, bytes);
         if (e != hipSuccess) return fail(BSM_ERR_NOMEM, "solver scratch allocation failed");
         // padding sites of internal fields are never written by the operator
-        // kernels and must read as zero in the vector reductions
+        // kernels and must read as zero in the vector reductions.  The fill
+        // runs on the null stream and may still be in flight when hipMemset
+        // returns; solvers use their own streams, so wait for it here.
         BSM_HIP(hipMemset(ctx->work, 0, bytes));
+        BSM_HIP(hipDeviceSynchronize());
         ctx->work_bytes = bytes;
     }
     *out = ctx->work;
@@ -321,6 +325,75 @@ bsm_status bsm_vec_dot(bsm_ctx ctx, const bsm_field_desc *desc, int32_t nparity,
     BSM_HIP(hipStreamSynchronize(st));
     *result = ctx->host_scal[S_TMP];
     return BSM_OK;
+}
+
+static bsm_status check_block(bsm_ctx ctx, const bsm_field_desc *desc) {
+    CHECK(check_ctx(ctx));
+    CHECK(check_desc(desc));
+    if (desc->rep != BSM_REP_ADJ) return fail(BSM_ERR_UNSUPPORTED, "block fields need real (adjoint) links");
+    return BSM_OK;
+}
+
+size_t bsm_block_bytes(bsm_ctx ctx, const bsm_field_desc *desc) {
+    if (check_block(ctx, desc) != BSM_OK) return 0;
+    return 2 * block_parity_bytes(ctx->g, desc->d_R);
+}
+
+size_t bsm_block_gauge_bytes(bsm_ctx ctx, const bsm_field_desc *desc) {
+    if (check_block(ctx, desc) != BSM_OK) return 0;
+    return block_link_bytes(ctx->g, desc->d_R);
+}
+
+bsm_status bsm_pack_block(bsm_ctx ctx, const bsm_field_desc *desc, int32_t n_rhs, const void *canon,
+                          void *block, void *stream) {
+    CHECK(check_block(ctx, desc));
+    if (!canon || !block) return fail(BSM_ERR_ARG, "null field pointer");
+    if (n_rhs < 1 || n_rhs > kNR) return fail(BSM_ERR_ARG, "n_rhs must be in [1, 16]");
+    return launch_pack_block(ctx->g, desc->d_R, n_rhs, canon, block, false, (hipStream_t)stream);
+}
+
+bsm_status bsm_unpack_block(bsm_ctx ctx, const bsm_field_desc *desc, int32_t n_rhs, const void *block,
+                            void *canon, void *stream) {
+    CHECK(check_block(ctx, desc));
+    if (!canon || !block) return fail(BSM_ERR_ARG, "null field pointer");
+    if (n_rhs < 1 || n_rhs > kNR) return fail(BSM_ERR_ARG, "n_rhs must be in [1, 16]");
+    return launch_pack_block(ctx->g, desc->d_R, n_rhs, canon, const_cast<void *>(block), true,
+                             (hipStream_t)stream);
+}
+
+bsm_status bsm_gauge_to_block(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, void *U_block,
+                              void *stream) {
+    CHECK(check_block(ctx, desc));
+    if (!U_rep || !U_block) return fail(BSM_ERR_ARG, "null field pointer");
+    return launch_gauge_to_block(ctx->g, desc->d_R, desc->link_prec, U_rep, (float *)U_block,
+                                 (hipStream_t)stream);
+}
+
+bsm_status bsm_dslash_eo_block(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_block,
+                               int32_t out_parity, int32_t dagger, const double *a, const void *x,
+                               const double *b, const void *in, void *out, void *stream) {
+    CHECK(check_block(ctx, desc));
+    if (out_parity != 0 && out_parity != 1) return fail(BSM_ERR_ARG, "out_parity must be 0 or 1");
+    if (!U_block || !in || !out || !b) return fail(BSM_ERR_ARG, "null pointer");
+    if (a && !x) return fail(BSM_ERR_ARG, "x is null but a is given");
+    const size_t bb = block_parity_bytes(ctx->g, desc->d_R);
+    const char *ip = (const char *)in;
+    char *op = (char *)out;
+    if (op < ip + bb && ip < op + bb) return fail(BSM_ERR_ARG, "in and out must not overlap");
+    BlockHopArgs h{};
+    h.U = (const float *)U_block;
+    h.in[out_parity] = (const float2 *)in;
+    h.x[out_parity] = (const float2 *)x;
+    h.out[out_parity] = (float2 *)out;
+    h.use_x = a ? 1 : 0;
+    for (int r = 0; r < kNR; r++) {
+        h.a[r] = a ? (float)a[r] : 0.f;
+        h.b[r] = (float)b[r];
+    }
+    h.dagger = dagger ? 1 : 0;
+    h.p0 = out_parity;
+    h.np = 1;
+    return launch_hop_block(ctx->g, desc->d_R, h, (hipStream_t)stream);
 }
 
 bsm_status bsm_set_hop_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t order, int32_t tchunk) {

@@ -1,0 +1,65 @@
+// Multi-RHS ("block") fields for the batched solver: up to kNR right-hand
+// sides stored together so each link load serves all of them.
+//
+// Block spinor, one parity block: [h][c < d][spin 4][rhs kNR] complex float,
+// site stride d * 4 * kNR complex.  A full block field is the even block
+// followed by the odd one.  RHS slots beyond n_rhs hold zeros.
+// Block links (real adjoint links only): [q][mu][h][i * d + j] float.
+#pragma once
+#include "bsm_internal.h"
+
+namespace bsm {
+
+constexpr int kNR = 16;   // RHS per block = the N width of one MFMA tile
+
+inline size_t block_site_bytes(int d) { return (size_t)d * 4 * kNR * 8; }
+inline size_t block_parity_bytes(const Geom &g, int d) { return block_site_bytes(d) * g.Vh_pad; }
+inline size_t block_link_bytes(const Geom &g, int d) { return (size_t)8 * g.Vh_pad * d * d * 4; }
+
+struct BlockHopArgs {
+    const float *U;          // block links
+    const float2 *in[2];     // in[p]: parity block read for output parity p
+    const float2 *x[2];
+    float2 *out[2];
+    float a[kNR], b[kNR];    // out_r = a_r x_r + b_r H in_r
+    int use_x;
+    int dagger;
+    int p0, np;
+    double *norm_partials;   // [workgroup][kNR]
+};
+
+bsm_status launch_hop_block(const Geom &g, int d, const BlockHopArgs &a, hipStream_t st);
+int hop_block_grid(const Geom &g, const BlockHopArgs &a);
+
+// layout conversions
+bsm_status launch_gauge_to_block(const Geom &g, int d, int link_prec, const void *U_rep, float *U_block,
+                                 hipStream_t st);
+// canonical complex128 [n_rhs][V][4][d] <-> block (both parities)
+bsm_status launch_pack_block(const Geom &g, int d, int n_rhs, const void *canon, void *block, bool unpack,
+                             hipStream_t st);
+// n_rhs standard F64 fields (per-RHS field stride std_stride, parity block at
+// offset std_off) <-> one parity block of a block field, for the RHS whose
+// bit is set in sel:
+//   mode 0: block = std (RHS slots >= n_rhs are zeroed) ;  mode 1: std += block
+bsm_status launch_std_block(const Geom &g, int d, int n_rhs, unsigned sel, char *std64, size_t std_stride,
+                            size_t std_off, float2 *block, int mode, hipStream_t st);
+
+// per-RHS vector kernels on nblk parity blocks of block fields (F32)
+// partials layout [workgroup][kNR]; returns the workgroup count
+int block_blas_grid(const Geom &g, int d, int nblk);
+bsm_status block_update(const Geom &g, int d, int nblk, float2 *x, const float2 *p, float2 *r,
+                        const float2 *q, const double *alpha, double *partials, hipStream_t st);
+bsm_status block_xpay(const Geom &g, int d, int nblk, float2 *p, const float2 *r, const double *beta,
+                      hipStream_t st);
+bsm_status block_norm(const Geom &g, int d, int nblk, const float2 *v, double *partials, hipStream_t st);
+// per-RHS scalars: op 0: pAp -> alpha ; op 1: rr_new -> beta, rr, hist ; op 2: rr, hist
+// alpha/beta are zero for RHS whose mask entry is 0
+bsm_status block_scalars(const double *partials, int nparts, double *scal, const int *mask, int op,
+                         int hist_slot, hipStream_t st);
+
+// device scalar layout for the batched solver (kNR doubles each)
+enum { B_RR = 0, B_PAP = 1, B_ALPHA = 2, B_BETA = 3, B_HIST = 4 };
+constexpr int kBlockHist = 64;   // history slots (iterations per graph replay)
+inline size_t block_scal_doubles() { return (size_t)(B_HIST + kBlockHist) * kNR; }
+
+}  // namespace bsm

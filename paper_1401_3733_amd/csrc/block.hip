@@ -1,0 +1,397 @@
+// Multi-RHS Wilson hop on FP32 matrix cores, and the per-RHS vector kernels of
+// the batched solver.
+//
+// For real (adjoint) links the hop of 16 right-hand sides at one site and
+// direction is one dense product: the d x d link times the d x 64 matrix of
+// projected half spinors (2 spin components x re/im x 16 RHS).  One wavefront
+// owns one site; per K-step of 4 colours it issues four
+// v_mfma_f32_16x16x4f32 (one per spin component and re/im part), with
+//   A[i][k]  = U_ik (forward) or U_ki (backward, U^dag = U^T),  lane l: i = l%16, k = l/16
+//   B[k][j]  = h[colour k][rhs j],                               lane l: k = l/16, j = l%16
+//   D[i][j]  -> lane l holds rows 4(l/16)+v, v<4, column j = l%16.
+// So lane l owns RHS l%16 and colours l/16 + 4 kb for the operands and rows
+// 4(l/16)+v of the result: the per-RHS epilogue coefficients, the spin
+// reconstruction and the per-RHS norms never leave the lane.
+#include "block.h"
+#include "dispatch.h"
+#include "spinor_io.h"
+
+namespace bsm {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <int MU>
+__device__ inline void project_c(const float2 (&s)[4], float sg, float2 &h0, float2 &h1) {
+    const float2 s0 = s[0], s1 = s[1], s2 = s[2], s3 = s[3];
+    if constexpr (MU == 0) {
+        h0 = make_float2(fmaf(-sg, s2.x, s0.x), fmaf(-sg, s2.y, s0.y));
+        h1 = make_float2(fmaf(-sg, s3.x, s1.x), fmaf(-sg, s3.y, s1.y));
+    } else if constexpr (MU == 1) {
+        h0 = make_float2(fmaf(-sg, s3.y, s0.x), fmaf(sg, s3.x, s0.y));
+        h1 = make_float2(fmaf(-sg, s2.y, s1.x), fmaf(sg, s2.x, s1.y));
+    } else if constexpr (MU == 2) {
+        h0 = make_float2(fmaf(sg, s3.x, s0.x), fmaf(sg, s3.y, s0.y));
+        h1 = make_float2(fmaf(-sg, s2.x, s1.x), fmaf(-sg, s2.y, s1.y));
+    } else {
+        h0 = make_float2(fmaf(-sg, s2.y, s0.x), fmaf(sg, s2.x, s0.y));
+        h1 = make_float2(fmaf(sg, s3.y, s1.x), fmaf(-sg, s3.x, s1.y));
+    }
+}
+
+// acc[spin][re/im] (rows 4q+v of colour) += hop contribution from G = U h
+template <int MU>
+__device__ inline void reconstruct_c(f4 (&acc)[4][2], float sg, float w, f4 g0r, f4 g0i, f4 g1r, f4 g1i) {
+    const float v = -sg * w;
+    acc[0][0] += w * g0r; acc[0][1] += w * g0i;
+    acc[1][0] += w * g1r; acc[1][1] += w * g1i;
+    if constexpr (MU == 0) {          // A^dag g = (g0, g1)
+        acc[2][0] += v * g0r; acc[2][1] += v * g0i;
+        acc[3][0] += v * g1r; acc[3][1] += v * g1i;
+    } else if constexpr (MU == 1) {   // (i g1, i g0)
+        acc[2][0] -= v * g1i; acc[2][1] += v * g1r;
+        acc[3][0] -= v * g0i; acc[3][1] += v * g0r;
+    } else if constexpr (MU == 2) {   // (g1, -g0)
+        acc[2][0] += v * g1r; acc[2][1] += v * g1i;
+        acc[3][0] -= v * g0r; acc[3][1] -= v * g0i;
+    } else {                          // (i g0, -i g1)
+        acc[2][0] -= v * g0i; acc[2][1] += v * g0r;
+        acc[3][0] += v * g1i; acc[3][1] -= v * g1r;
+    }
+}
+
+template <int MU, int D>
+__device__ inline void hop_dir_block(const Geom &g, const BlockHopArgs &a, const Coords &c, int p, uint32_t h,
+                                     int r, int q, float eta, f4 (&acc)[4][2]) {
+    constexpr int KB = (D + 3) / 4;
+    constexpr size_t SITE = (size_t)D * 4 * kNR;
+#pragma unroll
+    for (int dir = 0; dir < 2; dir++) {
+        const bool back = dir == 1;
+        float w;
+        const uint32_t hn = neighbour<MU>(g, c, back, w);
+        const float2 *sp = a.in[p] + (size_t)hn * SITE;
+        float2 s[KB][4];
+#pragma unroll
+        for (int kb = 0; kb < KB; kb++) {
+            const int cc = q + 4 * kb;
+#pragma unroll
+            for (int si = 0; si < 4; si++)
+                s[kb][si] = cc < D ? sp[(cc * 4 + si) * kNR + r] : make_float2(0.f, 0.f);
+        }
+        const float *L = a.U + ((size_t)((back ? 1 - p : p) * 4 + MU) * g.Vh_pad + (back ? hn : h)) * (D * D);
+        float A[KB];
+#pragma unroll
+        for (int kb = 0; kb < KB; kb++) {
+            const int k = q + 4 * kb;
+            A[kb] = (r < D && k < D) ? __builtin_nontemporal_load(L + (back ? k * D + r : r * D + k)) : 0.f;
+        }
+        const float sg = back ? -eta : eta;
+        f4 g0r = {0.f, 0.f, 0.f, 0.f}, g0i = g0r, g1r = g0r, g1i = g0r;
+#pragma unroll
+        for (int kb = 0; kb < KB; kb++) {
+            float2 h0, h1;
+            project_c<MU>(s[kb], sg, h0, h1);
+            g0r = __builtin_amdgcn_mfma_f32_16x16x4f32(A[kb], h0.x, g0r, 0, 0, 0);
+            g0i = __builtin_amdgcn_mfma_f32_16x16x4f32(A[kb], h0.y, g0i, 0, 0, 0);
+            g1r = __builtin_amdgcn_mfma_f32_16x16x4f32(A[kb], h1.x, g1r, 0, 0, 0);
+            g1i = __builtin_amdgcn_mfma_f32_16x16x4f32(A[kb], h1.y, g1i, 0, 0, 0);
+        }
+        reconstruct_c<MU>(acc, sg, w, g0r, g0i, g1r, g1i);
+    }
+}
+
+#ifndef BSM_BLOCK_WAVES
+#define BSM_BLOCK_WAVES 2
+#endif
+
+// 4 sites per 256-thread workgroup, one per wavefront.  The register budget
+// is capped so that several wavefronts per SIMD hide the load latency.
+template <int D>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BSM_BLOCK_WAVES)))
+void k_hop_block(Geom g, BlockHopArgs a, int nblk) {
+    constexpr size_t SITE = (size_t)D * 4 * kNR;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int pi = lb >= (uint32_t)nblk ? 1 : 0;
+    const uint32_t h = (lb - pi * nblk) * 4 + wave;
+    const int p = a.p0 + pi;
+    double nrm = 0.0;
+    if (h < (uint32_t)g.Vh) {
+        f4 acc[4][2];
+#pragma unroll
+        for (int s = 0; s < 4; s++) acc[s][0] = acc[s][1] = f4{0.f, 0.f, 0.f, 0.f};
+        const Coords c = decode(g, h, p);
+        const float eta = a.dagger ? -1.f : 1.f;
+        hop_dir_block<0, D>(g, a, c, p, h, r, q, eta, acc);
+        hop_dir_block<1, D>(g, a, c, p, h, r, q, eta, acc);
+        hop_dir_block<2, D>(g, a, c, p, h, r, q, eta, acc);
+        hop_dir_block<3, D>(g, a, c, p, h, r, q, eta, acc);
+        const float ar = a.a[r], br = a.b[r];
+        float2 *o = a.out[p] + (size_t)h * SITE;
+        const float2 *x = a.use_x ? a.x[p] + (size_t)h * SITE : nullptr;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int i = 4 * q + v;
+            if (i < D) {
+#pragma unroll
+                for (int s = 0; s < 4; s++) {
+                    const size_t e = (size_t)(i * 4 + s) * kNR + r;
+                    float re = br * acc[s][0][v], im = br * acc[s][1][v];
+                    if (x) {
+                        const float2 xv = x[e];
+                        re = fmaf(ar, xv.x, re);
+                        im = fmaf(ar, xv.y, im);
+                    }
+                    o[e] = make_float2(re, im);
+                    nrm += (double)re * re + (double)im * im;
+                }
+            }
+        }
+    }
+    if (a.norm_partials) {
+        nrm += __shfl_xor(nrm, 16, 64);
+        nrm += __shfl_xor(nrm, 32, 64);
+        __shared__ double ws[4][kNR];
+        if (lane < kNR) ws[wave][lane] = nrm;
+        __syncthreads();
+        if (threadIdx.x < kNR)
+            a.norm_partials[(size_t)lb * kNR + threadIdx.x] =
+                (ws[0][threadIdx.x] + ws[1][threadIdx.x]) + (ws[2][threadIdx.x] + ws[3][threadIdx.x]);
+    }
+}
+
+int hop_block_grid(const Geom &g, const BlockHopArgs &a) { return (g.Vh + 3) / 4 * a.np; }
+
+template <int D>
+struct BlockHopByD {
+    static bsm_status run(const Geom &g, const BlockHopArgs &a, hipStream_t st) {
+        if constexpr (D <= 16) {
+            const int grid = hop_block_grid(g, a);
+            k_hop_block<D><<<grid, 256, 0, st>>>(g, a, grid / a.np);
+            BSM_HIP(hipGetLastError());
+            return BSM_OK;
+        }
+        return fail(BSM_ERR_UNSUPPORTED, "block hop d_R");
+    }
+};
+
+bsm_status launch_hop_block(const Geom &g, int d, const BlockHopArgs &a, hipStream_t st) {
+    return dispatch_d<BlockHopByD>(d, g, a, st);
+}
+
+// --------------------------------------------------------------- layouts
+template <int LP>
+__global__ __launch_bounds__(256) void k_gauge_to_block(Geom g, int d, const char *src, float *dst) {
+    const uint32_t h = blockIdx.x * 256 + threadIdx.x;
+    const int qm = blockIdx.y;   // parity * 4 + mu
+    if (h >= (uint32_t)g.Vh_pad) return;
+    const int dd = d * d;
+    const char *blk = src + (size_t)qm * link_block_bytes(LP, true, d, g.Vh_pad);
+    float *o = dst + ((size_t)qm * g.Vh_pad + h) * dd;
+    for (int e = 0; e < dd; e++) o[e] = (float)load_link<LP, true, float>(blk, g.Vh_pad, e, h).re;
+}
+
+bsm_status launch_gauge_to_block(const Geom &g, int d, int link_prec, const void *U_rep, float *U_block,
+                                 hipStream_t st) {
+    dim3 grid((g.Vh_pad + 255) / 256, 8);
+    switch (link_prec) {
+    case BSM_F64: k_gauge_to_block<BSM_F64><<<grid, 256, 0, st>>>(g, d, (const char *)U_rep, U_block); break;
+    case BSM_F32: k_gauge_to_block<BSM_F32><<<grid, 256, 0, st>>>(g, d, (const char *)U_rep, U_block); break;
+    default: return fail(BSM_ERR_UNSUPPORTED, "block links from F16 links");
+    }
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
+// one thread per (site, colour-spin component); loops over the 16 RHS slots
+__global__ __launch_bounds__(256) void k_pack_block(Geom g, int d, int n_rhs, const double2 *canon,
+                                                    float2 *block, int unpack) {
+    const uint32_t h = blockIdx.x * 256 + threadIdx.x;
+    const int p = blockIdx.y;
+    const int cs = blockIdx.z;              // c * 4 + s
+    if (h >= (uint32_t)g.Vh_pad) return;
+    const int c = cs >> 2, s = cs & 3;
+    float2 *o = block + (size_t)p * g.Vh_pad * d * 4 * kNR + ((size_t)h * d * 4 + cs) * kNR;
+    const bool real_site = h < (uint32_t)g.Vh;
+    int64_t lex = 0;
+    if (real_site) {
+        Coords co = decode(g, h, p);
+        lex = (int64_t)co.row * g.L[1] + co.x;
+    }
+    const int64_t V = 2 * (int64_t)g.Vh;
+    for (int r = 0; r < kNR; r++) {
+        const bool use = real_site && r < n_rhs;
+        double2 *cp = (double2 *)canon + ((r * V + lex) * 4 + s) * d + c;
+        if (!unpack) {
+            o[r] = use ? make_float2((float)cp->x, (float)cp->y) : make_float2(0.f, 0.f);
+        } else if (use) {
+            *cp = make_double2(o[r].x, o[r].y);
+        }
+    }
+}
+
+bsm_status launch_pack_block(const Geom &g, int d, int n_rhs, const void *canon, void *block, bool unpack,
+                             hipStream_t st) {
+    dim3 grid((g.Vh_pad + 255) / 256, 2, d * 4);
+    k_pack_block<<<grid, 256, 0, st>>>(g, d, n_rhs, (const double2 *)canon, (float2 *)block, unpack ? 1 : 0);
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
+// element e of one parity block: r = e % 16, (h, c, s) from e / 16
+__global__ __launch_bounds__(256) void k_std_block(Geom g, int d, int n_rhs, unsigned sel, char *std64,
+                                                   size_t std_stride, size_t std_off, float2 *block, int mode) {
+    const size_t n = (size_t)g.Vh_pad * d * 4 * kNR;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+        const int r = (int)(e % kNR);
+        const size_t hcs = e / kNR;
+        const int s = (int)(hcs % 4);
+        const size_t hc = hcs / 4;
+        const int c = (int)(hc % d);
+        const size_t h = hc / d;
+        if (r >= n_rhs) {
+            if (mode == 0) block[e] = make_float2(0.f, 0.f);
+            continue;
+        }
+        if (!((sel >> r) & 1u)) continue;
+        double2 *sv = (double2 *)(std64 + r * std_stride + std_off) + (size_t)(s * d + c) * g.Vh_pad + h;
+        if (mode == 0) {
+            const double2 v = *sv;
+            block[e] = make_float2((float)v.x, (float)v.y);
+        } else {
+            const float2 v = block[e];
+            sv->x += (double)v.x;
+            sv->y += (double)v.y;
+        }
+    }
+}
+
+bsm_status launch_std_block(const Geom &g, int d, int n_rhs, unsigned sel, char *std64, size_t std_stride,
+                            size_t std_off, float2 *block, int mode, hipStream_t st) {
+    const size_t n = (size_t)g.Vh_pad * d * 4 * kNR;
+    size_t nb = (n + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    k_std_block<<<(int)nb, 256, 0, st>>>(g, d, n_rhs, sel, std64, std_stride, std_off, block, mode);
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
+// ------------------------------------------------------------ vector ops
+constexpr int kBlockBlasMax = 16384;
+
+int block_blas_grid(const Geom &g, int d, int nblk) {
+    const size_t n = (size_t)nblk * g.Vh_pad * d * 4 * kNR;
+    size_t nb = (n + 255) / 256;
+    return (int)(nb < kBlockBlasMax ? nb : kBlockBlasMax);
+}
+
+// per-RHS sum over the workgroup: lanes with equal tid % 16 share an RHS
+__device__ inline void block_rhs_sum(double v, double *partials) {
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    __shared__ double ws[4][kNR];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane < kNR) ws[wave][lane] = v;
+    __syncthreads();
+    if (threadIdx.x < kNR)
+        partials[(size_t)blockIdx.x * kNR + threadIdx.x] =
+            (ws[0][threadIdx.x] + ws[1][threadIdx.x]) + (ws[2][threadIdx.x] + ws[3][threadIdx.x]);
+}
+
+__global__ __launch_bounds__(256) void k_block_update(size_t n, float2 *x, const float2 *p, float2 *r,
+                                                      const float2 *q, const double *alpha, double *partials) {
+    const double al = alpha[threadIdx.x % kNR];
+    const float a = (float)al;
+    double nrm = 0;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+        float2 xv = x[e], pv = p[e], rv = r[e], qv = q[e];
+        xv.x = fmaf(a, pv.x, xv.x); xv.y = fmaf(a, pv.y, xv.y);
+        rv.x = fmaf(-a, qv.x, rv.x); rv.y = fmaf(-a, qv.y, rv.y);
+        x[e] = xv;
+        r[e] = rv;
+        nrm += (double)rv.x * rv.x + (double)rv.y * rv.y;
+    }
+    block_rhs_sum(nrm, partials);
+}
+
+__global__ __launch_bounds__(256) void k_block_xpay(size_t n, float2 *p, const float2 *r, const double *beta) {
+    const float b = (float)beta[threadIdx.x % kNR];
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+        float2 pv = p[e], rv = r[e];
+        p[e] = make_float2(fmaf(b, pv.x, rv.x), fmaf(b, pv.y, rv.y));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_block_norm(size_t n, const float2 *v, double *partials) {
+    double nrm = 0;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+        const float2 t = v[e];
+        nrm += (double)t.x * t.x + (double)t.y * t.y;
+    }
+    block_rhs_sum(nrm, partials);
+}
+
+static size_t block_elems(const Geom &g, int d, int nblk) { return (size_t)nblk * g.Vh_pad * d * 4 * kNR; }
+
+bsm_status block_update(const Geom &g, int d, int nblk, float2 *x, const float2 *p, float2 *r,
+                        const float2 *q, const double *alpha, double *partials, hipStream_t st) {
+    k_block_update<<<block_blas_grid(g, d, nblk), 256, 0, st>>>(block_elems(g, d, nblk), x, p, r, q, alpha,
+                                                                 partials);
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
+bsm_status block_xpay(const Geom &g, int d, int nblk, float2 *p, const float2 *r, const double *beta,
+                      hipStream_t st) {
+    k_block_xpay<<<block_blas_grid(g, d, nblk), 256, 0, st>>>(block_elems(g, d, nblk), p, r, beta);
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
+bsm_status block_norm(const Geom &g, int d, int nblk, const float2 *v, double *partials, hipStream_t st) {
+    k_block_norm<<<block_blas_grid(g, d, nblk), 256, 0, st>>>(block_elems(g, d, nblk), v, partials);
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
+// one workgroup: thread t sums the partials of RHS t % 16 over workgroups
+// t / 16, t / 16 + 16, ... (fixed order), then the 16 groups are combined
+__global__ __launch_bounds__(256) void k_block_scalars(const double *partials, int nparts, double *scal,
+                                                       const int *mask, int op, int slot) {
+    const int r = threadIdx.x % kNR, grp = threadIdx.x / kNR;
+    double s = 0;
+    for (int i = grp; i < nparts; i += 16) s += partials[(size_t)i * kNR + r];
+    __shared__ double ws[16][kNR];
+    ws[grp][r] = s;
+    __syncthreads();
+    if (threadIdx.x >= kNR) return;
+    double tot = 0;
+    for (int k = 0; k < 16; k++) tot += ws[k][r];
+    const bool on = mask[r] != 0;
+    double *RR = scal + B_RR * kNR, *PAP = scal + B_PAP * kNR, *AL = scal + B_ALPHA * kNR,
+           *BE = scal + B_BETA * kNR, *H = scal + (B_HIST + slot) * kNR;
+    if (op == 0) {
+        PAP[r] = tot;
+        const double al = RR[r] / tot;
+        AL[r] = (on && tot > 0 && isfinite(al)) ? al : 0.0;
+    } else if (op == 1) {
+        const double rr = RR[r];
+        const double be = tot / rr;
+        BE[r] = (on && rr > 0 && isfinite(be)) ? be : 0.0;
+        if (on) RR[r] = tot;
+        H[r] = tot;
+    } else {
+        RR[r] = tot;
+        H[r] = tot;
+    }
+}
+
+bsm_status block_scalars(const double *partials, int nparts, double *scal, const int *mask, int op,
+                         int hist_slot, hipStream_t st) {
+    k_block_scalars<<<1, 256, 0, st>>>(partials, nparts, scal, mask, op, hist_slot);
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
+}  // namespace bsm

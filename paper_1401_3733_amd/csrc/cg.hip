@@ -100,6 +100,50 @@ static bsm_status op_apply(const Op &o, int dagger, const void *x, void *y, bool
         if (_s != BSM_OK) return _s;     \
     } while (0)
 
+// sum n partials on the device and bring the result to the host (synchronous)
+static double reduce_to_host(bsm_ctx ctx, const double *partials, int n, hipStream_t st) {
+    reduce_into(partials, n, ctx->scal + S_TMP, st);
+    (void)hipMemcpyAsync(ctx->host_scal + S_TMP, ctx->scal + S_TMP, sizeof(double), hipMemcpyDeviceToHost, st);
+    (void)hipStreamSynchronize(st);
+    return ctx->host_scal[S_TMP];
+}
+
+// FP64: out = M^dag (bh - M x), with t as scratch (vectors of o's shape)
+static bsm_status normal_residual(const Op &o, const char *bh, const char *x, char *t, char *out,
+                                  hipStream_t st) {
+    Vec T{t, BSM_F64}, BH{(void *)bh, BSM_F64};
+    TRY(op_apply(o, 0, x, t, false, nullptr, st));
+    TRY(blas_axpby(o.g, o.d, nblk_vec(o), T, -1.0, T, 1.0, BH, nullptr, st));
+    return op_apply(o, 1, t, out, false, nullptr, st);
+}
+
+// FP64 true relative residual ||b - D x|| / ||b|| of the full system for the
+// full fields b, x (Schur: the odd sites of x are first rebuilt from x_e);
+// tfull is a full FP64 scratch field
+static bsm_status true_residual_full(const Op &o, const char *b, char *x, char *tfull, double bnorm2,
+                                     double *res, hipStream_t st) {
+    const Geom &g = o.g;
+    const size_t bb64 = spinor_block_bytes(BSM_F64, o.d, g.Vh_pad);
+    if (o.schur) {
+        HopArgs a{};
+        a.U = o.U; a.dagger = 0; a.p0 = 1; a.np = 1;
+        a.in[1] = x; a.x[1] = b + bb64; a.out[1] = x + bb64;
+        a.a = 1.0; a.b = o.kappa;
+        TRY(launch_hop(g, o.d, o.real, BSM_F64, BSM_F64, a, st));
+    }
+    HopArgs a{};
+    a.U = o.U; a.dagger = 0; a.p0 = 0; a.np = 2;
+    a.in[0] = x + bb64; a.in[1] = x; a.x[0] = x; a.x[1] = x + bb64;
+    a.out[0] = tfull; a.out[1] = tfull + bb64;
+    a.a = 1.0; a.b = -o.kappa;
+    TRY(launch_hop(g, o.d, o.real, BSM_F64, BSM_F64, a, st));
+    Vec TF{tfull, BSM_F64}, B{(void *)b, BSM_F64};
+    TRY(blas_axpby(g, o.d, 2, TF, -1.0, TF, 1.0, B, o.ctx->partials, st));
+    const double rn = reduce_to_host(o.ctx, o.ctx->partials, blas_blocks(g, 2), st);
+    *res = bnorm2 > 0 ? std::sqrt(rn / bnorm2) : std::sqrt(rn);
+    return BSM_OK;
+}
+
 struct Solver {
     bsm_ctx ctx;
     hipStream_t st;
@@ -116,46 +160,15 @@ struct Solver {
     double bnorm2;          // |b|^2 (full)
     double rhs_norm2;       // |M^dag bhat|^2
 
-    double host_reduce(const double *partials, int n) {
-        reduce_into(partials, n, ctx->scal + S_TMP, st);
-        hipMemcpyAsync(ctx->host_scal + S_TMP, ctx->scal + S_TMP, sizeof(double), hipMemcpyDeviceToHost, st);
-        hipStreamSynchronize(st);
-        return ctx->host_scal[S_TMP];
-    }
-
-    // even block (Schur) or the full field of the caller's x / b
-    char *xv() { return x; }
+    double host_reduce(const double *partials, int n) { return reduce_to_host(ctx, partials, n, st); }
 
     // FP64: out = M^dag (bhat - M x64)   (uses t64 as scratch)
     bsm_status normal_residual64(const char *x64, char *out) {
-        Vec T{t64, BSM_F64}, BH{bh, BSM_F64};
-        TRY(op_apply(op64, 0, x64, t64, false, nullptr, st));
-        TRY(blas_axpby(g, d, nblk_vec(op64), T, -1.0, T, 1.0, BH, nullptr, st));
-        return op_apply(op64, 1, t64, out, false, nullptr, st);
+        return normal_residual(op64, bh, x64, t64, out, st);
     }
 
     // reconstruct odd sites (Schur) and return the FP64 true relative residual
-    bsm_status true_residual(double *res) {
-        if (schur) {
-            HopArgs a{};
-            a.U = op64.U; a.dagger = 0; a.p0 = 1; a.np = 1;
-            a.in[1] = x; a.x[1] = b + bb64; a.out[1] = x + bb64;
-            a.a = 1.0; a.b = kappa;
-            TRY(launch_hop(g, d, real, BSM_F64, BSM_F64, a, st));
-        }
-        // tfull = D x ; tfull = b - tfull ; |.|^2
-        HopArgs a{};
-        a.U = op64.U; a.dagger = 0; a.p0 = 0; a.np = 2;
-        a.in[0] = x + bb64; a.in[1] = x; a.x[0] = x; a.x[1] = x + bb64;
-        a.out[0] = tfull; a.out[1] = tfull + bb64;
-        a.a = 1.0; a.b = -kappa;
-        TRY(launch_hop(g, d, real, BSM_F64, BSM_F64, a, st));
-        Vec TF{tfull, BSM_F64}, B{(void *)b, BSM_F64};
-        TRY(blas_axpby(g, d, 2, TF, -1.0, TF, 1.0, B, ctx->partials, st));
-        double rn = host_reduce(ctx->partials, blas_blocks(g, 2));
-        *res = bnorm2 > 0 ? std::sqrt(rn / bnorm2) : std::sqrt(rn);
-        return BSM_OK;
-    }
+    bsm_status true_residual(double *res) { return true_residual_full(op64, b, x, tfull, bnorm2, res, st); }
 
     bsm_status setup(void *work_base) {
         char *w = (char *)work_base;
@@ -452,4 +465,367 @@ extern "C" bsm_status bsm_cg_solve(bsm_ctx ctx, const bsm_field_desc *desc, cons
     if (s == BSM_ERR_NOT_CONVERGED) fail(s, "max_iter reached before the true residual met tol");
     if (s == BSM_ERR_NONFINITE) fail(s, "non-finite value in a reduction");
     return s;
+}
+
+// ===================================================================== batched
+// Many right-hand sides D(kappa_r) x_r = b_r at once (even-odd Schur CG on
+// the normal equations, one kappa per RHS).  For real (adjoint) links the
+// recurrence runs on 16-RHS block fields in FP32 with the matrix-core hop,
+// so every link load serves all RHS; K iterations are captured once as a HIP
+// graph and replayed.  Every RHS keeps its own alpha, beta and |r|^2 on the
+// device; between replays the host folds the FP32 solutions into the FP64
+// ones, recomputes in FP64 the residual of every RHS whose |r| dropped by
+// delta since its last update (reliable update) or reached its trigger, and
+// retires an RHS once its FP64 full-lattice true residual is <= tol: its
+// alpha and beta are masked to zero from then on.
+#include "block.h"
+
+namespace bsm {
+
+struct BlockSolve {
+    bsm_ctx ctx;
+    Geom g;
+    int d, n;
+    hipStream_t st;
+    const bsm_solver_params *prm;
+    const double *kappas;
+    const char *b;
+    char *x;
+    size_t full64, bb64, bbB;
+    // FP64 per RHS
+    std::vector<Op> ops;
+    char *bh, *r64, *t64, *tfull, *tmp64;
+    std::vector<double> bnorm2, rhs_norm2;
+    // FP32 block fields
+    float *Ublk;
+    float2 *p, *t, *q, *xlo, *rlo, *tmpB;
+    double *partials, *scal;
+    int *mask;
+    hipGraphExec_t graph = nullptr;
+    int K;
+};
+
+static bsm_status block_op(BlockSolve &B, int dagger, const float2 *in, float2 *out, bool norm, int *nparts) {
+    BlockHopArgs a{};
+    a.U = B.Ublk;
+    a.dagger = dagger;
+    a.np = 1;
+    // tmp_o = H_oe in_e
+    a.p0 = 1;
+    a.in[1] = in;
+    a.out[1] = B.tmpB;
+    a.use_x = 0;
+    for (int r = 0; r < kNR; r++) { a.a[r] = 0.f; a.b[r] = 1.f; }
+    TRY(launch_hop_block(B.g, B.d, a, B.st));
+    // out_e = in_e - kappa_r^2 H_eo tmp_o
+    BlockHopArgs c = a;
+    c.p0 = 0;
+    c.in[0] = B.tmpB;
+    c.x[0] = in;
+    c.out[0] = out;
+    c.use_x = 1;
+    for (int r = 0; r < kNR; r++) {
+        const double k = r < B.n ? B.kappas[r] : 0.0;
+        c.a[r] = 1.f;
+        c.b[r] = (float)(-k * k);
+    }
+    c.norm_partials = norm ? B.partials : nullptr;
+    if (nparts) *nparts = hop_block_grid(B.g, c);
+    return launch_hop_block(B.g, B.d, c, B.st);
+}
+
+// one CG iteration on the block fields: p = r + beta p ; t = M p ; alpha ;
+// q = M^dag t ; x += alpha p ; r -= alpha q ; beta, |r|^2 -> history slot k
+static bsm_status block_iteration(BlockSolve &B, int k) {
+    const Geom &g = B.g;
+    TRY(block_xpay(g, B.d, 1, B.p, B.rlo, B.scal + B_BETA * kNR, B.st));
+    int np = 0;
+    TRY(block_op(B, 0, B.p, B.t, true, &np));
+    TRY(block_scalars(B.partials, np, B.scal, B.mask, 0, 0, B.st));
+    TRY(block_op(B, 1, B.t, B.q, false, nullptr));
+    TRY(block_update(g, B.d, 1, B.xlo, B.p, B.rlo, B.q, B.scal + B_ALPHA * kNR, B.partials, B.st));
+    TRY(block_scalars(B.partials, block_blas_grid(g, B.d, 1), B.scal, B.mask, 1, k, B.st));
+    return BSM_OK;
+}
+
+static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
+    const Geom &g = B.g;
+    const int d = B.d, n = B.n;
+    hipStream_t st = B.st;
+    // ---- work memory
+    const size_t linkB = block_link_bytes(g, d);
+    BlockHopArgs one{};
+    one.np = 1;
+    const size_t parts = std::max((size_t)hop_block_grid(g, one), (size_t)block_blas_grid(g, d, 1)) * kNR;
+    // 15 carve-outs below, each rounded up to 256 bytes
+    size_t need = linkB + 6 * B.bbB + (size_t)(2 * n + 3) * B.bb64 + 2 * B.bb64 + parts * 8 +
+                  block_scal_doubles() * 8 + 64 * sizeof(int) + 16 * 256;
+    void *work = nullptr;
+    TRY(ctx_work(B.ctx, need, &work));
+    char *w = (char *)work;
+    auto take = [&](size_t bytes) { char *r = w; w += (bytes + 255) / 256 * 256; return r; };
+    B.Ublk = (float *)take(linkB);
+    B.p = (float2 *)take(B.bbB); B.t = (float2 *)take(B.bbB); B.q = (float2 *)take(B.bbB);
+    B.xlo = (float2 *)take(B.bbB); B.rlo = (float2 *)take(B.bbB); B.tmpB = (float2 *)take(B.bbB);
+    B.bh = take(n * B.bb64); B.r64 = take(n * B.bb64);
+    B.t64 = take(B.bb64); B.tmp64 = take(B.bb64); B.tfull = take(2 * B.bb64);
+    B.partials = (double *)take(parts * 8);
+    B.scal = (double *)take(block_scal_doubles() * 8);
+    B.mask = (int *)take(64 * sizeof(int));
+    // ---- links in block layout, per-RHS FP64 operators and right-hand sides
+    TRY(launch_gauge_to_block(g, d, BSM_F64, B.ops[0].U, B.Ublk, st));
+    BSM_HIP(hipMemsetAsync(B.x, 0, n * B.full64, st));
+    B.bnorm2.assign(n, 0.0);
+    B.rhs_norm2.assign(n, 0.0);
+    Vec none{nullptr, BSM_F64};
+    for (int r = 0; r < n; r++) {
+        Op &o = B.ops[r];
+        o.tmp = B.tmp64;
+        const char *br = B.b + r * B.full64;
+        char *bhr = B.bh + r * B.bb64;
+        HopArgs a{};
+        a.U = o.U; a.p0 = 0; a.np = 1;
+        a.in[0] = br + B.bb64; a.x[0] = br; a.out[0] = bhr;
+        a.a = 1.0; a.b = o.kappa;
+        TRY(launch_hop(g, d, o.real, BSM_F64, BSM_F64, a, st));
+        TRY(blas_dot(g, d, 2, Vec{(void *)br, BSM_F64}, none, B.ctx->partials, st));
+        B.bnorm2[r] = reduce_to_host(B.ctx, B.ctx->partials, blas_blocks(g, 2), st);
+        TRY(op_apply(o, 1, bhr, B.t64, false, nullptr, st));
+        TRY(blas_dot(g, d, 1, Vec{B.t64, BSM_F64}, none, B.ctx->partials, st));
+        B.rhs_norm2[r] = reduce_to_host(B.ctx, B.ctx->partials, blas_blocks(g, 1), st);
+    }
+    // ---- residuals: r64_r = M_r^dag (bhat_r - M_r x_r) for the selected RHS,
+    //      copied into the block residual; returns |r64_r|^2
+    std::vector<double> rr(kNR, 0.0), maxrr(kNR, 0.0), trig(n, B.prm->tol), res(n, INFINITY);
+    auto refresh = [&](unsigned sel) -> bsm_status {
+        for (int r = 0; r < n; r++) {
+            if (!((sel >> r) & 1u)) continue;
+            char *r64r = B.r64 + r * B.bb64;
+            TRY(normal_residual(B.ops[r], B.bh + r * B.bb64, B.x + r * B.full64, B.t64, r64r, st));
+            TRY(blas_dot(g, d, 1, Vec{r64r, BSM_F64}, none, B.ctx->partials, st));
+            rr[r] = reduce_to_host(B.ctx, B.ctx->partials, blas_blocks(g, 1), st);
+        }
+        return launch_std_block(g, d, n, sel, B.r64, B.bb64, 0, B.rlo, 0, st);
+    };
+    const unsigned all = n >= 32 ? 0xffffffffu : ((1u << n) - 1u);
+    TRY(refresh(all));
+    BSM_HIP(hipMemsetAsync(B.xlo, 0, B.bbB, st));
+    BSM_HIP(hipMemsetAsync(B.p, 0, B.bbB, st));
+    // pinned host mirrors of the device scalars and mask
+    double *hs = nullptr;
+    int *hmask = nullptr;
+    BSM_HIP(hipHostMalloc((void **)&hs, block_scal_doubles() * 8, hipHostMallocDefault));
+    if (hipHostMalloc((void **)&hmask, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        (void)hipHostFree(hs);
+        return fail(BSM_ERR_NOMEM, "pinned host scalars");
+    }
+    struct PinnedGuard {
+        double *a; int *b;
+        ~PinnedGuard() { (void)hipHostFree(a); (void)hipHostFree(b); }
+    } guard{hs, hmask};
+    for (size_t i = 0; i < block_scal_doubles(); i++) hs[i] = 0.0;
+    for (int i = 0; i < 64; i++) hmask[i] = 0;
+    for (int r = 0; r < n; r++) {
+        hmask[r] = 1;
+        hs[B_RR * kNR + r] = rr[r];
+        maxrr[r] = rr[r];
+    }
+    // beta = 0: the first xpay gives p = r
+    BSM_HIP(hipMemcpyAsync(B.scal, hs, block_scal_doubles() * 8, hipMemcpyHostToDevice, st));
+    BSM_HIP(hipMemcpyAsync(B.mask, hmask, 64 * sizeof(int), hipMemcpyHostToDevice, st));
+    BSM_HIP(hipStreamSynchronize(st));
+    // ---- capture K iterations once
+    B.K = std::max(1, std::min(B.prm->check_every > 0 ? B.prm->check_every : 8, kBlockHist));
+    hipGraph_t graph;
+    BSM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    bsm_status cap = BSM_OK;
+    for (int k = 0; k < B.K && cap == BSM_OK; k++) cap = block_iteration(B, k);
+    hipError_t ce = hipStreamEndCapture(st, &graph);
+    if (cap != BSM_OK) return cap;
+    BSM_HIP(ce);
+    BSM_HIP(hipGraphInstantiate(&B.graph, graph, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(graph);
+
+    const double delta2 = B.prm->delta > 0 ? B.prm->delta * B.prm->delta : 0.01;
+    int it = 0, active = n;
+    std::vector<int> iters(n, 0), updates(n, 0), restarts(n, 0);
+    std::vector<bsm_status> status(n, BSM_ERR_NOT_CONVERGED);
+    std::vector<double> prev(kNR, 0.0);
+    for (int r = 0; r < n; r++) prev[r] = rr[r];
+    while (active > 0 && it < B.prm->max_iter) {
+        BSM_HIP(hipGraphLaunch(B.graph, st));
+        it += B.K;
+        BSM_HIP(hipMemcpyAsync(hs, B.scal, block_scal_doubles() * 8, hipMemcpyDeviceToHost, st));
+        BSM_HIP(hipStreamSynchronize(st));
+        if (trace_enabled()) {
+            double mx = 0;
+            for (int r = 0; r < n; r++)
+                if (hmask[r]) mx = std::max(mx, hs[B_RR * kNR + r] / B.rhs_norm2[r]);
+            fprintf(stderr, "[batched] it %d active %d max rel normal residual^2 %.3e\n", it, active, mx);
+        }
+        unsigned upd = 0;
+        std::vector<double> before(kNR, 0.0);
+        for (int r = 0; r < n; r++) {
+            if (!hmask[r]) continue;
+            iters[r] = it;
+            bool bad = false;
+            for (int k = 0; k < B.K; k++) {
+                const double v = hs[(B_HIST + k) * kNR + r];
+                if (!std::isfinite(v)) bad = true;
+                maxrr[r] = std::max(maxrr[r], v);
+            }
+            if (bad) {
+                status[r] = BSM_ERR_NONFINITE;
+                hmask[r] = 0;
+                active--;
+                continue;
+            }
+            const double rnow = hs[B_RR * kNR + r];
+            before[r] = B.K >= 2 ? hs[(B_HIST + B.K - 2) * kNR + r] : prev[r];
+            prev[r] = rnow;
+            if (rnow < delta2 * maxrr[r] || rnow <= trig[r] * trig[r] * B.rhs_norm2[r]) upd |= 1u << r;
+        }
+        if (upd) {
+            // fold every x_lo into x64 (exact bookkeeping for all RHS), then
+            // replace the residual of the selected RHS by the FP64 one
+            TRY(launch_std_block(g, d, n, all, B.x, B.full64, 0, B.xlo, 1, st));
+            BSM_HIP(hipMemsetAsync(B.xlo, 0, B.bbB, st));
+            TRY(refresh(upd));
+            for (int r = 0; r < n; r++) {
+                if (!((upd >> r) & 1u)) continue;
+                if (trace_enabled())
+                    fprintf(stderr, "[batched]   rhs %d update: recurrence %.3e recomputed %.3e (rel^2)\n", r,
+                            hs[B_RR * kNR + r] / B.rhs_norm2[r], rr[r] / B.rhs_norm2[r]);
+                updates[r]++;
+                hs[B_BETA * kNR + r] = before[r] > 0 ? rr[r] / before[r] : 0.0;
+                hs[B_RR * kNR + r] = rr[r];
+                maxrr[r] = rr[r];
+                prev[r] = rr[r];
+                if (rr[r] <= trig[r] * trig[r] * B.rhs_norm2[r]) {
+                    Op o = B.ops[r];
+                    TRY(true_residual_full(o, B.b + r * B.full64, B.x + r * B.full64, B.tfull, B.bnorm2[r],
+                                           &res[r], st));
+                    if (trace_enabled())
+                        fprintf(stderr, "[batched]   rhs %d check: true residual %.3e (trigger %.1e)\n", r, res[r],
+                                trig[r]);
+                    if (res[r] <= B.prm->tol) {
+                        status[r] = BSM_OK;
+                        hmask[r] = 0;
+                        active--;
+                    } else {
+                        trig[r] *= 0.3;
+                        restarts[r]++;
+                    }
+                }
+            }
+            // only |r|^2 and beta change on the host (rows of the updated RHS;
+            // the others carry the values just read back)
+            BSM_HIP(hipMemcpyAsync(B.scal + B_RR * kNR, hs + B_RR * kNR, kNR * 8, hipMemcpyHostToDevice, st));
+            BSM_HIP(hipMemcpyAsync(B.scal + B_BETA * kNR, hs + B_BETA * kNR, kNR * 8, hipMemcpyHostToDevice, st));
+            BSM_HIP(hipMemcpyAsync(B.mask, hmask, 64 * sizeof(int), hipMemcpyHostToDevice, st));
+            BSM_HIP(hipStreamSynchronize(st));
+        }
+    }
+    // unconverged RHS: fold the last FP32 part in and report the true residual
+    if (active > 0) {
+        TRY(launch_std_block(g, d, n, all, B.x, B.full64, 0, B.xlo, 1, st));
+        for (int r = 0; r < n; r++)
+            if (hmask[r])
+                TRY(true_residual_full(B.ops[r], B.b + r * B.full64, B.x + r * B.full64, B.tfull, B.bnorm2[r],
+                                       &res[r], st));
+    }
+    (void)hipGraphExecDestroy(B.graph);
+    bsm_status worst = BSM_OK;
+    for (int r = 0; r < n; r++) {
+        stats[r].iters = iters[r];
+        stats[r].reliable_updates = updates[r];
+        stats[r].restarts = restarts[r];
+        stats[r].true_rel_res = res[r];
+        stats[r].converged = status[r] == BSM_OK;
+        if (status[r] != BSM_OK && worst == BSM_OK) worst = status[r];
+    }
+    return worst;
+}
+
+}  // namespace bsm
+
+extern "C" bsm_status bsm_batched_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep64,
+                                        const bsm_solver_params *prm, int32_t n_rhs, const double *kappas,
+                                        const void *b, void *x, bsm_solver_stats *stats, void *stream) {
+    if (!ctx || !desc || !prm || !kappas || !b || !x || !stats || !U_rep64) return fail(BSM_ERR_ARG, "null argument");
+    if (bsm_rep_dim(desc->N, desc->rep) != desc->d_R || desc->d_R < 2 || desc->d_R > 15)
+        return fail(BSM_ERR_ARG, "d_R does not match (N, rep) or is outside [2, 15]");
+    if (n_rhs < 1) return fail(BSM_ERR_ARG, "n_rhs must be >= 1");
+    for (int r = 0; r < n_rhs; r++)
+        if (!(kappas[r] > 0) || !std::isfinite(kappas[r])) return fail(BSM_ERR_ARG, "kappas must be > 0");
+    if (!(prm->tol > 0) || prm->max_iter < 1) return fail(BSM_ERR_ARG, "tol > 0 and max_iter >= 1 required");
+    if (b == x) return fail(BSM_ERR_ARG, "b and x must differ");
+    const Geom &g = ctx->g;
+    const int d = desc->d_R;
+    const size_t bb64 = spinor_block_bytes(BSM_F64, d, g.Vh_pad);
+    hipStream_t user = (hipStream_t)stream;
+    BSM_HIP(hipStreamSynchronize(user));
+    auto t0 = std::chrono::steady_clock::now();
+    bsm_status worst = BSM_OK;
+    if (desc->rep != BSM_REP_ADJ) {
+        // complex links: no shared-link block kernel; solve one RHS at a time
+        // (plain FP64 for an F64 desc, otherwise reliable-update CG with inner
+        // precision desc->prec on links converted to desc->link_prec)
+        void *Ulo = nullptr;
+        if (desc->prec != BSM_F64) {
+            if (desc->link_prec == BSM_F64) return fail(BSM_ERR_ARG, "mixed inner solve needs F32 or F16 links");
+            const size_t lb = 8 * link_block_bytes(desc->link_prec, false, d, g.Vh_pad);
+            BSM_HIP(hipMalloc(&Ulo, lb));
+            bsm_status cs = launch_convert_links(g, d, false, BSM_F64, desc->link_prec, U_rep64, Ulo, user);
+            if (cs != BSM_OK) { (void)hipFree(Ulo); return cs; }
+        }
+        bsm_field_desc d64 = *desc;
+        d64.prec = BSM_F64;
+        d64.link_prec = BSM_F64;
+        for (int r = 0; r < n_rhs; r++) {
+            bsm_solver_params p1 = *prm;
+            p1.kappa = kappas[r];
+            p1.schur = 1;
+            p1.variant = Ulo ? BSM_SOLVER_MIXED : BSM_SOLVER_PLAIN;
+            bsm_status s = bsm_cg_solve(ctx, Ulo ? desc : &d64, Ulo ? Ulo : U_rep64, U_rep64, &p1,
+                                        (const char *)b + r * 2 * bb64, (char *)x + r * 2 * bb64, &stats[r],
+                                        stream);
+            if (s != BSM_OK && worst == BSM_OK) worst = s;
+        }
+        if (Ulo) (void)hipFree(Ulo);
+        return worst;
+    }
+    hipStream_t st;
+    BSM_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    for (int r0 = 0; r0 < n_rhs; r0 += kNR) {
+        BlockSolve B{};
+        B.ctx = ctx;
+        B.g = g;
+        B.d = d;
+        B.n = std::min(kNR, n_rhs - r0);
+        B.st = st;
+        B.prm = prm;
+        B.kappas = kappas + r0;
+        B.b = (const char *)b + (size_t)r0 * 2 * bb64;
+        B.x = (char *)x + (size_t)r0 * 2 * bb64;
+        B.full64 = 2 * bb64;
+        B.bb64 = bb64;
+        B.bbB = block_parity_bytes(g, d);
+        for (int r = 0; r < B.n; r++) {
+            Op o{};
+            o.ctx = ctx; o.g = g; o.d = d; o.real = true; o.schur = true; o.kappa = B.kappas[r];
+            o.U = U_rep64; o.sprec = BSM_F64; o.lprec = BSM_F64; o.partials = ctx->partials;
+            B.ops.push_back(o);
+        }
+        bsm_status s = solve_block(B, stats + r0);
+        if (s != BSM_OK && worst == BSM_OK) worst = s;
+        if (s != BSM_OK && s != BSM_ERR_NOT_CONVERGED && s != BSM_ERR_NONFINITE) break;
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int r = 0; r < n_rhs; r++) stats[r].seconds = secs;
+    if (worst == BSM_ERR_NOT_CONVERGED) fail(worst, "max_iter reached before every RHS met tol");
+    if (worst == BSM_ERR_NONFINITE) fail(worst, "non-finite value in a reduction");
+    return worst;
 }

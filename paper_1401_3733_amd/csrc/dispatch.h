@@ -41,6 +41,8 @@ bsm_status launch_pack_spinor(const Geom &g, int d, int prec, int n_rhs, const v
                               void *internal, hipStream_t st, bool unpack);
 bsm_status launch_represent(const Geom &g, int N, int rep, int d, int link_prec, const void *Uc,
                             void *out, hipStream_t st);
+bsm_status launch_convert_links(const Geom &g, int d, bool real, int src_prec, int dst_prec, const void *src,
+                                void *dst, hipStream_t st);
 bsm_status launch_unpack_gauge(const Geom &g, int d, bool real, int link_prec, const void *in,
                                void *canon, hipStream_t st);
 

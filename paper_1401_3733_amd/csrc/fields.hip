@@ -288,4 +288,43 @@ bsm_status launch_unpack_gauge(const Geom &g, int d, bool real, int link_prec, c
     return fail(BSM_ERR_ARG, "bad link precision");
 }
 
+// links stored in one precision -> another (elementwise over all planes)
+template <int SRC, int DST, bool REAL>
+__global__ __launch_bounds__(256) void k_convert_links(size_t nelem, const char *src, char *dst) {
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < nelem; e += (size_t)gridDim.x * 256) {
+        const int64_t i = (int64_t)e;
+        // read element i of the flat plane array
+        double re, im = 0.0;
+        if constexpr (REAL) {
+            if constexpr (SRC == BSM_F64) re = ((const double *)src)[i];
+            else if constexpr (SRC == BSM_F32) re = ((const float *)src)[i];
+            else re = __half2float(((const __half *)src)[i]);
+        } else {
+            if constexpr (SRC == BSM_F64) { double2 t = ((const double2 *)src)[i]; re = t.x; im = t.y; }
+            else if constexpr (SRC == BSM_F32) { float2 t = ((const float2 *)src)[i]; re = t.x; im = t.y; }
+            else { float2 t = __half22float2(((const __half2 *)src)[i]); re = t.x; im = t.y; }
+        }
+        store_link<DST, REAL>(dst, 0, 0, (uint32_t)i, re, im);
+    }
+}
+
+template <int SRC, int DST>
+static bsm_status conv2(size_t n, bool real, const void *src, void *dst, hipStream_t st) {
+    size_t nb = (n + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    if (real) k_convert_links<SRC, DST, true><<<(int)nb, 256, 0, st>>>(n, (const char *)src, (char *)dst);
+    else k_convert_links<SRC, DST, false><<<(int)nb, 256, 0, st>>>(n, (const char *)src, (char *)dst);
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
+bsm_status launch_convert_links(const Geom &g, int d, bool real, int src_prec, int dst_prec, const void *src,
+                                void *dst, hipStream_t st) {
+    const size_t n = (size_t)8 * d * d * g.Vh_pad;
+    if (src_prec == BSM_F64 && dst_prec == BSM_F32) return conv2<BSM_F64, BSM_F32>(n, real, src, dst, st);
+    if (src_prec == BSM_F64 && dst_prec == BSM_F16S) return conv2<BSM_F64, BSM_F16S>(n, real, src, dst, st);
+    if (src_prec == BSM_F32 && dst_prec == BSM_F16S) return conv2<BSM_F32, BSM_F16S>(n, real, src, dst, st);
+    return fail(BSM_ERR_UNSUPPORTED, "link conversion");
+}
+
 }  // namespace bsm

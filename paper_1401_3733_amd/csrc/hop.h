@@ -124,37 +124,6 @@ __device__ inline void link_mul(const LinkRegs<D, REAL, LP, NT, T> &L, const voi
     }
 }
 
-// neighbour of c one step along +mu (back = false) or -mu: half index and the
-// boundary factor of the hop
-template <int MU>
-__device__ inline uint32_t neighbour(const Geom &g, const Coords &c, bool back, float &w) {
-    const int Lmu = g.L[MU];
-    const int xm = MU == 0 ? c.t : MU == 1 ? c.x : MU == 2 ? c.y : c.z;
-    int xn = back ? xm - 1 : xm + 1;
-    w = 1.f;
-    const bool ap = (g.apbc >> MU) & 1;
-    if (xn == Lmu) { xn = 0; if (ap) w = -1.f; }
-    if (xn < 0) { xn = Lmu - 1; if (ap) w = -1.f; }
-    if constexpr (MU == 1) {
-        return (uint32_t)c.row * g.LXh + (xn >> 1);
-    } else {
-        int t = c.t, z = c.z, y = c.y;
-        if (MU == 0) t = xn;
-        if (MU == 2) y = xn;
-        if (MU == 3) z = xn;
-        uint32_t row = ((uint32_t)t * g.L[3] + z) * g.L[2] + y;
-        return row * g.LXh + c.xh;
-    }
-}
-
-// one hop with the neighbour's half spinor already projected: link multiply
-// (forward link of this site, or the daggered link of the neighbour) and
-// reconstruction into acc
-// Non-temporal link loads per spinor precision (bit SP of BSM_LINK_NT).
-#ifndef BSM_LINK_NT
-#define BSM_LINK_NT 0x7
-#endif
-
 // link block and site of a hop: forward uses U_mu(x) (this site, parity p),
 // backward U_mu(x - mu) stored at the neighbour (parity 1-p)
 template <int MU, bool BACK>
@@ -162,6 +131,9 @@ __device__ inline const char *link_block(const char *U, size_t lblk, int p) {
     return U + (size_t)((BACK ? 1 - p : p) * 4 + MU) * lblk;
 }
 
+// one hop with the neighbour's half spinor already projected: link multiply
+// (forward link of this site, or the daggered link of the neighbour) and
+// reconstruction into acc
 template <int MU, int D, bool REAL, int LP, bool BACK, class T, bool NT = true>
 __device__ inline void hop_half(const Geom &g, const LinkRegs<D, REAL, LP, NT, T> &L, const char *blk,
                                 uint32_t hl, T sg, T w, const cx<T> (&h0)[D], const cx<T> (&h1)[D],

@@ -120,6 +120,34 @@ __device__ inline cx<T> load_link(const void *blk, int64_t stride, int e, uint32
     }
 }
 
+// neighbour of c one step along +mu (back = false) or -mu: half index and the
+// boundary factor of the hop
+template <int MU>
+__device__ inline uint32_t neighbour(const Geom &g, const Coords &c, bool back, float &w) {
+    const int Lmu = g.L[MU];
+    const int xm = MU == 0 ? c.t : MU == 1 ? c.x : MU == 2 ? c.y : c.z;
+    int xn = back ? xm - 1 : xm + 1;
+    w = 1.f;
+    const bool ap = (g.apbc >> MU) & 1;
+    if (xn == Lmu) { xn = 0; if (ap) w = -1.f; }
+    if (xn < 0) { xn = Lmu - 1; if (ap) w = -1.f; }
+    if constexpr (MU == 1) {
+        return (uint32_t)c.row * g.LXh + (xn >> 1);
+    } else {
+        int t = c.t, z = c.z, y = c.y;
+        if (MU == 0) t = xn;
+        if (MU == 2) y = xn;
+        if (MU == 3) z = xn;
+        uint32_t row = ((uint32_t)t * g.L[3] + z) * g.L[2] + y;
+        return row * g.LXh + c.xh;
+    }
+}
+
+// Non-temporal link loads per spinor precision (bit SP of BSM_LINK_NT).
+#ifndef BSM_LINK_NT
+#define BSM_LINK_NT 0x7
+#endif
+
 // Sum over a 256-thread workgroup in a fixed order (valid on thread 0):
 // xor-shuffles inside each 64-wide wavefront, then the 4 wavefronts in order.
 __device__ inline double block_sum_256(double v) {

@@ -1,0 +1,151 @@
+"""Multi-RHS block path: the matrix-core hop of 16 right-hand sides and the
+batched solver, against the FP64 oracle applied to each RHS."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1401_3733_amd import bsm
+from paper_1401_3733_amd import inputs as gen
+from tests.gpu_util import Setup, c128, note, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _block_setup(lat, N, seed):
+    Uf = gen.gauge_links(lat, N, "haar", seed)
+    S = Setup(lat, N, "adj", Uf, prec="f64")
+    UR = oracle.represent(Uf, "adj").real.astype(np.complex128)
+    Ub = S.ctx.new_block_gauge(S.desc)
+    S.ctx.bsm_gauge_to_block(S.desc, S.U, Ub)
+    return S, UR, Ub
+
+
+def _unpack_block(S, blk, n):
+    import torch
+    out = torch.zeros((n, S.lat.V, 4, S.d), dtype=torch.complex128, device="cuda")
+    S.ctx.bsm_unpack_block(S.desc, blk, out, n)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("N", [2, 3, 4])
+@pytest.mark.parametrize("n_rhs", [16, 5])
+def test_block_hop_matches_oracle_per_rhs(N, n_rhs):
+    note(f"block hop N={N} n_rhs={n_rhs}")
+    lat = gen.Lattice(8, 6, 4, 6)
+    S, UR, Ub = _block_setup(lat, N, 700 + N)
+    d = S.d
+    psi = gen.gaussian_spinor(lat, d, 701, n_rhs=n_rhs)
+    xs = gen.gaussian_spinor(lat, d, 702, n_rhs=n_rhs)
+    A, X = S.ctx.new_block(S.desc), S.ctx.new_block(S.desc)
+    S.ctx.bsm_pack_block(S.desc, c128(psi), A, n_rhs)
+    S.ctx.bsm_pack_block(S.desc, c128(xs), X, n_rhs)
+    # pack/unpack round trip is the FP32 rounding of the input
+    back = _unpack_block(S, A, n_rhs)
+    assert rel(back, psi) < 1e-7
+    nb = S.ctx.block_bytes(S.desc) // 2
+    par = oracle.parity_mask(lat)
+    a = np.linspace(0.5, 1.5, 16)
+    b = -np.linspace(0.01, 0.02, 16)
+    for p in (0, 1):
+        for dag in (0, 1):
+            out = S.ctx.new_block(S.desc)
+            S.ctx.bsm_dslash_eo_block(S.desc, Ub, p, dag, a, X[p * nb:(p + 1) * nb], b,
+                                      A[(1 - p) * nb:(2 - p) * nb], out[p * nb:(p + 1) * nb])
+            got = _unpack_block(S, out, n_rhs)
+            for r in range(n_rhs):
+                ref = a[r] * xs[r] + b[r] * oracle.hop(lat, UR, psi[r], dagger=bool(dag), parity=p)
+                m = par == p
+                assert rel(got[r][m], ref[m]) < 2e-6, (p, dag, r, rel(got[r][m], ref[m]))
+                assert np.all(got[r][~m] == 0)
+
+
+def test_block_hop_without_x():
+    lat = gen.Lattice(4, 4, 4, 4)
+    S, UR, Ub = _block_setup(lat, 4, 710)
+    psi = gen.gaussian_spinor(lat, 15, 711, n_rhs=16)
+    A = S.ctx.new_block(S.desc)
+    S.ctx.bsm_pack_block(S.desc, c128(psi), A, 16)
+    nb = S.ctx.block_bytes(S.desc) // 2
+    out = S.ctx.new_block(S.desc)
+    S.ctx.bsm_dslash_eo_block(S.desc, Ub, 0, 0, None, None, np.ones(16), A[nb:], out[:nb])
+    got = _unpack_block(S, out, 16)
+    par = oracle.parity_mask(lat)
+    for r in (0, 7, 15):
+        ref = oracle.hop(lat, UR, psi[r], parity=0)
+        assert rel(got[r][par == 0], ref[par == 0]) < 2e-6
+
+
+@pytest.mark.parametrize("n_rhs", [16, 3])
+def test_batched_solve_adjoint(n_rhs):
+    note(f"batched solve adjoint n_rhs={n_rhs}")
+    lat = gen.Lattice(8, 4, 4, 6)
+    Uf = gen.gauge_links(lat, 4, "haar", 720)
+    S = Setup(lat, 4, "adj", Uf, prec="f64")
+    UR = oracle.represent(Uf, "adj").real.astype(np.complex128)
+    kappas = list(np.linspace(0.10, 0.125, 16))[:n_rhs]
+    b = gen.gaussian_spinor(lat, 15, 721, n_rhs=n_rhs)
+    bb = S.pack(b, n_rhs=n_rhs)
+    import torch
+    x = torch.zeros_like(bb)
+    prm = bsm.solver_params(0.1, 1e-10, schur=True, check_every=8)
+    status, stats = S.ctx.bsm_batched_solve(S.desc, S.U, prm, kappas, bb, x)
+    xs = S.unpack(x, n_rhs=n_rhs)
+    print(stats[0], stats[-1])
+    assert status == 0
+    for r in range(n_rhs):
+        assert stats[r]["converged"]
+        tr = oracle.true_residual(lat, UR, kappas[r], b[r], xs[r])
+        assert tr <= 1e-10, (r, tr)
+        assert abs(tr - stats[r]["true_rel_res"]) < 1e-12
+    for r in (0, n_rhs - 1):
+        xo, _ = oracle.solve(lat, UR, kappas[r], b[r], tol=1e-13, schur=True)
+        assert rel(xs[r], xo) <= 1e-9
+
+
+def test_batched_solve_complex_links_fallback():
+    note("batched solve fund fallback")
+    lat = gen.Lattice(8, 4, 4, 4)
+    Uf = gen.gauge_links(lat, 3, "near_identity", 730, eps=0.3)
+    S = Setup(lat, 3, "fund", Uf, prec="f64")
+    S32 = Setup(lat, 3, "fund", Uf, prec="f32")
+    kappas = [0.11, 0.12, 0.125]
+    b = gen.gaussian_spinor(lat, 3, 731, n_rhs=3)
+    bb = S.pack(b, n_rhs=3)
+    import torch
+    x = torch.zeros_like(bb)
+    status, stats = S32.ctx.bsm_batched_solve(S32.desc, S.U, bsm.solver_params(0.1, 1e-10), kappas, bb, x)
+    xs = S.unpack(x, n_rhs=3)
+    assert status == 0
+    for r in range(3):
+        assert oracle.true_residual(lat, Uf, kappas[r], b[r], xs[r]) <= 1e-10
+
+
+def test_block_hop_full_size_sampled():
+    """24^3x48 SU(4) adjoint, 16 RHS, the launch configuration of the batched
+    solver: out_r = x_r - H in_r with x = in = psi_r gives D(kappa=1) psi_r on
+    the output parity; compared at sampled sites with the oracle."""
+    note("block hop full size sampled")
+    lat = gen.config_lattice(4)
+    Uf = gen.config_links(4, lat)
+    S = Setup(lat, 4, "adj", Uf, prec="f64")
+    UR = oracle.represent(Uf, "adj").real.astype(np.complex128)
+    Ub = S.ctx.new_block_gauge(S.desc)
+    S.ctx.bsm_gauge_to_block(S.desc, S.U, Ub)
+    n_rhs = 4
+    psi = gen.gaussian_spinor(lat, 15, 740, n_rhs=n_rhs)
+    A = S.ctx.new_block(S.desc)
+    S.ctx.bsm_pack_block(S.desc, c128(psi), A, n_rhs)
+    nb = S.ctx.block_bytes(S.desc) // 2
+    par = oracle.parity_mask(lat)
+    rng = np.random.default_rng(5)
+    for p in (0, 1):
+        out = S.ctx.new_block(S.desc)
+        S.ctx.bsm_dslash_eo_block(S.desc, Ub, p, 0, np.ones(16), A[p * nb:(p + 1) * nb], -np.ones(16),
+                                  A[(1 - p) * nb:(2 - p) * nb], out[p * nb:(p + 1) * nb])
+        got = _unpack_block(S, out, n_rhs)
+        sites = np.flatnonzero(par == p)
+        sample = np.concatenate([sites[:64], sites[-64:], rng.choice(sites, 256, replace=False)])
+        for r in range(n_rhs):
+            ref = oracle.dslash_sites(lat, UR, 1.0, psi[r], sample)
+            assert rel(got[r][sample], ref) < 2e-6, (p, r, rel(got[r][sample], ref))
