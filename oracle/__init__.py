@@ -68,6 +68,8 @@ def lib():
         L.orc_op_apply.argtypes = [ip, ip, C.c_int, dp, C.c_double, C.c_int, C.c_int, dp, dp]
         L.orc_gamma.argtypes = [C.c_int, dp]
         L.orc_parity.argtypes = [ip, C.c_long]
+        for name in ("orc_ptc_layer", "orc_ptc_layer_adjoint", "orc_ptc_weight_grad"):
+            getattr(L, name).argtypes = [ip, ip, C.c_int, dp, C.c_int, C.c_int, dp, dp, dp]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
         _lib = L
@@ -188,6 +190,34 @@ def cgnr_raw(lat, U, kappa, b, x0=None, tol=1e-10, maxit=100000, schur=False):
     it = lib().orc_cgnr_raw(_ip(lat.dims), _ip(lat.bc), _d_of(U), _dp(U), float(kappa),
                             int(schur), _dp(b), _dp(x), float(tol), int(maxit), C.byref(rel))
     return x, it, rel.value
+
+
+def ptc_layer(lat, U, W, inp):
+    """PTC layer: W [cout][cin][9][4][4], inp [cin][V][4][d] -> [cout][V][4][d]."""
+    U, W, inp = _c128(U), _c128(W), _c128(inp)
+    cout, cin = W.shape[:2]
+    out = np.zeros((cout,) + inp.shape[1:], np.complex128)
+    lib().orc_ptc_layer(_ip(lat.dims), _ip(lat.bc), _d_of(U), _dp(U), cin, cout, _dp(W), _dp(inp), _dp(out))
+    return out
+
+
+def ptc_layer_adjoint(lat, U, W, inp):
+    """Adjoint of ptc_layer: inp [cout][V][4][d] -> [cin][V][4][d]."""
+    U, W, inp = _c128(U), _c128(W), _c128(inp)
+    cout, cin = W.shape[:2]
+    out = np.zeros((cin,) + inp.shape[1:], np.complex128)
+    lib().orc_ptc_layer_adjoint(_ip(lat.dims), _ip(lat.bc), _d_of(U), _dp(U), cin, cout, _dp(W), _dp(inp),
+                                _dp(out))
+    return out
+
+
+def ptc_weight_grad(lat, U, G, v, cin, cout):
+    """dW [cout][cin][9][4][4] for output gradient G [cout][..] and input v [cin][..]."""
+    U, G, v = _c128(U), _c128(G), _c128(v)
+    dW = np.zeros((cout, cin, 9, 4, 4), np.complex128)
+    lib().orc_ptc_weight_grad(_ip(lat.dims), _ip(lat.bc), _d_of(U), _dp(U), cin, cout, _dp(G), _dp(v),
+                              _dp(dW))
+    return dW
 
 
 def parity_mask(lat) -> np.ndarray:

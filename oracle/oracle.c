@@ -550,3 +550,125 @@ void orc_set_num_threads(int n)
     (void)n;
 #endif
 }
+
+/* ------------------------------------------------------------------ */
+/* parallel-transport convolution (PTC) layer                          */
+/*   out_i(x) = sum_j sum_p W_p^{ij} (T_p in_j)(x)                      */
+/* paths p: 0 = stay, 1 + mu = hop from x + mu, 5 + mu = hop from x - mu */
+/*   T_0 in(x) = in(x)                                                 */
+/*   T_{1+mu} in(x) = s+ U_mu(x) in(x + mu)                            */
+/*   T_{5+mu} in(x) = s- U_mu(x - mu)^dag in(x - mu)                   */
+/* W_p^{ij} is a complex 4 x 4 spin matrix; W layout                   */
+/* [cout][cin][9][4][4]; channel fields [c][V][4][d].                  */
+/* ------------------------------------------------------------------ */
+
+/* t[a][i] = (T_p f)(s) for spinor field f */
+static void transport(const int L[4], const int bc[4], int d, const cplx *U, int p, const cplx *f, long s,
+                      cplx *t)
+{
+    if (p == 0) {
+        for (int k = 0; k < 4 * d; k++) t[k] = f[(size_t)s * 4 * d + k];
+        return;
+    }
+    int mu = (p - 1) % 4;
+    int dir = p <= 4 ? +1 : -1;
+    double sign;
+    long y = neighbour(L, bc, s, mu, dir, &sign);
+    const cplx *link = dir > 0 ? U + ((size_t)s * 4 + mu) * d * d : U + ((size_t)y * 4 + mu) * d * d;
+    const cplx *v = f + (size_t)y * 4 * d;
+    for (int a = 0; a < 4; a++)
+        for (int i = 0; i < d; i++) {
+            cplx acc = 0;
+            for (int j = 0; j < d; j++)
+                acc += dir > 0 ? link[i * d + j] * v[a * d + j] : conj(link[j * d + i]) * v[a * d + j];
+            t[a * d + i] = sign * acc;
+        }
+}
+
+static int reverse_path(int p) { return p == 0 ? 0 : (p <= 4 ? p + 4 : p - 4); }
+
+void orc_ptc_layer(const int L[4], const int bc[4], int d, const double *Uin, int cin, int cout,
+                   const double *Win, const double *in, double *out)
+{
+    const cplx *U = (const cplx *)Uin, *W = (const cplx *)Win, *f = (const cplx *)in;
+    cplx *o = (cplx *)out;
+    long V = volume(L);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; s++) {
+        cplx t[4 * 16];
+        for (int i = 0; i < cout; i++)
+            for (int k = 0; k < 4 * d; k++) o[((size_t)i * V + s) * 4 * d + k] = 0;
+        for (int j = 0; j < cin; j++)
+            for (int p = 0; p < 9; p++) {
+                transport(L, bc, d, U, p, f + (size_t)j * V * 4 * d, s, t);
+                for (int i = 0; i < cout; i++) {
+                    const cplx *w = W + (((size_t)i * cin + j) * 9 + p) * 16;
+                    cplx *oi = o + ((size_t)i * V + s) * 4 * d;
+                    for (int a = 0; a < 4; a++)
+                        for (int b = 0; b < 4; b++)
+                            for (int c = 0; c < d; c++) oi[a * d + c] += w[a * 4 + b] * t[b * d + c];
+                }
+            }
+    }
+}
+
+/* the adjoint layer: out_j = sum_i sum_p (W_p^{ij})^dag (T_{rev p} in_i),
+ * in: [cout][V][4][d] -> out: [cin][V][4][d] (T_p^dag = T_{rev p}) */
+void orc_ptc_layer_adjoint(const int L[4], const int bc[4], int d, const double *Uin, int cin, int cout,
+                           const double *Win, const double *in, double *out)
+{
+    const cplx *U = (const cplx *)Uin, *W = (const cplx *)Win, *f = (const cplx *)in;
+    cplx *o = (cplx *)out;
+    long V = volume(L);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; s++) {
+        cplx t[4 * 16];
+        for (int j = 0; j < cin; j++)
+            for (int k = 0; k < 4 * d; k++) o[((size_t)j * V + s) * 4 * d + k] = 0;
+        for (int i = 0; i < cout; i++)
+            for (int p = 0; p < 9; p++) {
+                transport(L, bc, d, U, reverse_path(p), f + (size_t)i * V * 4 * d, s, t);
+                for (int j = 0; j < cin; j++) {
+                    const cplx *w = W + (((size_t)i * cin + j) * 9 + p) * 16;
+                    cplx *oj = o + ((size_t)j * V + s) * 4 * d;
+                    for (int a = 0; a < 4; a++)
+                        for (int b = 0; b < 4; b++)
+                            for (int c = 0; c < d; c++) oj[b * d + c] += conj(w[a * 4 + b]) * t[a * d + c];
+                }
+            }
+    }
+}
+
+/* gradient of a real loss with respect to W (Wirtinger convention
+ * dL/dRe W + i dL/dIm W) given G = dL/dRe out + i dL/dIm out and the layer
+ * input v:  dW_p^{ij}[a][b] = sum_x sum_c G_i(x)[a][c] conj((T_p v_j)(x)[b][c]) */
+void orc_ptc_weight_grad(const int L[4], const int bc[4], int d, const double *Uin, int cin, int cout,
+                         const double *Gin, const double *vin, double *dWout)
+{
+    const cplx *U = (const cplx *)Uin, *G = (const cplx *)Gin, *v = (const cplx *)vin;
+    cplx *dW = (cplx *)dWout;
+    long V = volume(L);
+    size_t nw = (size_t)cout * cin * 9 * 16;
+    for (size_t k = 0; k < nw; k++) dW[k] = 0;
+#pragma omp parallel
+    {
+        cplx *loc = calloc(nw, sizeof(cplx));
+        cplx t[4 * 16];
+#pragma omp for schedule(static)
+        for (long s = 0; s < V; s++)
+            for (int j = 0; j < cin; j++)
+                for (int p = 0; p < 9; p++) {
+                    transport(L, bc, d, U, p, v + (size_t)j * V * 4 * d, s, t);
+                    for (int i = 0; i < cout; i++) {
+                        const cplx *g = G + ((size_t)i * V + s) * 4 * d;
+                        cplx *w = loc + (((size_t)i * cin + j) * 9 + p) * 16;
+                        for (int a = 0; a < 4; a++)
+                            for (int b = 0; b < 4; b++)
+                                for (int c = 0; c < d; c++) w[a * 4 + b] += g[a * d + c] * conj(t[b * d + c]);
+                    }
+                }
+#pragma omp critical
+        for (size_t k = 0; k < nw; k++) dW[k] += loc[k];
+        free(loc);
+    }
+}

@@ -1,0 +1,170 @@
+"""Pins of the PTC layer, its adjoint and weight gradient, the two-layer
+net's backpropagation, Adam and FGCR."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dense, ptc
+from paper_1401_3733_amd import inputs as gen
+from tests.helpers import gauge_transform_links, rel, vdot
+
+KAPPA = 0.13
+
+
+def _rand_w(shape, seed):
+    g = np.random.default_rng(seed)
+    return g.standard_normal(shape) + 1j * g.standard_normal(shape)
+
+
+def test_wilson_weights_reproduce_the_dirac_operator():
+    lat = gen.Lattice(4, 2, 4, 2)
+    U = gen.gauge_links(lat, 3, "haar", 1)
+    psi = gen.gaussian_spinor(lat, 3, 2)
+    out = oracle.ptc_layer(lat, U, ptc.wilson_weights(KAPPA), psi[None])[0]
+    assert rel(out, oracle.dslash(lat, U, KAPPA, psi)) < 1e-15
+
+
+def test_identity_weights():
+    lat = gen.Lattice(2, 2, 2, 4)
+    U = gen.gauge_links(lat, 2, "haar", 3)
+    psi = gen.gaussian_spinor(lat, 2, 4, n_rhs=3)
+    W = np.zeros((3, 3, 9, 4, 4), complex)
+    for i in range(3):
+        W[i, i, 0] = np.eye(4)
+    assert np.array_equal(oracle.ptc_layer(lat, U, W, psi), psi)
+
+
+def test_gauge_equivariance():
+    lat = gen.Lattice(4, 2, 2, 4)
+    Uf = gen.gauge_links(lat, 3, "haar", 5)
+    Om = gen.random_gauge_transform(lat, 3, 6)
+    Ut = gauge_transform_links(lat, Uf, Om)
+    W = _rand_w((2, 2, 9, 4, 4), 7)
+    psi = gen.gaussian_spinor(lat, 3, 8, n_rhs=2)
+    rot = lambda f: np.einsum("sij,csaj->csai", Om, f)
+    lhs = oracle.ptc_layer(lat, Ut, W, rot(psi))
+    rhs = rot(oracle.ptc_layer(lat, Uf, W, psi))
+    assert rel(lhs, rhs) < 1e-14
+
+
+def test_adjoint_layer_identity():
+    lat = gen.Lattice(4, 2, 4, 2, bc=(-1, 1, -1, 1))
+    U = gen.gauge_links(lat, 2, "haar", 9)
+    W = _rand_w((3, 2, 9, 4, 4), 10)
+    x = gen.gaussian_spinor(lat, 2, 11, n_rhs=2)
+    y = gen.gaussian_spinor(lat, 2, 12, n_rhs=3)
+    a = vdot(y, oracle.ptc_layer(lat, U, W, x))
+    b = vdot(oracle.ptc_layer_adjoint(lat, U, W, y), x)
+    assert abs(a - b) / abs(a) < 1e-14
+    # the Wilson weights: the adjoint layer is D^dag
+    psi = gen.gaussian_spinor(lat, 2, 13)
+    Dd = oracle.ptc_layer_adjoint(lat, U, ptc.wilson_weights(KAPPA), psi[None])[0]
+    assert rel(Dd, oracle.dslash(lat, U, KAPPA, psi, dagger=True)) < 1e-15
+
+
+def test_weight_gradient_matches_finite_differences():
+    lat = gen.Lattice(2, 2, 2, 4)
+    U = gen.gauge_links(lat, 2, "haar", 14)
+    cin, cout = 2, 3
+    W = _rand_w((cout, cin, 9, 4, 4), 15) * 0.3
+    v = gen.gaussian_spinor(lat, 2, 16, n_rhs=cin)
+    t = gen.gaussian_spinor(lat, 2, 17, n_rhs=cout)
+
+    def loss(W):
+        d = oracle.ptc_layer(lat, U, W, v) - t
+        return np.vdot(d, d).real
+
+    G = 2 * (oracle.ptc_layer(lat, U, W, v) - t)
+    dW = oracle.ptc_weight_grad(lat, U, G, v, cin, cout)
+    g = np.random.default_rng(0)
+    # the loss is quadratic in any single weight, so the central difference is
+    # exact up to rounding; a large step keeps the rounding small
+    h = 1e-3
+    for _ in range(12):
+        idx = tuple(int(g.integers(0, n)) for n in W.shape)
+        for part, unit in (("re", 1.0), ("im", 1j)):
+            Wp, Wm = W.copy(), W.copy()
+            Wp[idx] += h * unit
+            Wm[idx] -= h * unit
+            fd = (loss(Wp) - loss(Wm)) / (2 * h)
+            an = dW[idx].real if part == "re" else dW[idx].imag
+            assert abs(fd - an) <= 1e-8 * max(1.0, abs(an)), (idx, part, fd, an)
+
+
+def test_net_backprop_matches_finite_differences():
+    lat = gen.Lattice(2, 2, 2, 4)
+    U = gen.gauge_links(lat, 3, "near_identity", 18, eps=0.5)
+    W1, W2 = ptc.init_weights(4, 19)
+    W1 = W1 + 0.05 * _rand_w(W1.shape, 20)
+    W2 = W2 + 0.05 * _rand_w(W2.shape, 21)
+    es = [gen.gaussian_spinor(lat, 3, 22 + k) for k in range(2)]
+    rs = [oracle.dslash(lat, U, KAPPA, e) for e in es]
+    L, g1, g2 = ptc.loss_and_grad(lat, U, W1, W2, rs, es)
+    g = np.random.default_rng(1)
+    h = 1e-3   # quadratic in each single weight: central differences are exact
+    for which, W, gW in (("W1", W1, g1), ("W2", W2, g2)):
+        for _ in range(6):
+            idx = tuple(int(g.integers(0, n)) for n in W.shape)
+            for unit, part in ((1.0, "re"), (1j, "im")):
+                Wp, Wm = W.copy(), W.copy()
+                Wp[idx] += h * unit
+                Wm[idx] -= h * unit
+                args_p = (Wp, W2) if which == "W1" else (W1, Wp)
+                args_m = (Wm, W2) if which == "W1" else (W1, Wm)
+                fd = (ptc.loss_and_grad(lat, U, *args_p, rs, es)[0] -
+                      ptc.loss_and_grad(lat, U, *args_m, rs, es)[0]) / (2 * h)
+                an = gW[idx].real if part == "re" else gW[idx].imag
+                assert abs(fd - an) <= 1e-8 * max(1.0, abs(an)), (which, idx, part, fd, an)
+
+
+def test_adam_first_steps_closed_form():
+    # with a constant gradient g, mhat = g and vhat = g^2 at every step, so each
+    # step moves every real coordinate by -lr * sign(g) (up to eps)
+    opt = ptc.Adam(lr=1e-2)
+    w = np.array([1.0 + 2.0j, -0.5 + 0.0j])
+    g = np.array([0.3 - 4.0j, -2.0 + 1e-3j])
+    w1 = opt.step(w, g)
+    w2 = opt.step(w1, g)
+    step = -1e-2 * (np.sign(g.real) + 1j * np.sign(g.imag))
+    assert np.allclose(w1 - w, step, atol=1e-8)
+    assert np.allclose(w2 - w1, step, atol=1e-8)
+
+
+@pytest.mark.parametrize("m", [4, 64])
+def test_fgcr_identity_preconditioner_matches_lu(m):
+    lat = gen.Lattice(4, 2, 2, 2)
+    U = gen.gauge_links(lat, 2, "near_identity", 30, eps=0.4)
+    b = gen.gaussian_spinor(lat, 2, 31)
+    Dm = dense.dense_dirac(lat, U, KAPPA)
+    xs = np.linalg.solve(Dm, b.reshape(-1)).reshape(b.shape)
+    D = lambda v: oracle.dslash(lat, U, KAPPA, v)
+    x, it, hist = ptc.fgcr(D, lambda r: r, b, tol=1e-12, m=m)
+    assert hist[-1] <= 1e-12 and rel(x, xs) < 1e-10
+    # residual norms never increase (each step is a least-squares update)
+    assert all(hist[i + 1] <= hist[i] * (1 + 1e-12) for i in range(len(hist) - 1))
+    if m == 64:
+        assert it <= b.size                     # no restart: at most n steps
+
+
+def test_fgcr_exact_inverse_converges_in_one_step():
+    lat = gen.Lattice(2, 2, 2, 4)
+    U = gen.gauge_links(lat, 2, "haar", 32)
+    b = gen.gaussian_spinor(lat, 2, 33)
+    Dm = dense.dense_dirac(lat, U, KAPPA)
+    Dinv = np.linalg.inv(Dm)
+    D = lambda v: oracle.dslash(lat, U, KAPPA, v)
+    M = lambda r: (Dinv @ r.reshape(-1)).reshape(r.shape)
+    x, it, hist = ptc.fgcr(D, M, b, tol=1e-12, m=8)
+    assert it == 1 and hist[-1] < 1e-12
+
+
+def test_fgcr_with_wilson_layer_as_preconditioner():
+    # M = 1 + kappa H (first Neumann terms of D^-1): fewer iterations than M = 1
+    lat = gen.Lattice(4, 4, 2, 2)
+    U = gen.gauge_links(lat, 3, "near_identity", 34, eps=0.3)
+    b = gen.gaussian_spinor(lat, 3, 35)
+    D = lambda v: oracle.dslash(lat, U, KAPPA, v)
+    Mneu = lambda r: r + KAPPA * oracle.hop(lat, U, r)
+    _, it0, _ = ptc.fgcr(D, lambda r: r, b, tol=1e-10, m=16)
+    _, it1, h1 = ptc.fgcr(D, Mneu, b, tol=1e-10, m=16)
+    assert h1[-1] <= 1e-10 and it1 < it0
