@@ -200,6 +200,7 @@ typedef struct {
     int32_t max_iter;
     double delta;          /* reliable update threshold (MIXED), e.g. 0.1 */
     int32_t check_every;   /* iterations between host convergence checks (>= 1) */
+    int32_t restart;       /* FGCR: Krylov vectors per cycle (e.g. 16) */
 } bsm_solver_params;
 
 typedef struct {
@@ -209,6 +210,8 @@ typedef struct {
     int32_t converged;
     double true_rel_res;
     double seconds;
+    int32_t fell_back;     /* FGCR: finished by the plain CG fallback */
+    int32_t precond_applies;
 } bsm_solver_stats;
 
 /* Solve D x = b (Section II.B: the operator is inverted by conjugate
@@ -223,6 +226,63 @@ typedef struct {
 bsm_status bsm_cg_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep,
                         const void *U_rep64, const bsm_solver_params *params, const void *b,
                         void *x, bsm_solver_stats *stats, void *stream);
+
+/* ------------------------------------------------- learned preconditioner
+ * A gauge-covariant network of parallel-transport convolution (PTC) layers:
+ *   out_i(x) = sum_j sum_p W_p^{ij} (T_p v_j)(x),  p in {stay, +mu, -mu} (9 paths)
+ *   T_{+mu} v(x) = s+ U_mu(x) v(x+mu),  T_{-mu} v(x) = s- U_mu(x-mu)^dag v(x-mu)
+ * W_p^{ij} complex 4 x 4 spin matrices, complex float [cout][cin][9][4][4].
+ * The preconditioner is M(r) = L2(L1(r)) with L1: 1 -> C channels and
+ * L2: C -> 1 (weights W1 then W2, consecutive: bsm_net_bytes).  Channel fields
+ * are consecutive F32 full internal fields.  desc: spinor F32, link F32,
+ * complex links (d_R <= 6). */
+size_t bsm_net_bytes(int32_t channels);
+bsm_status bsm_ptc_layer(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, int32_t cin,
+                         int32_t cout, const void *W, const void *in, void *out, void *stream);
+/* the adjoint layer: in has cout channels, out cin channels */
+bsm_status bsm_ptc_layer_adjoint(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, int32_t cin,
+                                 int32_t cout, const void *W, const void *in, void *out, void *stream);
+/* dW = dL/dRe W + i dL/dIm W for a layer with input v (cin channels) and
+ * output gradient G = dL/dRe out + i dL/dIm out (cout channels):
+ * dW_p^{ij}[a][b] = sum_x sum_c G_i(x)[a][c] conj((T_p v_j)(x)[b][c]).  FP64 sums. */
+bsm_status bsm_ptc_weight_grad(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, int32_t cin,
+                               int32_t cout, const void *G, const void *v, void *dW, void *stream);
+/* z = M(r) for F32 full fields r, z */
+bsm_status bsm_precond_apply(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, int32_t channels,
+                             const void *net, const void *r, void *z, void *stream);
+
+typedef struct {
+    float lr, beta1, beta2, eps;   /* Adam (e.g. 1e-3, 0.9, 0.999, 1e-8) */
+    int32_t batch;                 /* pairs per step */
+    int32_t steps;
+    uint64_t seed;                 /* batch selection (splitmix64 counter stream) */
+    int32_t step0;                 /* Adam steps already taken with adam_state (0 at first) */
+} bsm_train_params;
+/* Adam steps on loss = mean over a batch of |M(r) - e|^2 / |e|^2 with
+ * gradients from the adjoint layers and the weight-gradient kernel.
+ * r_pairs, e_pairs: n_pairs consecutive F32 full fields each.  adam_state:
+ * device, 2 * bsm_net_bytes(channels) bytes, zero before the first call.
+ * losses: host array of steps (batch loss before each update).  Synchronous. */
+bsm_status bsm_precond_train(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, int32_t channels,
+                             void *net, void *adam_state, const void *r_pairs, const void *e_pairs,
+                             int32_t n_pairs, const bsm_train_params *params, float *losses, void *stream);
+/* Training pairs from plain FP64 Schur CG on D x = b with b = D x*_s for
+ * each of n_solves solutions x*_s (F64 full fields): after k = iters[q]
+ * iterations from x_0 = 0 (q < n_snap; k = 0 gives e = x*), e = x* - x_k
+ * and r = D e, stored as F32 full fields at r_out / e_out [s * n_snap + q].
+ * U_rep64: FP64 links.  Synchronous. */
+bsm_status bsm_precond_pairs(bsm_ctx ctx, const bsm_field_desc *desc64, const void *U_rep64, double kappa,
+                             int32_t n_solves, const void *x_star, int32_t n_snap, const int32_t *iters,
+                             void *r_out, void *e_out, void *stream);
+/* Flexible GCR(params->restart) on D x = b (full lattice, FP64 vectors) with
+ * z = M(r) from the network (net nullable: M = 1), the FP64 true residual
+ * recomputed at every restart, and a fall back to plain FP64 Schur CG from
+ * the current x when a cycle reduces |r| by less than a factor 2 or meets a
+ * non-finite value.  desc/U_rep: the network's F32 operator; U_rep64: FP64
+ * links.  b, x: F64 full fields.  Synchronous. */
+bsm_status bsm_fgcr_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, const void *U_rep64,
+                          const bsm_solver_params *params, int32_t channels, const void *net, const void *b,
+                          void *x, bsm_solver_stats *stats, void *stream);
 
 /* ------------------------------------------------------- many right-hand sides
  * Block fields hold up to 16 right-hand sides together (FP32, layout private)

@@ -40,15 +40,21 @@ class FieldDesc(C.Structure):
 class SolverParams(C.Structure):
     _fields_ = [("variant", C.c_int32), ("schur", C.c_int32), ("kappa", C.c_double),
                 ("tol", C.c_double), ("max_iter", C.c_int32), ("delta", C.c_double),
-                ("check_every", C.c_int32)]
+                ("check_every", C.c_int32), ("restart", C.c_int32)]
 
 
 class SolverStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("reliable_updates", C.c_int32), ("restarts", C.c_int32),
-                ("converged", C.c_int32), ("true_rel_res", C.c_double), ("seconds", C.c_double)]
+                ("converged", C.c_int32), ("true_rel_res", C.c_double), ("seconds", C.c_double),
+                ("fell_back", C.c_int32), ("precond_applies", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TrainParams(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("batch", C.c_int32), ("steps", C.c_int32), ("seed", C.c_uint64), ("step0", C.c_int32)]
 
 
 _lib = None
@@ -86,6 +92,18 @@ _SIGS = {
                                       C.POINTER(C.c_double), _vp, C.POINTER(C.c_double), _vp, _vp, _vp]),
     "bsm_batched_solve": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.POINTER(SolverParams), C.c_int32,
                                     C.POINTER(C.c_double), _vp, _vp, C.POINTER(SolverStats), _vp]),
+    "bsm_net_bytes": (C.c_size_t, [C.c_int32]),
+    "bsm_ptc_layer": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp]),
+    "bsm_ptc_layer_adjoint": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, C.c_int32, _vp, _vp, _vp,
+                                        _vp]),
+    "bsm_ptc_weight_grad": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp]),
+    "bsm_precond_apply": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, _vp, _vp, _vp, _vp]),
+    "bsm_precond_train": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, _vp, _vp, _vp, _vp, C.c_int32,
+                                    C.POINTER(TrainParams), C.POINTER(C.c_float), _vp]),
+    "bsm_precond_pairs": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_double, C.c_int32, _vp, C.c_int32,
+                                    C.POINTER(C.c_int32), _vp, _vp, _vp]),
+    "bsm_fgcr_solve": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, _vp, C.POINTER(SolverParams), C.c_int32, _vp,
+                                 _vp, _vp, C.POINTER(SolverStats), _vp]),
     "bsm_cg_solve": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, _vp, C.POINTER(SolverParams), _vp, _vp,
                                C.POINTER(SolverStats), _vp]),
 }
@@ -290,6 +308,50 @@ class Context:
             _check(status, "bsm_cg_solve")
         return status, st.as_dict()
 
+    # ------------------------------------------------ learned preconditioner
+    def new_net(self, channels, device="cuda"):
+        import torch
+        return torch.zeros(lib().bsm_net_bytes(int(channels)) // 4, dtype=torch.float32, device=device)
+
+    def bsm_ptc_layer(self, d, U_rep, cin, cout, W, inp, out, stream=None):
+        _check(lib().bsm_ptc_layer(self.handle, C.byref(d), _ptr(U_rep), int(cin), int(cout), _ptr(W), _ptr(inp),
+                                   _ptr(out), _stream(stream)), "bsm_ptc_layer")
+
+    def bsm_ptc_layer_adjoint(self, d, U_rep, cin, cout, W, inp, out, stream=None):
+        _check(lib().bsm_ptc_layer_adjoint(self.handle, C.byref(d), _ptr(U_rep), int(cin), int(cout), _ptr(W),
+                                           _ptr(inp), _ptr(out), _stream(stream)), "bsm_ptc_layer_adjoint")
+
+    def bsm_ptc_weight_grad(self, d, U_rep, cin, cout, G, v, dW, stream=None):
+        _check(lib().bsm_ptc_weight_grad(self.handle, C.byref(d), _ptr(U_rep), int(cin), int(cout), _ptr(G),
+                                         _ptr(v), _ptr(dW), _stream(stream)), "bsm_ptc_weight_grad")
+
+    def bsm_precond_apply(self, d, U_rep, channels, net, r, z, stream=None):
+        _check(lib().bsm_precond_apply(self.handle, C.byref(d), _ptr(U_rep), int(channels), _ptr(net), _ptr(r),
+                                       _ptr(z), _stream(stream)), "bsm_precond_apply")
+
+    def bsm_precond_train(self, d, U_rep, channels, net, adam_state, r_pairs, e_pairs, n_pairs,
+                          params: TrainParams, stream=None):
+        losses = (C.c_float * max(1, params.steps))()
+        _check(lib().bsm_precond_train(self.handle, C.byref(d), _ptr(U_rep), int(channels), _ptr(net),
+                                       _ptr(adam_state), _ptr(r_pairs), _ptr(e_pairs), int(n_pairs),
+                                       C.byref(params), losses, _stream(stream)), "bsm_precond_train")
+        return list(losses)[:params.steps]
+
+    def bsm_precond_pairs(self, d64, U_rep64, kappa, n_solves, x_star, iters, r_out, e_out, stream=None):
+        it = (C.c_int32 * len(iters))(*[int(i) for i in iters])
+        _check(lib().bsm_precond_pairs(self.handle, C.byref(d64), _ptr(U_rep64), float(kappa), int(n_solves),
+                                       _ptr(x_star), len(iters), it, _ptr(r_out), _ptr(e_out), _stream(stream)),
+               "bsm_precond_pairs")
+
+    def bsm_fgcr_solve(self, d, U_rep, U_rep64, params: SolverParams, channels, net, b, x, stream=None,
+                       check=True):
+        st = SolverStats()
+        status = lib().bsm_fgcr_solve(self.handle, C.byref(d), _ptr(U_rep), _ptr(U_rep64), C.byref(params),
+                                      int(channels), _ptr(net), _ptr(b), _ptr(x), C.byref(st), _stream(stream))
+        if check and status != OK:
+            _check(status, "bsm_fgcr_solve")
+        return status, st.as_dict()
+
 
 def _darr(vals, n=None):
     if vals is None:
@@ -301,9 +363,14 @@ def _darr(vals, n=None):
 
 
 def solver_params(kappa, tol=1e-10, schur=True, variant=SOLVER_PLAIN, max_iter=100000, delta=0.1,
-                  check_every=8) -> SolverParams:
+                  check_every=8, restart=16) -> SolverParams:
     return SolverParams(variant, int(schur), float(kappa), float(tol), int(max_iter), float(delta),
-                        int(check_every))
+                        int(check_every), int(restart))
+
+
+def train_params(lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, batch=4, steps=100, seed=0, step0=0) -> TrainParams:
+    return TrainParams(float(lr), float(beta1), float(beta2), float(eps), int(batch), int(steps), int(seed),
+                       int(step0))
 
 
 def bsm_stream_copy(src, dst, nbytes=None, nontemporal=0, blocks=0, stream=None):

@@ -26,6 +26,7 @@
 
 #include "blas.h"
 #include "dispatch.h"
+#include "solver.h"
 
 namespace bsm {
 
@@ -39,24 +40,11 @@ static bool trace_enabled() {
     return on == 1;
 }
 
-struct Op {
-    bsm_ctx ctx;
-    Geom g;
-    int d;
-    bool real;
-    bool schur;
-    double kappa;
-    const void *U;
-    int sprec, lprec;
-    void *tmp;      // one parity block in sprec (Schur intermediate)
-    double *partials;
-};
-
-static size_t blk(const Op &o) { return spinor_block_bytes(o.sprec, o.d, o.g.Vh_pad); }
-static int nblk_vec(const Op &o) { return o.schur ? 1 : 2; }
+size_t blk(const Op &o) { return spinor_block_bytes(o.sprec, o.d, o.g.Vh_pad); }
+int nblk_vec(const Op &o) { return o.schur ? 1 : 2; }
 
 // y = M x or M^dag x; norm partials of y when partials != null (count in *np)
-static bsm_status op_apply(const Op &o, int dagger, const void *x, void *y, bool norm, int *np,
+bsm_status op_apply(const Op &o, int dagger, const void *x, void *y, bool norm, int *np,
                            hipStream_t st) {
     HopArgs a{};
     a.U = o.U;
@@ -101,7 +89,7 @@ static bsm_status op_apply(const Op &o, int dagger, const void *x, void *y, bool
     } while (0)
 
 // sum n partials on the device and bring the result to the host (synchronous)
-static double reduce_to_host(bsm_ctx ctx, const double *partials, int n, hipStream_t st) {
+double reduce_to_host(bsm_ctx ctx, const double *partials, int n, hipStream_t st) {
     reduce_into(partials, n, ctx->scal + S_TMP, st);
     (void)hipMemcpyAsync(ctx->host_scal + S_TMP, ctx->scal + S_TMP, sizeof(double), hipMemcpyDeviceToHost, st);
     (void)hipStreamSynchronize(st);
@@ -109,7 +97,7 @@ static double reduce_to_host(bsm_ctx ctx, const double *partials, int n, hipStre
 }
 
 // FP64: out = M^dag (bh - M x), with t as scratch (vectors of o's shape)
-static bsm_status normal_residual(const Op &o, const char *bh, const char *x, char *t, char *out,
+bsm_status normal_residual(const Op &o, const char *bh, const char *x, char *t, char *out,
                                   hipStream_t st) {
     Vec T{t, BSM_F64}, BH{(void *)bh, BSM_F64};
     TRY(op_apply(o, 0, x, t, false, nullptr, st));
@@ -120,7 +108,7 @@ static bsm_status normal_residual(const Op &o, const char *bh, const char *x, ch
 // FP64 true relative residual ||b - D x|| / ||b|| of the full system for the
 // full fields b, x (Schur: the odd sites of x are first rebuilt from x_e);
 // tfull is a full FP64 scratch field
-static bsm_status true_residual_full(const Op &o, const char *b, char *x, char *tfull, double bnorm2,
+bsm_status true_residual_full(const Op &o, const char *b, char *x, char *tfull, double bnorm2,
                                      double *res, hipStream_t st) {
     const Geom &g = o.g;
     const size_t bb64 = spinor_block_bytes(BSM_F64, o.d, g.Vh_pad);

@@ -1,0 +1,556 @@
+// Learned preconditioner: network application, training (Adam on the GPU),
+// training pairs from CG, and flexible GCR with the network and a plain-CG
+// fall back.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "ptc.h"
+#include "solver.h"
+#include "spinor_io.h"
+
+namespace bsm {
+
+static size_t layer_weights(int cin, int cout) { return (size_t)cout * cin * 9 * 16; }   // complex
+
+static bsm_status check_net_desc(bsm_ctx ctx, const bsm_field_desc *desc) {
+    if (!ctx || !desc) return fail(BSM_ERR_ARG, "null argument");
+    if (bsm_rep_dim(desc->N, desc->rep) != desc->d_R) return fail(BSM_ERR_ARG, "d_R does not match (N, rep)");
+    if (desc->prec != BSM_F32 || desc->link_prec != BSM_F32)
+        return fail(BSM_ERR_ARG, "the network runs on F32 spinors and F32 links");
+    if (desc->rep == BSM_REP_ADJ) return fail(BSM_ERR_UNSUPPORTED, "network kernels use complex links");
+    if (desc->d_R > kPtcMaxD) return fail(BSM_ERR_UNSUPPORTED, "network kernels are compiled for d_R <= 6");
+    return BSM_OK;
+}
+
+// ------------------------------------------------------ FGCR vector kernels
+// Flat loops over the complex numbers of F64 full fields (n double2).  GCR
+// keeps the directions w_j = D z_j unnormalised with nn_j = |w_j|^2, so the
+// projections use coefficients <w_j, w> / nn_j.  Orthogonalisation is
+// classical Gram-Schmidt in one fused pass (all dots, then all updates),
+// equal to modified Gram-Schmidt in exact arithmetic; the residual stays
+// exact either way because r and x are updated with the same (w, z) pair.
+constexpr int kGcrMax = 64;   // largest restart length
+constexpr int kZdotJ = 8;     // dot products per workgroup row
+constexpr int kZblocks = 1024;
+
+struct ZPtrs { const double2 *p[kGcrMax]; };
+
+__device__ inline void block_sum2(double &re, double &im, double2 *ws, int slot, double2 *dst) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        re += __shfl_xor(re, o, 64);
+        im += __shfl_xor(im, o, 64);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) ws[w * kZdotJ + slot] = make_double2(re, im);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        *dst = make_double2((ws[slot].x + ws[kZdotJ + slot].x) + (ws[2 * kZdotJ + slot].x + ws[3 * kZdotJ + slot].x),
+                            (ws[slot].y + ws[kZdotJ + slot].y) + (ws[2 * kZdotJ + slot].y + ws[3 * kZdotJ + slot].y));
+}
+
+// partials[j][block] = sum conj(W_j) w over this workgroup's elements, for
+// j in [blockIdx.y * 8, min(k, +8))
+__global__ __launch_bounds__(256) void k_zmultidot(ZPtrs W, int k, const double2 *w, size_t n, double2 *partials) {
+    const int j0 = blockIdx.y * kZdotJ;
+    double re[kZdotJ], im[kZdotJ];
+#pragma unroll
+    for (int q = 0; q < kZdotJ; q++) re[q] = im[q] = 0.0;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+        const double2 y = w[e];
+#pragma unroll
+        for (int q = 0; q < kZdotJ; q++) {
+            if (j0 + q >= k) break;
+            const double2 x = W.p[j0 + q][e];
+            re[q] += x.x * y.x + x.y * y.y;
+            im[q] += x.x * y.y - x.y * y.x;
+        }
+    }
+    __shared__ double2 ws[4 * kZdotJ];
+#pragma unroll
+    for (int q = 0; q < kZdotJ; q++) {
+        if (j0 + q >= k) break;
+        block_sum2(re[q], im[q], ws, q, &partials[(size_t)(j0 + q) * gridDim.x + blockIdx.x]);
+    }
+}
+
+// one workgroup per column j: s = sum of nb partials (fixed order);
+// mode 0: coef[j] = s / nn[j] (0 when nn[j] is 0); mode 1: out[j] = s
+__global__ __launch_bounds__(256) void k_zcols(const double2 *partials, int nb, const double *nn, double2 *coef,
+                                               int mode) {
+    const int j = blockIdx.x;
+    double re = 0, im = 0;
+    for (int i = threadIdx.x; i < nb; i += 256) {
+        re += partials[(size_t)j * nb + i].x;
+        im += partials[(size_t)j * nb + i].y;
+    }
+    __shared__ double2 ws[4 * kZdotJ];
+    __shared__ double2 s;
+    block_sum2(re, im, ws, 0, &s);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    if (mode == 0) {
+        const double d = nn[j];
+        coef[j] = d > 0 ? make_double2(s.x / d, s.y / d) : make_double2(0.0, 0.0);
+    } else {
+        coef[j] = s;
+    }
+}
+
+// w -= sum_j coef_j W_j ; z -= sum_j coef_j Z_j ; partials of |w|^2 and <w, r>
+__global__ __launch_bounds__(256) void k_zorth(ZPtrs W, ZPtrs Z, int k, const double2 *coef, double2 *w, double2 *z,
+                                               const double2 *r, size_t n, double2 *partials) {
+    __shared__ double2 cs[kGcrMax];
+    if (threadIdx.x < k) cs[threadIdx.x] = coef[threadIdx.x];
+    __syncthreads();
+    double nw = 0, dr = 0, di = 0;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+        double2 wv = w[e], zv = z[e];
+        for (int j = 0; j < k; j++) {
+            const double2 c = cs[j], a = W.p[j][e], b = Z.p[j][e];
+            wv.x -= c.x * a.x - c.y * a.y;
+            wv.y -= c.x * a.y + c.y * a.x;
+            zv.x -= c.x * b.x - c.y * b.y;
+            zv.y -= c.x * b.y + c.y * b.x;
+        }
+        if (k > 0) {
+            w[e] = wv;
+            z[e] = zv;
+        }
+        const double2 rv = r[e];
+        nw += wv.x * wv.x + wv.y * wv.y;
+        dr += wv.x * rv.x + wv.y * rv.y;
+        di += wv.x * rv.y - wv.y * rv.x;
+    }
+    __shared__ double2 ws[4 * kZdotJ];
+    double zero = 0;
+    block_sum2(nw, zero, ws, 0, &partials[blockIdx.x]);
+    block_sum2(dr, di, ws, 1, &partials[(size_t)gridDim.x + blockIdx.x]);
+}
+
+// nn[k] = sum partials[0][*]; alpha = (sum partials[1][*]) / nn[k]
+__global__ __launch_bounds__(256) void k_zalpha(const double2 *partials, int nb, double *nn, int k, double2 *alpha) {
+    double a = 0, b = 0, c = 0;
+    for (int i = threadIdx.x; i < nb; i += 256) {
+        a += partials[i].x;
+        b += partials[nb + i].x;
+        c += partials[nb + i].y;
+    }
+    __shared__ double2 ws[4 * kZdotJ];
+    __shared__ double2 s0, s1;
+    double zero = 0;
+    block_sum2(a, zero, ws, 0, &s0);
+    block_sum2(b, c, ws, 1, &s1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        nn[k] = s0.x;
+        *alpha = s0.x > 0 ? make_double2(s1.x / s0.x, s1.y / s0.x) : make_double2(0.0, 0.0);
+    }
+}
+
+// x += alpha z ; r -= alpha w ; partials of |r|^2
+__global__ __launch_bounds__(256) void k_zupdate(double2 *x, double2 *r, const double2 *z, const double2 *w, size_t n,
+                                                 const double2 *alpha, double2 *partials) {
+    const double ar = alpha->x, ai = alpha->y;
+    double rr = 0;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+        const double2 zv = z[e], wv = w[e];
+        double2 xv = x[e], rv = r[e];
+        xv.x += ar * zv.x - ai * zv.y;
+        xv.y += ar * zv.y + ai * zv.x;
+        rv.x -= ar * wv.x - ai * wv.y;
+        rv.y -= ar * wv.y + ai * wv.x;
+        x[e] = xv;
+        r[e] = rv;
+        rr += rv.x * rv.x + rv.y * rv.y;
+    }
+    __shared__ double2 ws[4 * kZdotJ];
+    double zero = 0;
+    block_sum2(rr, zero, ws, 0, &partials[blockIdx.x]);
+}
+
+// |a|^2 partials (for |b|^2 and restart residuals)
+__global__ __launch_bounds__(256) void k_znorm(const double2 *a, size_t n, double2 *partials) {
+    double s = 0;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+        const double2 v = a[e];
+        s += v.x * v.x + v.y * v.y;
+    }
+    __shared__ double2 ws[4 * kZdotJ];
+    double zero = 0;
+    block_sum2(s, zero, ws, 0, &partials[blockIdx.x]);
+}
+
+#define TRY(x)                           \
+    do {                                 \
+        bsm_status _s = (x);             \
+        if (_s != BSM_OK) return _s;     \
+    } while (0)
+
+// z = M(r) on F32 full fields; h: channels F32 full fields of scratch
+static bsm_status net_apply(bsm_ctx ctx, const bsm_field_desc *desc, const void *U, int C, const void *net,
+                            const void *r, void *h, void *z, hipStream_t st) {
+    const float2 *W1 = (const float2 *)net;
+    const float2 *W2 = W1 + layer_weights(1, C);
+    PtcArgs a{};
+    a.U = U;
+    a.W = W1; a.in = r; a.out = h; a.cin = 1; a.cout = C;
+    TRY(launch_ptc_layer(ctx->g, desc->d_R, a, st));
+    a.W = W2; a.in = h; a.out = z; a.cin = C; a.cout = 1;
+    return launch_ptc_layer(ctx->g, desc->d_R, a, st);
+}
+
+static uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+}  // namespace bsm
+
+using namespace bsm;
+
+extern "C" {
+
+size_t bsm_net_bytes(int32_t channels) {
+    if (channels < 1) return 0;
+    return (layer_weights(1, channels) + layer_weights(channels, 1)) * sizeof(float2);
+}
+
+bsm_status bsm_ptc_layer(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, int32_t cin, int32_t cout,
+                         const void *W, const void *in, void *out, void *stream) {
+    TRY(check_net_desc(ctx, desc));
+    if (!U_rep || !W || !in || !out) return fail(BSM_ERR_ARG, "null pointer");
+    if (cin < 1 || cout < 1 || cin > 64 || cout > 64) return fail(BSM_ERR_ARG, "channels must be in [1, 64]");
+    if (in == out) return fail(BSM_ERR_ARG, "in and out must differ");
+    PtcArgs a{};
+    a.U = U_rep; a.W = W; a.in = in; a.out = out; a.cin = cin; a.cout = cout;
+    return launch_ptc_layer(ctx->g, desc->d_R, a, (hipStream_t)stream);
+}
+
+bsm_status bsm_ptc_layer_adjoint(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, int32_t cin,
+                                 int32_t cout, const void *W, const void *in, void *out, void *stream) {
+    TRY(check_net_desc(ctx, desc));
+    if (!U_rep || !W || !in || !out) return fail(BSM_ERR_ARG, "null pointer");
+    if (cin < 1 || cout < 1 || cin > 64 || cout > 64) return fail(BSM_ERR_ARG, "channels must be in [1, 64]");
+    hipStream_t st = (hipStream_t)stream;
+    void *Wa = nullptr;
+    TRY(ctx_work(ctx, layer_weights(cin, cout) * sizeof(float2), &Wa));
+    TRY(launch_ptc_adjoint_weights(W, Wa, cin, cout, st));
+    PtcArgs a{};
+    a.U = U_rep; a.W = Wa; a.in = in; a.out = out; a.cin = cout; a.cout = cin;
+    return launch_ptc_layer(ctx->g, desc->d_R, a, st);
+}
+
+bsm_status bsm_ptc_weight_grad(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, int32_t cin,
+                               int32_t cout, const void *G, const void *v, void *dW, void *stream) {
+    TRY(check_net_desc(ctx, desc));
+    if (!U_rep || !G || !v || !dW) return fail(BSM_ERR_ARG, "null pointer");
+    if (cin < 1 || cout < 1 || cin > 64 || cout > 64) return fail(BSM_ERR_ARG, "channels must be in [1, 64]");
+    void *parts = nullptr;
+    TRY(ctx_work(ctx, (size_t)ptc_wgrad_blocks(ctx->g) * layer_weights(cin, cout) * sizeof(double2), &parts));
+    PtcArgs a{};
+    a.U = U_rep; a.in = v; a.G = G; a.cin = cin; a.cout = cout;
+    return launch_ptc_wgrad(ctx->g, desc->d_R, a, (double2 *)parts, (float2 *)dW, 1.0, false, (hipStream_t)stream);
+}
+
+bsm_status bsm_precond_apply(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, int32_t channels,
+                             const void *net, const void *r, void *z, void *stream) {
+    TRY(check_net_desc(ctx, desc));
+    if (!U_rep || !net || !r || !z) return fail(BSM_ERR_ARG, "null pointer");
+    if (channels < 1 || channels > 64) return fail(BSM_ERR_ARG, "channels must be in [1, 64]");
+    const size_t f32 = 2 * spinor_block_bytes(BSM_F32, desc->d_R, ctx->g.Vh_pad);
+    void *h = nullptr;
+    TRY(ctx_work(ctx, channels * f32, &h));
+    return net_apply(ctx, desc, U_rep, channels, net, r, h, z, (hipStream_t)stream);
+}
+
+bsm_status bsm_precond_train(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, int32_t channels,
+                             void *net, void *adam_state, const void *r_pairs, const void *e_pairs, int32_t n_pairs,
+                             const bsm_train_params *prm, float *losses, void *stream) {
+    TRY(check_net_desc(ctx, desc));
+    if (!U_rep || !net || !adam_state || !r_pairs || !e_pairs || !prm) return fail(BSM_ERR_ARG, "null pointer");
+    if (channels < 1 || channels > 64 || n_pairs < 1 || prm->batch < 1 || prm->steps < 0)
+        return fail(BSM_ERR_ARG, "bad channels, n_pairs, batch or steps");
+    hipStream_t st = (hipStream_t)stream;
+    const Geom &g = ctx->g;
+    const int d = desc->d_R, C = channels;
+    const size_t f32 = 2 * spinor_block_bytes(BSM_F32, d, g.Vh_pad);
+    const size_t nw1 = layer_weights(1, C), nw2 = layer_weights(C, 1), nw = nw1 + nw2;
+    const size_t parts_bytes = (size_t)ptc_wgrad_blocks(g) * std::max(nw1, nw2) * sizeof(double2);
+    // scratch: h (C fields), y, Gy, Gh (C fields), W2 adjoint, grads, partials
+    const size_t need = (2 * C + 2) * f32 + nw2 * sizeof(float2) + nw * sizeof(float2) + parts_bytes + 8 * 256;
+    void *work = nullptr;
+    TRY(ctx_work(ctx, need, &work));
+    char *w = (char *)work;
+    auto take = [&](size_t bytes) { char *r = w; w += (bytes + 255) / 256 * 256; return r; };
+    char *h = take(C * f32), *y = take(f32), *Gy = take(f32), *Gh = take(C * f32);
+    float2 *W2a = (float2 *)take(nw2 * sizeof(float2));
+    float2 *grad = (float2 *)take(nw * sizeof(float2));
+    double2 *parts = (double2 *)take(parts_bytes);
+    float2 *W1 = (float2 *)net, *W2 = W1 + nw1;
+    // |e|^2 of every pair, once
+    std::vector<double> e2(n_pairs);
+    Vec none{nullptr, BSM_F32};
+    for (int k = 0; k < n_pairs; k++) {
+        TRY(blas_dot(g, d, 2, Vec{(char *)e_pairs + k * f32, BSM_F32}, none, ctx->partials, st));
+        e2[k] = reduce_to_host(ctx, ctx->partials, blas_blocks(g, 2), st);
+        if (!(e2[k] > 0)) return fail(BSM_ERR_ARG, "a training error field is zero");
+    }
+    for (int step = 0; step < prm->steps; step++) {
+        BSM_HIP(hipMemsetAsync(grad, 0, nw * sizeof(float2), st));
+        TRY(launch_ptc_adjoint_weights(W2, W2a, C, 1, st));
+        double loss = 0;
+        for (int bidx = 0; bidx < prm->batch; bidx++) {
+            const uint64_t pick = splitmix64(prm->seed + (uint64_t)step * prm->batch + bidx) % (uint64_t)n_pairs;
+            const char *r = (const char *)r_pairs + pick * f32;
+            const char *e = (const char *)e_pairs + pick * f32;
+            TRY(net_apply(ctx, desc, U_rep, C, net, r, h, y, st));
+            // Gy = 2 (y - e) / (|e|^2 B); loss term |Gy|^2 |e|^2 B / 4
+            const double c = 2.0 / (e2[pick] * prm->batch);
+            TRY(blas_axpby(g, d, 2, Vec{Gy, BSM_F32}, c, Vec{y, BSM_F32}, -c, Vec{(void *)e, BSM_F32}, ctx->partials, st));
+            const double g2 = reduce_to_host(ctx, ctx->partials, blas_blocks(g, 2), st);
+            loss += g2 * e2[pick] * prm->batch / 4.0;
+            PtcArgs a{};
+            a.U = U_rep;
+            // dW2 += Gy conj(T h)
+            a.in = h; a.G = Gy; a.cin = C; a.cout = 1;
+            TRY(launch_ptc_wgrad(g, d, a, parts, grad + nw1, 1.0, true, st));
+            // Gh = L2^dag Gy
+            PtcArgs b{};
+            b.U = U_rep; b.W = W2a; b.in = Gy; b.out = Gh; b.cin = 1; b.cout = C;
+            TRY(launch_ptc_layer(g, d, b, st));
+            // dW1 += Gh conj(T r)
+            a.in = r; a.G = Gh; a.cin = 1; a.cout = C;
+            TRY(launch_ptc_wgrad(g, d, a, parts, grad, 1.0, true, st));
+        }
+        if (losses) losses[step] = (float)loss;
+        if (!std::isfinite(loss)) return fail(BSM_ERR_NONFINITE, "non-finite training loss");
+        TRY(launch_adam(net, grad, adam_state, (int)nw, prm->lr, prm->beta1, prm->beta2, prm->eps,
+                        prm->step0 + step + 1, st));
+    }
+    BSM_HIP(hipStreamSynchronize(st));
+    return BSM_OK;
+}
+
+bsm_status bsm_precond_pairs(bsm_ctx ctx, const bsm_field_desc *desc64, const void *U_rep64, double kappa,
+                             int32_t n_solves, const void *x_star, int32_t n_snap, const int32_t *iters,
+                             void *r_out, void *e_out, void *stream) {
+    if (!ctx || !desc64 || !U_rep64 || !x_star || !iters || !r_out || !e_out) return fail(BSM_ERR_ARG, "null pointer");
+    if (desc64->prec != BSM_F64 || desc64->link_prec != BSM_F64) return fail(BSM_ERR_ARG, "pairs need F64 desc");
+    if (n_solves < 1 || n_snap < 1) return fail(BSM_ERR_ARG, "n_solves and n_snap must be >= 1");
+    for (int q = 0; q < n_snap; q++)
+        if (iters[q] < 0) return fail(BSM_ERR_ARG, "snapshot iterations must be >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    const Geom &g = ctx->g;
+    const int d = desc64->d_R;
+    const size_t f64 = 2 * spinor_block_bytes(BSM_F64, d, g.Vh_pad);
+    const size_t f32 = 2 * spinor_block_bytes(BSM_F32, d, g.Vh_pad);
+    void *bx = nullptr;
+    // b, x_k and e in FP64 (own allocation: the solver below uses the context scratch)
+    BSM_HIP(hipMalloc(&bx, 3 * f64));
+    char *b = (char *)bx, *xk = b + f64, *e = xk + f64;
+    bsm_status status = BSM_OK;
+    for (int s = 0; s < n_solves && status == BSM_OK; s++) {
+        const char *xs = (const char *)x_star + s * f64;
+        status = bsm_dslash_apply(ctx, desc64, U_rep64, kappa, 0, xs, b, stream);
+        for (int q = 0; q < n_snap && status == BSM_OK; q++) {
+            if (iters[q] == 0) {
+                // the start of the solve: x_0 = 0, e = x*
+                if (hipMemsetAsync(xk, 0, f64, st) != hipSuccess) { status = fail(BSM_ERR_HIP, "memset"); break; }
+            } else {
+                bsm_solver_params p{};
+                p.variant = BSM_SOLVER_PLAIN; p.schur = 1; p.kappa = kappa; p.tol = 1e-30;
+                p.max_iter = iters[q]; p.check_every = 1 << 20;
+                bsm_solver_stats sst{};
+                bsm_status cs = bsm_cg_solve(ctx, desc64, U_rep64, U_rep64, &p, b, xk, &sst, stream);
+                if (cs != BSM_OK && cs != BSM_ERR_NOT_CONVERGED) { status = cs; break; }
+            }
+            // e = x* - x_k ; r = D e  (F32 copies)
+            Vec E{e, BSM_F64};
+            status = blas_axpby(g, d, 2, E, 1.0, Vec{(void *)xs, BSM_F64}, -1.0, Vec{xk, BSM_F64}, nullptr, st);
+            if (status != BSM_OK) break;
+            const size_t k = (size_t)s * n_snap + q;
+            status = blas_axpby(g, d, 2, Vec{(char *)e_out + k * f32, BSM_F32}, 1.0, E, 0.0,
+                                Vec{nullptr, BSM_F64}, nullptr, st);
+            if (status != BSM_OK) break;
+            status = bsm_dslash_apply(ctx, desc64, U_rep64, kappa, 0, e, xk, stream);
+            if (status != BSM_OK) break;
+            status = blas_axpby(g, d, 2, Vec{(char *)r_out + k * f32, BSM_F32}, 1.0, Vec{xk, BSM_F64}, 0.0,
+                                Vec{nullptr, BSM_F64}, nullptr, st);
+        }
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(bx);
+    return status;
+}
+
+bsm_status bsm_fgcr_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, const void *U_rep64,
+                          const bsm_solver_params *prm, int32_t channels, const void *net, const void *bin,
+                          void *xout, bsm_solver_stats *stats, void *stream) {
+    if (!ctx || !desc || !prm || !bin || !xout || !stats || !U_rep64) return fail(BSM_ERR_ARG, "null argument");
+    if (stats) *stats = bsm_solver_stats{};
+    if (net) {
+        TRY(check_net_desc(ctx, desc));
+        if (!U_rep) return fail(BSM_ERR_ARG, "the network needs F32 links");
+        if (channels < 1 || channels > 64) return fail(BSM_ERR_ARG, "channels must be in [1, 64]");
+    }
+    if (bsm_rep_dim(desc->N, desc->rep) != desc->d_R) return fail(BSM_ERR_ARG, "d_R does not match (N, rep)");
+    if (!(prm->kappa > 0) || !(prm->tol > 0) || prm->max_iter < 1) return fail(BSM_ERR_ARG, "kappa, tol, max_iter");
+    const int m = prm->restart > 0 ? prm->restart : 16;
+    if (m > kGcrMax) return fail(BSM_ERR_ARG, "restart must be <= 64");
+    if (bin == xout) return fail(BSM_ERR_ARG, "b and x must differ");
+    hipStream_t st = (hipStream_t)stream;
+    const Geom &g = ctx->g;
+    const int d = desc->d_R;
+    bsm_field_desc d64 = *desc;
+    d64.prec = BSM_F64;
+    d64.link_prec = BSM_F64;
+    const size_t f64 = 2 * spinor_block_bytes(BSM_F64, d, g.Vh_pad);
+    const size_t f32 = 2 * spinor_block_bytes(BSM_F32, d, g.Vh_pad);
+    const size_t n = f64 / sizeof(double2);
+    const int nb = (int)std::min<size_t>((n + 255) / 256, kZblocks);
+    auto t0 = std::chrono::steady_clock::now();
+    // own allocation: the fall back CG uses the context scratch
+    const size_t need = (2 * (size_t)m + 2) * f64 + (net ? (2 + (size_t)channels) * f32 : 0) +
+                        (size_t)kGcrMax * nb * sizeof(double2) + 4 * kGcrMax * sizeof(double2) + 16 * 256;
+    void *work = nullptr;
+    BSM_HIP(hipMalloc(&work, need));
+    char *w = (char *)work;
+    auto take = [&](size_t bytes) { char *r = w; w += (bytes + 255) / 256 * 256; return r; };
+    ZPtrs Zp{}, Wp{};
+    std::vector<char *> Z(m), Wv(m);
+    for (int k = 0; k < m; k++) {
+        Z[k] = take(f64);
+        Wv[k] = take(f64);
+        Zp.p[k] = (const double2 *)Z[k];
+        Wp.p[k] = (const double2 *)Wv[k];
+    }
+    char *r = take(f64), *t = take(f64);
+    char *r32 = net ? take(f32) : nullptr, *z32 = net ? take(f32) : nullptr;
+    char *h32 = net ? take((size_t)channels * f32) : nullptr;
+    double2 *parts = (double2 *)take((size_t)kGcrMax * nb * sizeof(double2));
+    double2 *coef = (double2 *)take(4 * kGcrMax * sizeof(double2));
+    double *nn = (double *)(coef + kGcrMax);          // kGcrMax doubles
+    double2 *alpha = coef + 2 * kGcrMax, *rr = coef + 3 * kGcrMax;
+    double2 hrr{};
+    const char *b = (const char *)bin;
+    char *x = (char *)xout;
+    hipError_t he = hipSuccess;
+    auto readback = [&](double *out) -> bsm_status {
+        BSM_HIP(hipMemcpyAsync(&hrr, rr, sizeof(double2), hipMemcpyDeviceToHost, st));
+        BSM_HIP(hipStreamSynchronize(st));
+        *out = hrr.x;
+        return BSM_OK;
+    };
+    auto norm2 = [&](const void *v, double *out) -> bsm_status {
+        k_znorm<<<nb, 256, 0, st>>>((const double2 *)v, n, parts);
+        k_zcols<<<1, 256, 0, st>>>(parts, nb, nullptr, rr, 1);
+        BSM_HIP(hipGetLastError());
+        return readback(out);
+    };
+    // r = b - D x, |r|^2
+    auto residual = [&](double *out) -> bsm_status {
+        TRY(bsm_dslash_apply(ctx, &d64, U_rep64, prm->kappa, 0, x, t, stream));
+        TRY(blas_axpby(g, d, 2, Vec{r, BSM_F64}, 1.0, Vec{(void *)b, BSM_F64}, -1.0, Vec{t, BSM_F64}, nullptr, st));
+        return norm2(r, out);
+    };
+    auto step = [&](int k) -> bsm_status {
+        // z_k = M(r)
+        if (net) {
+            TRY(blas_axpby(g, d, 2, Vec{r32, BSM_F32}, 1.0, Vec{r, BSM_F64}, 0.0, Vec{nullptr, BSM_F64}, nullptr, st));
+            TRY(net_apply(ctx, desc, U_rep, channels, net, r32, h32, z32, st));
+            TRY(blas_axpby(g, d, 2, Vec{Z[k], BSM_F64}, 1.0, Vec{z32, BSM_F32}, 0.0, Vec{nullptr, BSM_F32}, nullptr,
+                           st));
+        } else {
+            BSM_HIP(hipMemcpyAsync(Z[k], r, f64, hipMemcpyDeviceToDevice, st));
+        }
+        // w_k = D z_k, orthogonal to the earlier w_j
+        TRY(bsm_dslash_apply(ctx, &d64, U_rep64, prm->kappa, 0, Z[k], Wv[k], stream));
+        if (k > 0) {
+            k_zmultidot<<<dim3(nb, (k + kZdotJ - 1) / kZdotJ), 256, 0, st>>>(Wp, k, (const double2 *)Wv[k], n, parts);
+            k_zcols<<<k, 256, 0, st>>>(parts, nb, nn, coef, 0);
+        }
+        k_zorth<<<nb, 256, 0, st>>>(Wp, Zp, k, coef, (double2 *)Wv[k], (double2 *)Z[k], (const double2 *)r, n, parts);
+        k_zalpha<<<1, 256, 0, st>>>(parts, nb, nn, k, alpha);
+        k_zupdate<<<nb, 256, 0, st>>>((double2 *)x, (double2 *)r, (const double2 *)Z[k], (const double2 *)Wv[k], n,
+                                      alpha, parts);
+        k_zcols<<<1, 256, 0, st>>>(parts, nb, nullptr, rr, 1);
+        BSM_HIP(hipGetLastError());
+        return BSM_OK;
+    };
+
+    bsm_status status = BSM_OK;
+    double bn2 = 0, r2 = 0;
+    int it = 0, cycles = 0, applies = 0;
+    bool fallback = false;
+    he = hipMemsetAsync(work, 0, need, st);
+    if (he == hipSuccess) he = hipMemsetAsync(x, 0, f64, st);
+    if (he != hipSuccess) status = hip_check(he, "fgcr init");
+    if (status == BSM_OK) status = norm2(b, &bn2);
+    if (status == BSM_OK && !std::isfinite(bn2)) status = fail(BSM_ERR_NONFINITE, "non-finite right-hand side");
+    const double tol2 = prm->tol * prm->tol * bn2;
+    if (status == BSM_OK && bn2 > 0) status = residual(&r2);
+    while (status == BSM_OK && bn2 > 0 && it < prm->max_iter) {
+        if (!std::isfinite(r2)) { fallback = true; break; }
+        if (r2 <= tol2) break;
+        const double r2_cycle = r2;
+        for (int k = 0; k < m && it < prm->max_iter; k++) {
+            if ((status = step(k)) != BSM_OK) break;
+            if (net) applies++;
+            it++;
+            double rk = 0;
+            if ((status = readback(&rk)) != BSM_OK) break;
+            if (!std::isfinite(rk) || rk <= tol2) break;
+        }
+        if (status != BSM_OK) break;
+        cycles++;
+        if ((status = residual(&r2)) != BSM_OK) break;   // restart from the FP64 true residual
+        if (r2 <= tol2) break;
+        if (!std::isfinite(r2) || (it < prm->max_iter && r2 > 0.25 * r2_cycle)) { fallback = true; break; }
+    }
+    if (status == BSM_OK && fallback) {
+        // plain FP64 Schur CG on D e = r from the current x, then x += e
+        bsm_solver_params p = *prm;
+        p.variant = BSM_SOLVER_PLAIN;
+        p.schur = 1;
+        if (std::isfinite(r2) && r2 > 0) {
+            p.tol = prm->tol * std::sqrt(bn2 / r2);
+        } else {
+            he = hipMemsetAsync(x, 0, f64, st);
+            if (he == hipSuccess) he = hipMemcpyAsync(r, b, f64, hipMemcpyDeviceToDevice, st);
+            if (he != hipSuccess) status = hip_check(he, "fgcr fall back");
+            p.tol = prm->tol;
+        }
+        p.max_iter = std::max(1, prm->max_iter - it);
+        bsm_solver_stats cs{};
+        if (status == BSM_OK) {
+            const bsm_status s2 = bsm_cg_solve(ctx, &d64, U_rep64, U_rep64, &p, r, t, &cs, stream);
+            it += cs.iters;
+            if (s2 == BSM_OK || s2 == BSM_ERR_NOT_CONVERGED) {
+                status = blas_axpby(g, d, 2, Vec{x, BSM_F64}, 1.0, Vec{x, BSM_F64}, 1.0, Vec{t, BSM_F64}, nullptr, st);
+                if (status == BSM_OK) status = residual(&r2);
+            } else {
+                status = s2;
+            }
+        }
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(work);
+    stats->iters = it;
+    stats->restarts = cycles;
+    stats->fell_back = fallback ? 1 : 0;
+    stats->precond_applies = applies;
+    stats->true_rel_res = bn2 > 0 ? std::sqrt(r2 / bn2) : 0.0;
+    stats->converged = status == BSM_OK && stats->true_rel_res <= prm->tol;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (status != BSM_OK) return status;
+    if (!stats->converged) return fail(BSM_ERR_NOT_CONVERGED, "fgcr: max_iter reached before tol");
+    return BSM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,266 @@
+// Parallel-transport convolution (PTC) layers of the learned preconditioner.
+//
+//   out_i(x) = sum_j sum_p W_p^{ij} (T_p v_j)(x),   p in {stay, +mu, -mu}
+//   T_{+mu} v(x) = s+ U_mu(x) v(x+mu),  T_{-mu} v(x) = s- U_mu(x-mu)^dag v(x-mu)
+//
+// W_p^{ij} is a complex 4 x 4 spin matrix acting on the spin index of the
+// transported field; the links act on colour, so the layer commutes with
+// gauge transformations.  Channel fields are F32 full internal fields,
+// consecutive per channel.  Weights: complex float [cout][cin][9][4][4].
+// The adjoint layer is a PTC layer with weights (W_p^{ij})^dag at the
+// reversed path and channels swapped (T_{+mu}^dag = T_{-mu}), built by a
+// small kernel; the weight gradient is a lattice sum of outer products.
+// Arithmetic is FP32; reductions accumulate in FP64.
+#include "dispatch.h"
+#include "ptc.h"
+#include "spinor_io.h"
+
+namespace bsm {
+
+// t = (T_p v)(x) for the site (p_x, h) with coordinates c
+template <int D>
+__device__ inline void transport(const Geom &g, const char *U, size_t lblk, const char *v_full, size_t pblk,
+                                 int px, uint32_t h, const Coords &c, int path, cx<float> (&t)[4 * D]) {
+    if (path == 0) {
+        load_spinor<BSM_F32, D, float>(v_full + px * pblk, g.Vh_pad, h, t);
+        return;
+    }
+    const int mu = (path - 1) & 3;
+    const bool back = path > 4;
+    float w;
+    uint32_t hn;
+    switch (mu) {
+    case 0: hn = neighbour<0>(g, c, back, w); break;
+    case 1: hn = neighbour<1>(g, c, back, w); break;
+    case 2: hn = neighbour<2>(g, c, back, w); break;
+    default: hn = neighbour<3>(g, c, back, w); break;
+    }
+    cx<float> s[4 * D];
+    load_spinor<BSM_F32, D, float>(v_full + (1 - px) * pblk, g.Vh_pad, hn, s);
+    const char *blk = U + (size_t)((back ? 1 - px : px) * 4 + mu) * lblk;
+    const uint32_t hl = back ? hn : h;
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int i = 0; i < D; i++) t[a * D + i] = mk<float>(0.f, 0.f);
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            const cx<float> u = load_link<BSM_F32, false, float>(blk, g.Vh_pad, i * D + j, hl);
+#pragma unroll
+            for (int a = 0; a < 4; a++) {
+                if (!back) t[a * D + i] = cfma(u, s[a * D + j], t[a * D + i]);
+                else t[a * D + j] = cfma_conj(u, s[a * D + i], t[a * D + j]);
+            }
+        }
+#pragma unroll
+    for (int k = 0; k < 4 * D; k++) t[k] = w * t[k];
+}
+
+// one thread per site of both parities; blockIdx.y selects a group of CG
+// output channels
+template <int D, int CG>
+__global__ __launch_bounds__(256) void k_ptc_layer(Geom g, PtcArgs a, int nblk) {
+    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int px = lb >= (uint32_t)nblk ? 1 : 0;
+    const uint32_t h = (lb - px * nblk) * 256 + threadIdx.x;
+    if (h >= (uint32_t)g.Vh) return;
+    const int i0 = blockIdx.y * CG;
+    const size_t pblk = spinor_block_bytes(BSM_F32, D, g.Vh_pad);
+    const size_t lblk = link_block_bytes(BSM_F32, false, D, g.Vh_pad);
+    const Coords c = decode(g, h, px);
+    cx<float> acc[CG][4 * D];
+#pragma unroll
+    for (int q = 0; q < CG; q++)
+#pragma unroll
+        for (int k = 0; k < 4 * D; k++) acc[q][k] = mk<float>(0.f, 0.f);
+    const float2 *W = (const float2 *)a.W;
+    for (int j = 0; j < a.cin; j++) {
+        const char *vj = (const char *)a.in + (size_t)j * 2 * pblk;
+        for (int p = 0; p < 9; p++) {
+            cx<float> t[4 * D];
+            transport<D>(g, (const char *)a.U, lblk, vj, pblk, px, h, c, p, t);
+#pragma unroll
+            for (int q = 0; q < CG; q++) {
+                const int i = i0 + q;
+                if (i >= a.cout) break;
+                const float2 *w = W + (((size_t)i * a.cin + j) * 9 + p) * 16;
+#pragma unroll
+                for (int sa = 0; sa < 4; sa++)
+#pragma unroll
+                    for (int sb = 0; sb < 4; sb++) {
+                        const float2 wv = w[sa * 4 + sb];
+                        const cx<float> wc = mk<float>(wv.x, wv.y);
+#pragma unroll
+                        for (int cc = 0; cc < D; cc++) acc[q][sa * D + cc] = cfma(wc, t[sb * D + cc], acc[q][sa * D + cc]);
+                    }
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < CG; q++) {
+        const int i = i0 + q;
+        if (i >= a.cout) break;
+        char *oi = (char *)a.out + (size_t)i * 2 * pblk + px * pblk;
+        store_spinor<BSM_F32, D, float>(oi, g.Vh_pad, h, acc[q]);
+    }
+}
+
+// Wa[j][i][rev p] = W[i][j][p]^dag
+__global__ void k_ptc_adjoint_weights(const float2 *W, float2 *Wa, int cin, int cout) {
+    const int n = cout * cin * 9 * 16;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const int ab = e % 16, rest = e / 16;
+        const int p = rest % 9, ij = rest / 9;
+        const int j = ij % cin, i = ij / cin;
+        const int sa = ab / 4, sb = ab % 4;
+        const int pr = p == 0 ? 0 : (p <= 4 ? p + 4 : p - 4);
+        const float2 w = W[(((size_t)i * cin + j) * 9 + p) * 16 + sa * 4 + sb];
+        Wa[(((size_t)j * cout + i) * 9 + pr) * 16 + sb * 4 + sa] = make_float2(w.x, -w.y);
+    }
+}
+
+// dW partials: grid.x over sites (both parities), grid.y = cin * 9 (j, p).
+// Each thread forms t = T_p v_j at its site and, for every output channel i,
+// the 16 spin-matrix entries sum_c G_i[a][c] conj(t[b][c]); the workgroup
+// sums them (FP64) into partials[(block * cout + i) * cin * 9 + j * 9 + p][16].
+template <int D>
+__global__ __launch_bounds__(256) void k_ptc_wgrad(Geom g, PtcArgs a, int nblk, double2 *partials) {
+    const uint32_t lb = blockIdx.x;
+    const int px = lb >= (uint32_t)nblk ? 1 : 0;
+    const uint32_t h = (lb - px * nblk) * 256 + threadIdx.x;
+    const int j = blockIdx.y / 9, p = blockIdx.y % 9;
+    const bool active = h < (uint32_t)g.Vh;
+    const size_t pblk = spinor_block_bytes(BSM_F32, D, g.Vh_pad);
+    const size_t lblk = link_block_bytes(BSM_F32, false, D, g.Vh_pad);
+    cx<float> t[4 * D];
+    if (active) {
+        const Coords c = decode(g, h, px);
+        transport<D>(g, (const char *)a.U, lblk, (const char *)a.in + (size_t)j * 2 * pblk, pblk, px, h, c, p, t);
+    }
+    __shared__ double2 red[4][16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int i = 0; i < a.cout; i++) {
+        cx<float> G[4 * D];
+        if (active) load_spinor<BSM_F32, D, float>((const char *)a.G + (size_t)i * 2 * pblk + px * pblk, g.Vh_pad, h, G);
+        for (int e = 0; e < 16; e++) {
+            const int sa = e / 4, sb = e % 4;
+            double re = 0, im = 0;
+            if (active) {
+                cx<float> s = mk<float>(0.f, 0.f);
+#pragma unroll
+                for (int cc = 0; cc < D; cc++) s = cfma_conj(t[sb * D + cc], G[sa * D + cc], s);
+                re = s.re;
+                im = s.im;
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                re += __shfl_xor(re, o, 64);
+                im += __shfl_xor(im, o, 64);
+            }
+            if (lane == 0) red[wave][e] = make_double2(re, im);
+        }
+        __syncthreads();
+        if (threadIdx.x < 16) {
+            double2 s0 = red[0][threadIdx.x], s1 = red[1][threadIdx.x], s2 = red[2][threadIdx.x],
+                    s3 = red[3][threadIdx.x];
+            partials[(((size_t)lb * a.cout + i) * a.cin * 9 + j * 9 + p) * 16 + threadIdx.x] =
+                make_double2((s0.x + s1.x) + (s2.x + s3.x), (s0.y + s1.y) + (s2.y + s3.y));
+        }
+        __syncthreads();
+    }
+}
+
+// dW[e] = sum over workgroups (fixed order), e over cout * cin * 9 * 16
+__global__ void k_ptc_wgrad_reduce(const double2 *partials, int nblocks, int nw, float2 *dW, double scale,
+                                   int accumulate) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nw; e += gridDim.x * blockDim.x) {
+        double re = 0, im = 0;
+        for (int b = 0; b < nblocks; b++) {
+            const double2 v = partials[(size_t)b * nw + e];
+            re += v.x;
+            im += v.y;
+        }
+        float2 o = make_float2((float)(scale * re), (float)(scale * im));
+        if (accumulate) {
+            o.x += dW[e].x;
+            o.y += dW[e].y;
+        }
+        dW[e] = o;
+    }
+}
+
+// Adam on the real and imaginary parts (Kingma & Ba 2014)
+__global__ void k_adam(float2 *w, const float2 *g, float4 *mv, int n, float lr, float b1, float b2, float eps,
+                       int t) {
+    const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        float4 s = mv[e];   // m.re, m.im, v.re, v.im
+        const float2 gv = g[e];
+        s.x = b1 * s.x + (1.f - b1) * gv.x;
+        s.y = b1 * s.y + (1.f - b1) * gv.y;
+        s.z = b2 * s.z + (1.f - b2) * gv.x * gv.x;
+        s.w = b2 * s.w + (1.f - b2) * gv.y * gv.y;
+        mv[e] = s;
+        float2 wv = w[e];
+        wv.x -= lr * (s.x / c1) / (sqrtf(s.z / c2) + eps);
+        wv.y -= lr * (s.y / c1) / (sqrtf(s.w / c2) + eps);
+        w[e] = wv;
+    }
+}
+
+// ------------------------------------------------------------- launchers
+template <int D>
+struct PtcByD {
+    static bsm_status run(const Geom &g, const PtcArgs &a, int mode, double2 *partials, hipStream_t st) {
+        if constexpr (D > kPtcMaxD) {
+            return fail(BSM_ERR_UNSUPPORTED, "PTC layers are compiled for d_R <= 6");
+        } else {
+            const int nblk = (g.Vh + 255) / 256;
+            if (mode == 0) {
+                constexpr int CG = 4;
+                dim3 grid(2 * nblk, (a.cout + CG - 1) / CG);
+                k_ptc_layer<D, CG><<<grid, 256, 0, st>>>(g, a, nblk);
+            } else {
+                dim3 grid(2 * nblk, a.cin * 9);
+                k_ptc_wgrad<D><<<grid, 256, 0, st>>>(g, a, nblk, partials);
+            }
+            BSM_HIP(hipGetLastError());
+            return BSM_OK;
+        }
+    }
+};
+
+bsm_status launch_ptc_layer(const Geom &g, int d, const PtcArgs &a, hipStream_t st) {
+    return dispatch_d<PtcByD>(d, g, a, 0, (double2 *)nullptr, st);
+}
+
+int ptc_wgrad_blocks(const Geom &g) { return 2 * ((g.Vh + 255) / 256); }
+
+bsm_status launch_ptc_wgrad(const Geom &g, int d, const PtcArgs &a, double2 *partials, float2 *dW, double scale,
+                            bool accumulate, hipStream_t st) {
+    bsm_status s = dispatch_d<PtcByD>(d, g, a, 1, partials, st);
+    if (s != BSM_OK) return s;
+    const int nw = a.cout * a.cin * 9 * 16;
+    k_ptc_wgrad_reduce<<<(nw + 255) / 256, 256, 0, st>>>(partials, ptc_wgrad_blocks(g), nw, dW, scale,
+                                                          accumulate ? 1 : 0);
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
+bsm_status launch_ptc_adjoint_weights(const void *W, void *Wa, int cin, int cout, hipStream_t st) {
+    const int n = cout * cin * 9 * 16;
+    k_ptc_adjoint_weights<<<(n + 255) / 256, 256, 0, st>>>((const float2 *)W, (float2 *)Wa, cin, cout);
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
+bsm_status launch_adam(void *w, const void *g, void *mv, int n, float lr, float b1, float b2, float eps, int t,
+                       hipStream_t st) {
+    k_adam<<<(n + 255) / 256, 256, 0, st>>>((float2 *)w, (const float2 *)g, (float4 *)mv, n, lr, b1, b2, eps, t);
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
+}  // namespace bsm
