@@ -1,22 +1,35 @@
 """Benchmark: Wilson-Dirac even-odd hop bandwidth and CG time-to-solution.
 
-Workload (one GPU): 32^3 x 64 lattice, SU(3) fundamental fermions, links
-exp(i 0.3 H) with H Gaussian traceless Hermitian, antiperiodic time,
+Headline workload (one GPU): 32^3 x 64 lattice, SU(3) fundamental fermions,
+links exp(i 0.3 H) with H Gaussian traceless Hermitian, antiperiodic time,
 kappa = 0.13, Gaussian source.  A timed step is one application of the
 even-odd hopping block H_{p,1-p} in FP32 (the Dphi kernel that every solve
 repeats), alternating the output parity.  value = algorithmic bytes of one
-hop (all 4V links once, the input parity field once, the output once) /
-mean step time.  The run also reports the FP64 hop, CG time-to-solution at a
-1e-10 FP64 true residual (plain FP64 Schur CG and reliable-update mixed
-precision), and the FP64 CPU oracle's hop rate on the host cores.
+hop (8 links per output site, the input parity field once, the output once)
+/ mean step time, from HIP events on the stream the kernel runs on.
 
-  python bench.py [--steps K] [--warmup W] [--no-cg] [--no-cpu]
+The same run reports time-to-solution at a 1e-10 FP64 true relative residual
+against plain FP64 Schur CG on the same GPU for
+  * the headline lattice: reliable-update CG with FP32 and FP16+scale inner
+    precision;
+  * 32^3 x 64 SU(3) two-index symmetric (d_R = 6), kappa 0.125: reliable-
+    update CG with FP16+scale spinors (FP32 links, and FP16 links);
+  * 24^3 x 48 SU(4) adjoint (d_R = 15), 16 right-hand sides with kappa in
+    [0.10, 0.125]: the batched matrix-core solver vs 16 sequential solves;
+  * 16^3 x 32 SU(3) fundamental, links exp(i 0.5 H), kappa 0.1335: FGCR with
+    the trained parallel-transport network vs plain CG and vs GCR without
+    the network (training time reported separately);
+and the FP64 CPU oracle's hop rate on the host cores.
+
+  python bench.py [--steps K] [--warmup W] [--sections hop,cg,cfg3,cfg4,cfg5,cpu]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -26,6 +39,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+ALL_SECTIONS = ("hop", "cg", "cfg3", "cfg4", "cfg5", "cpu")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hop_f32_32x32x32x64_su3_traffic.md")
 
 
 def log(msg):
@@ -46,6 +61,31 @@ def hop_flops(d, real, n_out_sites):
     return ((64 if real else 128) * d * d + 56 * d) * n_out_sites
 
 
+def hop_source_hash():
+    """Hash of the sources that define the FP32 hop kernel: counter data taken
+    for another version of them is not reported."""
+    h = hashlib.sha256()
+    for f in ("hop.h", "bsm_internal.h", "spinor_io.h"):
+        with open(os.path.join(ROOT, "paper_1401_3733_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per FP32 hop launch from the committed counter summary, or
+    None when it is missing or was taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None, "no counter summary"
+    txt = open(TRAFFIC_SUMMARY).read()
+    m = re.search(r"source_hash:\s*(\w+)", txt)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not b:
+        return None, "summary without source_hash / hbm_bytes_per_launch"
+    if m.group(1) != hop_source_hash():
+        return None, "kernel sources changed since the counters were taken"
+    return float(b.group(1)), "rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated"
+
+
 def time_hops(ctx, desc, U, A, B, steps, warmup):
     import torch
     nb = ctx.spinor_bytes(desc, 1, 1)
@@ -58,13 +98,269 @@ def time_hops(ctx, desc, U, A, B, steps, warmup):
     for i in range(warmup):
         step(i)
     torch.cuda.synchronize()
+    st = torch.cuda.current_stream()   # the stream the library launches on
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
+    e0.record(st)
     for i in range(steps):
         step(i)
-    e1.record()
+    e1.record(st)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps  # ms
+
+
+def solve_row(status, st, base=None):
+    row = dict(status=status, seconds=round(st["seconds"], 4), iters=st["iters"],
+               true_rel_res=st["true_rel_res"], reliable_updates=st["reliable_updates"],
+               restarts=st["restarts"])
+    if base:
+        row["speedup_vs_plain_f64"] = round(base / st["seconds"], 3) if st["seconds"] > 0 else None
+    return row
+
+
+def rel_diff(ctx, d64, x, y):
+    import torch
+    t = torch.empty_like(x)
+    ctx.bsm_vec_axpby(d64, 2, 1.0, x, -1.0, y, t)
+    return float(np.sqrt(ctx.bsm_vec_dot(d64, 2, t) / ctx.bsm_vec_dot(d64, 2, y)))
+
+
+# --------------------------------------------------------------- sections
+def bench_hop(ctx, lat, Uf_dev, psi_dev, args, bsm):
+    import torch
+    res = {}
+    Vh = lat.V // 2
+    for prec in (("f32",) if args.only_f32 else ("f32", "f64")):
+        d = bsm.desc(3, "fund", prec)
+        U = ctx.new_gauge(d)
+        ctx.bsm_gauge_represent(d, Uf_dev, U)
+        A, B = ctx.new_spinor(d), ctx.new_spinor(d)
+        ctx.bsm_pack_spinor(d, psi_dev, A)
+        log(f"autotune {prec} hop ...")
+        ctx.bsm_autotune(d, U)
+        plan = ctx.bsm_get_hop_plan(d)
+        steps = args.steps if prec == "f32" else max(10, args.steps // 4)
+        log(f"timing {prec} even-odd hop: {steps} steps, plan {plan}")
+        ms = time_hops(ctx, d, U, A, B, steps, args.warmup)
+        nbytes = hop_bytes(3, False, prec, prec, Vh)
+        res[prec] = dict(ms=ms, gbs=nbytes / ms / 1e6, tflops=hop_flops(3, False, Vh) / ms / 1e9,
+                         bytes=nbytes, plan=plan, steps=steps)
+        log(f"  {prec}: {ms * 1e3:.1f} us/hop, {res[prec]['gbs']:.0f} GB/s")
+        del U, A, B
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_cg_cfg2(ctx, lat, Uf_dev, psi_dev, kappa, bsm):
+    import torch
+    cg = {}
+    d64 = bsm.desc(3, "fund", "f64")
+    U64 = ctx.new_gauge(d64)
+    ctx.bsm_gauge_represent(d64, Uf_dev, U64)
+    b = ctx.new_spinor(d64)
+    ctx.bsm_pack_spinor(d64, psi_dev, b)
+    x64 = ctx.new_spinor(d64)
+    x = ctx.new_spinor(d64)
+    base = None
+    for name, prec, lprec, variant in (("plain_f64", "f64", "f64", bsm.SOLVER_PLAIN),
+                                       ("mixed_f32", "f32", "f32", bsm.SOLVER_MIXED),
+                                       ("mixed_f16s", "f16s", "f32", bsm.SOLVER_MIXED)):
+        dl = bsm.desc(3, "fund", prec, lprec)
+        Ul = U64 if prec == "f64" else ctx.new_gauge(dl)
+        if prec != "f64":
+            ctx.bsm_gauge_represent(dl, Uf_dev, Ul)
+        prm = bsm.solver_params(kappa, 1e-10, schur=True, variant=variant)
+        log(f"CG 32^3x64 SU(3) {name} ...")
+        out = x64 if name == "plain_f64" else x
+        status, st = ctx.bsm_cg_solve(dl, Ul, U64, prm, b, out, check=False)
+        cg[name] = solve_row(status, st, base)
+        if name == "plain_f64":
+            base = st["seconds"]
+        else:
+            cg[name]["x_rel_diff_vs_plain"] = rel_diff(ctx, d64, x, x64)
+        log(f"  {cg[name]}")
+    del U64, b, x, x64
+    torch.cuda.empty_cache()
+    return cg
+
+
+def bench_cfg3(bsm, gen):
+    """Mixed-precision reliable-update CG, 32^3 x 64 SU(3) two-index symmetric."""
+    import torch
+    c = gen.CONFIGS[3]
+    lat = gen.config_lattice(3)
+    log("cfg3: generating 32^3x64 SU(3) links and source ...")
+    Uf = bsm.to_device_c128(gen.config_links(3, lat))
+    ctx = bsm.Context(lat.dims, lat.bc)
+    d64 = bsm.desc(3, "sym", "f64")
+    src = bsm.to_device_c128(gen.config_source(3, d64.d_R, lat))
+    U64 = ctx.new_gauge(d64)
+    ctx.bsm_gauge_represent(d64, Uf, U64)
+    b = ctx.new_spinor(d64)
+    ctx.bsm_pack_spinor(d64, src, b)
+    del src
+    x64, x = ctx.new_spinor(d64), ctx.new_spinor(d64)
+    out = {"workload": "32^3x64 SU(3) 2S (d_R=6), exp(0.3iH) links, kappa 0.125, Schur CG to 1e-10"}
+    base = None
+    for name, prec, lprec, variant in (("plain_f64", "f64", "f64", bsm.SOLVER_PLAIN),
+                                       ("mixed_f16s", "f16s", "f32", bsm.SOLVER_MIXED),
+                                       ("mixed_f16s_f16links", "f16s", "f16s", bsm.SOLVER_MIXED)):
+        dl = bsm.desc(3, "sym", prec, lprec)
+        Ul = U64 if prec == "f64" else ctx.new_gauge(dl)
+        if prec != "f64":
+            ctx.bsm_gauge_represent(dl, Uf, Ul)
+        prm = bsm.solver_params(c["kappa"], 1e-10, schur=True, variant=variant)
+        log(f"cfg3 {name} ...")
+        status, st = ctx.bsm_cg_solve(dl, Ul, U64, prm, b, x64 if base is None else x, check=False)
+        out[name] = solve_row(status, st, base)
+        if base is None:
+            base = st["seconds"]
+        else:
+            out[name]["x_rel_diff_vs_plain"] = rel_diff(ctx, d64, x, x64)
+        log(f"  {out[name]}")
+        if prec != "f64":
+            del Ul
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_cfg4(bsm, gen):
+    """16 right-hand sides, 24^3 x 48 SU(4) adjoint: batched vs sequential."""
+    import torch
+    c = gen.CONFIGS[4]
+    lat = gen.config_lattice(4)
+    log("cfg4: generating 24^3x48 SU(4) links and 16 sources ...")
+    Uf = bsm.to_device_c128(gen.config_links(4, lat))
+    ctx = bsm.Context(lat.dims, lat.bc)
+    d64 = bsm.desc(4, "adj", "f64")
+    U = ctx.new_gauge(d64)
+    ctx.bsm_gauge_represent(d64, Uf, U)
+    del Uf
+    kappas = [float(k) for k in c["kappa"]]
+    n = len(kappas)
+    fb = ctx.spinor_bytes(d64, 2, 1)
+    b = ctx.new_spinor(d64, 2, n)
+    for r in range(n):   # one Philox stream per right-hand side
+        src = gen.gaussian_spinor(lat, d64.d_R, gen.SEED_SOURCE + 4 + 100 * r)
+        ctx.bsm_pack_spinor(d64, bsm.to_device_c128(src), b[r * fb:(r + 1) * fb])
+    torch.cuda.synchronize()
+    xb = torch.zeros_like(b)
+    xs = torch.zeros_like(b)
+    prm = bsm.solver_params(kappas[0], 1e-10, schur=True, max_iter=5000)
+    log("cfg4 batched (warm-up call: graph capture, buffers) ...")
+    ctx.bsm_batched_solve(d64, U, prm, kappas, b, xb, check=False)
+    log("cfg4 batched ...")
+    st, stats = ctx.bsm_batched_solve(d64, U, prm, kappas, b, xb, check=False)
+    tb = stats[0]["seconds"]
+    log(f"  {tb:.3f} s, iters {[s['iters'] for s in stats]}")
+    tseq, its, worst = 0.0, [], 0.0
+    log("cfg4 sequential plain FP64 ...")
+    for r in range(n):
+        p1 = bsm.solver_params(kappas[r], 1e-10, schur=True)
+        sl = slice(r * fb, (r + 1) * fb)
+        s1, st1 = ctx.bsm_cg_solve(d64, U, U, p1, b[sl], xs[sl], check=False)
+        tseq += st1["seconds"]
+        its.append(st1["iters"])
+        worst = max(worst, rel_diff(ctx, d64, xb[sl], xs[sl]))
+    log(f"  {tseq:.3f} s, iters {its}")
+    out = {"workload": "24^3x48 SU(4) adjoint (d_R=15, real links), Haar links, 16 RHS, "
+                       "kappa linspace(0.10, 0.125, 16), Schur CG to 1e-10 each",
+           "kappas": kappas,
+           "batched": dict(status=st, seconds=round(tb, 4), iters=[s["iters"] for s in stats],
+                           max_true_rel_res=max(s["true_rel_res"] for s in stats),
+                           reliable_updates=[s["reliable_updates"] for s in stats]),
+           "sequential_plain_f64": dict(seconds=round(tseq, 4), iters=its),
+           "speedup_vs_plain_f64": round(tseq / tb, 3) if tb > 0 else None,
+           "max_x_rel_diff_vs_plain": worst}
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_cfg5(bsm, gen, train_steps=300, n_pairs=32, channels=8):
+    """FGCR with the trained PTC network, 16^3 x 32 SU(3), kappa 0.1335."""
+    import torch
+    c = gen.CONFIGS[5]
+    lat = gen.config_lattice(5)
+    kappa = c["kappa"]
+    log("cfg5: generating 16^3x32 SU(3) links, sources and training solutions ...")
+    Uf = bsm.to_device_c128(gen.config_links(5, lat))
+    ctx = bsm.Context(lat.dims, lat.bc)
+    d64 = bsm.desc(3, "fund", "f64")
+    d32 = bsm.desc(3, "fund", "f32")
+    U64, U32 = ctx.new_gauge(d64), ctx.new_gauge(d32)
+    ctx.bsm_gauge_represent(d64, Uf, U64)
+    ctx.bsm_gauge_represent(d32, Uf, U32)
+    # training solutions x* (Gaussian, own seeds) and the evaluation source
+    xs = ctx.new_spinor(d64, 2, n_pairs)
+    xs_c = np.stack([gen.gaussian_spinor(lat, 3, gen.SEED_TRAIN + 5 + 1000 * s) for s in range(n_pairs)])
+    ctx.bsm_pack_spinor(d64, bsm.to_device_c128(xs_c), xs, n_pairs)
+    del xs_c
+    b = ctx.new_spinor(d64)
+    ctx.bsm_pack_spinor(d64, bsm.to_device_c128(gen.config_source(5, 3, lat)), b)
+    f32 = ctx.spinor_bytes(d32, 2, 1)
+    r_pairs = torch.zeros(n_pairs * f32 // 4, dtype=torch.float32, device="cuda")
+    e_pairs = torch.zeros_like(r_pairs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.bsm_precond_pairs(d64, U64, kappa, n_pairs, xs, [0], r_pairs, e_pairs)
+    t_pairs = time.perf_counter() - t0
+    W1, W2 = _init_weights(channels, gen.SEED_NET + 5)
+    net = torch.cat([torch.from_numpy(W1.astype(np.complex64).ravel()),
+                     torch.from_numpy(W2.astype(np.complex64).ravel())]).cuda()
+    adam = torch.zeros(4 * net.numel(), dtype=torch.float32, device="cuda")
+    log(f"cfg5 training {train_steps} Adam steps on {n_pairs} pairs ...")
+    t0 = time.perf_counter()
+    losses = ctx.bsm_precond_train(d32, U32, channels, net, adam, r_pairs, e_pairs, n_pairs,
+                                   bsm.train_params(lr=5e-3, batch=4, steps=train_steps, seed=gen.SEED_TRAIN + 5))
+    t_train = time.perf_counter() - t0
+    log(f"  loss {losses[0]:.4f} -> {np.mean(losses[-20:]):.4f} in {t_train:.2f} s")
+    x = ctx.new_spinor(d64)
+    x0 = ctx.new_spinor(d64)
+    rows = {}
+    log("cfg5 plain FP64 Schur CG ...")
+    s, st = ctx.bsm_cg_solve(d64, U64, U64, bsm.solver_params(kappa, 1e-10, schur=True), b, x0, check=False)
+    base = st["seconds"]
+    rows["plain_f64"] = solve_row(s, st)
+    log(f"  {rows['plain_f64']}")
+    log("cfg5 mixed FP32 CG ...")
+    s, st = ctx.bsm_cg_solve(d32, U32, U64, bsm.solver_params(kappa, 1e-10, schur=True, variant=bsm.SOLVER_MIXED),
+                             b, x, check=False)
+    rows["mixed_f32"] = solve_row(s, st, base)
+    for name, use_net in (("gcr_no_net", False), ("fgcr_net", True)):
+        log(f"cfg5 {name} ...")
+        prm = bsm.solver_params(kappa, 1e-10, max_iter=20000, restart=16)
+        s, st = ctx.bsm_fgcr_solve(d32, U32, U64, prm, channels, net if use_net else None, b, x, check=False)
+        rows[name] = solve_row(s, st, base)
+        rows[name].update(fell_back=st["fell_back"], precond_applies=st["precond_applies"],
+                          x_rel_diff_vs_plain=rel_diff(ctx, d64, x, x0))
+        log(f"  {rows[name]}")
+    gain = base - rows["fgcr_net"]["seconds"]
+    out = {"workload": "16^3x32 SU(3) fund, exp(0.5iH) links, kappa 0.1335, 1e-10 true residual",
+           "net": f"2 PTC layers 1->{channels}->1, 9 paths, FP32",
+           "training": dict(pairs=n_pairs, snapshot_iters=[0], steps=train_steps, batch=4, lr=5e-3,
+                            seconds=round(t_train, 3), pairs_seconds=round(t_pairs, 3),
+                            loss_first=losses[0], loss_last20=float(np.mean(losses[-20:]))),
+           "solves": rows,
+           "break_even_solves": (round(t_train / gain, 1) if gain > 0 else None)}
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def _init_weights(channels, seed):
+    """Stay path ~ identity / sqrt(C), hops ~ N(0, 1e-2) complex (Philox)."""
+    g = np.random.Generator(np.random.Philox(seed))
+
+    def cg(shape, s):
+        z = g.standard_normal(shape + (2,)) * s
+        return z[..., 0] + 1j * z[..., 1]
+
+    W1 = cg((channels, 1, 9, 4, 4), 1e-2)
+    W2 = cg((1, channels, 9, 4, 4), 1e-2)
+    W1[:, 0, 0] += np.eye(4) / np.sqrt(channels)
+    W2[0, :, 0] += np.eye(4) / np.sqrt(channels)
+    return W1, W2
 
 
 def cpu_baseline(lat, Uf, psi, bytes_per_hop, min_seconds=10.0):
@@ -93,25 +389,30 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--sections", type=str, default=",".join(ALL_SECTIONS))
+    ap.add_argument("--no-cg", action="store_true", help="skip every solve section")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--dims", type=str, default="64,32,32,32", help="T,LX,LY,LZ")
+    ap.add_argument("--dims", type=str, default="64,32,32,32", help="T,LX,LY,LZ of the hop workload")
     ap.add_argument("--only-f32", action="store_true", help="skip the FP64 hop timing")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run N plain 1 GiB device copies (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: multi-GPU runs are not part of this build "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: multi-GPU runs are not part of this build; "
+              "how the path would shard is described in the design notes", file=sys.stderr)
         sys.exit(2)
+    sections = set(s for s in args.sections.split(",") if s)
+    if args.no_cg:
+        sections -= {"cg", "cfg3", "cfg4", "cfg5"}
+    if args.no_cpu:
+        sections.discard("cpu")
+    sections.add("hop")
 
     import torch
     from paper_1401_3733_amd import bsm
     from paper_1401_3733_amd import inputs as gen
 
-    if not os.path.exists(bsm.LIB_PATH):
-        from paper_1401_3733_amd import build as _b
-        _b.build()
+    bsm.lib()   # raises if the HIP library is not built
     torch.cuda.set_device(0)
     dims = tuple(int(v) for v in args.dims.split(","))
     lat = gen.Lattice(*dims, bc=(-1, 1, 1, 1))
@@ -124,8 +425,6 @@ def main():
     ctx = bsm.Context(lat.dims, lat.bc)
     Uf_dev = bsm.to_device_c128(Uf)
     psi_dev = bsm.to_device_c128(psi)
-    res = {}
-    Vh = lat.V // 2
     if args.copy_calib:
         src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -135,64 +434,33 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration: {args.copy_calib} copies of 1 GiB")
         del src, dst
-    for prec in (("f32",) if args.only_f32 else ("f32", "f64")):
-        d = bsm.desc(3, "fund", prec)
-        U = ctx.new_gauge(d)
-        ctx.bsm_gauge_represent(d, Uf_dev, U)
-        A, B = ctx.new_spinor(d), ctx.new_spinor(d)
-        ctx.bsm_pack_spinor(d, psi_dev, A)
-        steps = args.steps if prec == "f32" else max(10, args.steps // 4)
-        log(f"timing {prec} even-odd hop: {steps} steps")
-        ms = time_hops(ctx, d, U, A, B, steps, args.warmup)
-        nbytes = hop_bytes(3, False, prec, prec, Vh)
-        res[prec] = dict(ms=ms, gbs=nbytes / ms / 1e6, tflops=hop_flops(3, False, Vh) / ms / 1e9,
-                         bytes=nbytes)
-        log(f"  {prec}: {ms * 1e3:.1f} us/hop, {res[prec]['gbs']:.0f} GB/s")
-        del U, A, B
+    res = bench_hop(ctx, lat, Uf_dev, psi_dev, args, bsm)
+    cg = bench_cg_cfg2(ctx, lat, Uf_dev, psi_dev, kappa, bsm) if "cg" in sections else None
+    del Uf_dev, psi_dev
+    ctx.close()
     torch.cuda.empty_cache()
-
-    cg = None
-    if not args.no_cg:
-        cg = {}
-        d64 = bsm.desc(3, "fund", "f64")
-        U64 = ctx.new_gauge(d64)
-        ctx.bsm_gauge_represent(d64, Uf_dev, U64)
-        b = ctx.new_spinor(d64)
-        ctx.bsm_pack_spinor(d64, psi_dev, b)
-        x = ctx.new_spinor(d64)
-        for name, prec, lprec, variant in (("plain_f64", "f64", "f64", bsm.SOLVER_PLAIN),
-                                           ("mixed_f32", "f32", "f32", bsm.SOLVER_MIXED),
-                                           ("mixed_f16s", "f16s", "f32", bsm.SOLVER_MIXED)):
-            dl = bsm.desc(3, "fund", prec, lprec)
-            Ul = U64 if prec == "f64" else ctx.new_gauge(dl)
-            if prec != "f64":
-                ctx.bsm_gauge_represent(dl, Uf_dev, Ul)
-            prm = bsm.solver_params(kappa, 1e-10, schur=True, variant=variant)
-            log(f"CG {name} ...")
-            status, st = ctx.bsm_cg_solve(dl, Ul, U64, prm, b, x, check=False)
-            cg[name] = dict(status=status, seconds=st["seconds"], iters=st["iters"],
-                            true_rel_res=st["true_rel_res"], reliable_updates=st["reliable_updates"],
-                            restarts=st["restarts"])
-            log(f"  {cg[name]}")
-        base = cg["plain_f64"]["seconds"]
-        for k in cg:
-            cg[k]["speedup_vs_plain_f64"] = base / cg[k]["seconds"] if cg[k]["seconds"] > 0 else None
-        del U64, b, x
-        torch.cuda.empty_cache()
+    forms = {}
+    if "cfg3" in sections:
+        forms["mixed_precision"] = bench_cfg3(bsm, gen)
+    if "cfg4" in sections:
+        forms["batched"] = bench_cfg4(bsm, gen)
+    if "cfg5" in sections:
+        forms["learned_preconditioner"] = bench_cfg5(bsm, gen)
 
     cpu = None
-    if not args.no_cpu:
+    if "cpu" in sections:
         log("CPU oracle baseline ...")
         cpu = cpu_baseline(lat, Uf, psi, res["f32"]["bytes"])
         log(f"  {cpu['value']:.2f} GB/s on {cpu['cores']} threads")
 
     r32 = res["f32"]
+    traffic, traffic_note = measured_traffic()
     out = {
         "metric": "Dslash GB/s (% HBM roofline); CG time-to-solution at 1e-10 vs plain FP64",
         "value": round(r32["gbs"], 1),
         "unit": "GB/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": r32["steps"],
         "warmup": args.warmup,
         "ms_per_step": r32["ms"],
         "higher_is_better": True,
@@ -200,16 +468,19 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"even-odd Wilson hop, {lat.dims[1]}^3x{lat.dims[0]} SU(3) fundamental, "
-                               f"exp(0.3iH) links, antiperiodic time, kappa {kappa}",
-                   "lattice": list(lat.dims), "d_R": 3, "rep": "fund", "step": "one FP32 even-odd hop"},
+        "config": {"workload": f"even-odd Wilson hop, {lat.dims[1]}x{lat.dims[2]}x{lat.dims[3]}x{lat.dims[0]} "
+                               f"SU(3) fundamental, exp(0.3iH) links, antiperiodic time, kappa {kappa}",
+                   "lattice": list(lat.dims), "d_R": 3, "rep": "fund", "step": "one FP32 even-odd hop",
+                   "hop_plan": r32["plan"]},
         "roofline": {"bound": "hbm", "achieved": round(r32["gbs"], 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(r32["gbs"] / PEAK_HBM_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(r32["gbs"] / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "algorithmic_bytes_per_launch": r32["bytes"], "traffic_source": traffic_note},
         "tflops_f32": round(r32["tflops"], 2),
         "hop_f64": None if "f64" not in res else {
             "gbs": round(res["f64"]["gbs"], 1), "us": round(res["f64"]["ms"] * 1e3, 2),
-            "frac": round(res["f64"]["gbs"] / PEAK_HBM_GBS, 4)},
+            "frac": round(res["f64"]["gbs"] / PEAK_HBM_GBS, 4), "plan": res["f64"]["plan"]},
         "cg": cg,
+        "forms": forms or None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
