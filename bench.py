@@ -135,8 +135,9 @@ def bench_hop(ctx, lat, Uf_dev, psi_dev, args, bsm):
         ctx.bsm_gauge_represent(d, Uf_dev, U)
         A, B = ctx.new_spinor(d), ctx.new_spinor(d)
         ctx.bsm_pack_spinor(d, psi_dev, A)
-        log(f"autotune {prec} hop ...")
-        ctx.bsm_autotune(d, U)
+        if not args.no_autotune:
+            log(f"autotune {prec} hop ...")
+            ctx.bsm_autotune(d, U)
         plan = ctx.bsm_get_hop_plan(d)
         steps = args.steps if prec == "f32" else max(10, args.steps // 4)
         log(f"timing {prec} even-odd hop: {steps} steps, plan {plan}")
@@ -394,6 +395,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--dims", type=str, default="64,32,32,32", help="T,LX,LY,LZ of the hop workload")
     ap.add_argument("--only-f32", action="store_true", help="skip the FP64 hop timing")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default hop plan (counter runs: every hop dispatch is the same kernel)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run N plain 1 GiB device copies (counter calibration)")
     args = ap.parse_args()
@@ -426,11 +429,13 @@ def main():
     Uf_dev = bsm.to_device_c128(Uf)
     psi_dev = bsm.to_device_c128(psi)
     if args.copy_calib:
+        # a plain copy kernel of known size: its counter readings calibrate
+        # the hop's (1 GiB read + 1 GiB written per launch)
         src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         for _ in range(args.copy_calib):
-            dst.copy_(src)
+            bsm.bsm_stream_copy(src, dst)
         torch.cuda.synchronize()
         log(f"calibration: {args.copy_calib} copies of 1 GiB")
         del src, dst

@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbsm.so")
+# BSM_LIB selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("BSM_LIB") or os.path.join(_HERE, "libbsm.so")
 
 OK, ERR_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_NOMEM, ERR_NOT_CONVERGED, ERR_NONFINITE = range(7)
 REP = {"fund": 0, "adj": 1, "sym": 2, "asym": 3}
