@@ -253,7 +253,8 @@ def bench_cfg4(bsm, gen):
     log("cfg4 batched ...")
     st, stats = ctx.bsm_batched_solve(d64, U, prm, kappas, b, xb, check=False)
     tb = stats[0]["seconds"]
-    log(f"  {tb:.3f} s, iters {[s['iters'] for s in stats]}")
+    plan = ctx.bsm_get_block_plan(d64)
+    log(f"  {tb:.3f} s, iters {[s['iters'] for s in stats]}, block plan {plan}")
     tseq, its, worst = 0.0, [], 0.0
     log("cfg4 sequential plain FP64 ...")
     for r in range(n):
@@ -267,7 +268,7 @@ def bench_cfg4(bsm, gen):
     out = {"workload": "24^3x48 SU(4) adjoint (d_R=15, real links), Haar links, 16 RHS, "
                        "kappa linspace(0.10, 0.125, 16), Schur CG to 1e-10 each",
            "kappas": kappas,
-           "batched": dict(status=st, seconds=round(tb, 4), iters=[s["iters"] for s in stats],
+           "batched": dict(status=st, seconds=round(tb, 4), iters=[s["iters"] for s in stats], block_plan=plan,
                            max_true_rel_res=max(s["true_rel_res"] for s in stats),
                            reliable_updates=[s["reliable_updates"] for s in stats]),
            "sequential_plain_f64": dict(seconds=round(tseq, 4), iters=its),

@@ -274,12 +274,15 @@ bsm_status bsm_precond_train(bsm_ctx ctx, const bsm_field_desc *desc, const void
 bsm_status bsm_precond_pairs(bsm_ctx ctx, const bsm_field_desc *desc64, const void *U_rep64, double kappa,
                              int32_t n_solves, const void *x_star, int32_t n_snap, const int32_t *iters,
                              void *r_out, void *e_out, void *stream);
-/* Flexible GCR(params->restart) on D x = b (full lattice, FP64 vectors) with
- * z = M(r) from the network (net nullable: M = 1), the FP64 true residual
- * recomputed at every restart, and a fall back to plain FP64 Schur CG from
- * the current x when a cycle reduces |r| by less than a factor 2 or meets a
- * non-finite value.  desc/U_rep: the network's F32 operator; U_rep64: FP64
- * links.  b, x: F64 full fields.  Synchronous. */
+/* Flexible GCR(params->restart) on D x = b with z = M(r) from the network
+ * (net nullable: M = 1).  Each restart cycle solves the correction equation
+ * D e = r in FP32 (directions, D, Gram-Schmidt; sums in FP64), then
+ * x += e in FP64 and r = b - D x is recomputed in FP64 (the judge).  A cycle
+ * that reduces |r| by less than a factor 2, or meets a non-finite value,
+ * hands over to plain FP64 Schur CG from the current x (from x = 0 after a
+ * non-finite value).  desc/U_rep: F32 spinors and F32 links (the inner
+ * operator and the network); U_rep64: FP64 links.  b, x: F64 full fields;
+ * padding sites of b must be zero (as pack leaves them).  Synchronous. */
 bsm_status bsm_fgcr_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, const void *U_rep64,
                           const bsm_solver_params *params, int32_t channels, const void *net, const void *b,
                           void *x, bsm_solver_stats *stats, void *stream);
@@ -309,6 +312,18 @@ bsm_status bsm_gauge_to_block(bsm_ctx ctx, const bsm_field_desc *desc, const voi
 bsm_status bsm_dslash_eo_block(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_block,
                                int32_t out_parity, int32_t dagger, const double *a, const void *x,
                                const double *b, const void *in, void *out, void *stream);
+/* Block hop launch plan per d_R: sites per wavefront (1, or 2 processed
+ * interleaved with half the register budget per wavefront) and wavefronts
+ * per workgroup (1, 2, 4).  bsm_block_autotune times every plan on the
+ * given block links (scratch fields owned by the context) and keeps the
+ * fastest; the batched solver tunes once per d_R and context unless a plan
+ * was set by hand.  us: time per hop of the tuned plan (0: default plan,
+ * -1: set by hand).  Synchronous. */
+bsm_status bsm_block_autotune(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_block, void *stream);
+bsm_status bsm_set_block_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t sites_per_wave,
+                              int32_t waves_per_group);
+bsm_status bsm_get_block_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t *sites_per_wave,
+                              int32_t *waves_per_group, float *us);
 /* Solve D(kappa_r) x_r = b_r for n_rhs right-hand sides with their own
  * kappa_r (Section II.B's inversion, for a family of masses).  b and x are
  * n_rhs consecutive full internal FP64 fields; U_rep64 are FP64 links.

@@ -26,24 +26,28 @@ bsm_status hip_check(hipError_t e, const char *what) {
     return BSM_ERR_HIP;
 }
 
-bsm_status ctx_work(bsm_ctx ctx, size_t bytes, void **out) {
-    if (bytes > ctx->work_bytes) {
-        if (ctx->work) BSM_HIP(hipFree(ctx->work));
-        ctx->work = nullptr;
-        ctx->work_bytes = 0;
-        hipError_t e = hipMalloc(&ctx->work, bytes);
-        if (e != hipSuccess) return fail(BSM_ERR_NOMEM, "solver scratch allocation failed");
+bsm_status ctx_work_slot(bsm_ctx ctx, int slot, size_t bytes, void **out) {
+    void *&w = slot == 0 ? ctx->work : ctx->work2;
+    size_t &wb = slot == 0 ? ctx->work_bytes : ctx->work2_bytes;
+    if (bytes > wb) {
+        if (w) BSM_HIP(hipFree(w));
+        w = nullptr;
+        wb = 0;
+        hipError_t e = hipMalloc(&w, bytes);
+        if (e != hipSuccess) return fail(BSM_ERR_NOMEM, "scratch allocation failed");
         // padding sites of internal fields are never written by the operator
         // kernels and must read as zero in the vector reductions.  The fill
         // runs on the null stream and may still be in flight when hipMemset
         // returns; solvers use their own streams, so wait for it here.
-        BSM_HIP(hipMemset(ctx->work, 0, bytes));
+        BSM_HIP(hipMemset(w, 0, bytes));
         BSM_HIP(hipDeviceSynchronize());
-        ctx->work_bytes = bytes;
+        wb = bytes;
     }
-    *out = ctx->work;
+    *out = w;
     return BSM_OK;
 }
+
+bsm_status ctx_work(bsm_ctx ctx, size_t bytes, void **out) { return ctx_work_slot(ctx, 0, bytes, out); }
 
 int hop_blocks(const Geom &g) { return (g.Vh + 255) / 256; }
 
@@ -143,8 +147,7 @@ bsm_status bsm_ctx_create(const bsm_lattice *lat, bsm_ctx *out) {
         V *= lat->L[mu];
     }
     if (V / 2 > (1 << 30)) return fail(BSM_ERR_ARG, "lattice too large");
-    bsm_ctx c = new bsm_ctx_s();
-    memset(c, 0, sizeof(*c));
+    bsm_ctx c = new bsm_ctx_s();   // value-initialised: zeros, then the plans' defaults
     c->lat = *lat;
     Geom &g = c->g;
     for (int mu = 0; mu < 4; mu++) g.L[mu] = lat->L[mu];
@@ -176,6 +179,7 @@ void bsm_ctx_destroy(bsm_ctx c) {
     if (c->scal) (void)hipFree(c->scal);
     if (c->host_scal) (void)hipHostFree(c->host_scal);
     if (c->work) (void)hipFree(c->work);
+    if (c->work2) (void)hipFree(c->work2);
     delete c;
 }
 
@@ -393,7 +397,43 @@ bsm_status bsm_dslash_eo_block(bsm_ctx ctx, const bsm_field_desc *desc, const vo
     h.dagger = dagger ? 1 : 0;
     h.p0 = out_parity;
     h.np = 1;
+    h.spw = ctx->block_plans[desc->d_R].spw;
+    h.wpb = ctx->block_plans[desc->d_R].wpb;
     return launch_hop_block(ctx->g, desc->d_R, h, (hipStream_t)stream);
+}
+
+bsm_status bsm_block_autotune(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_block, void *stream) {
+    CHECK(check_block(ctx, desc));
+    if (!U_block) return fail(BSM_ERR_ARG, "null pointer");
+    const size_t bb = block_parity_bytes(ctx->g, desc->d_R);
+    void *w = nullptr;
+    CHECK(ctx_work(ctx, 2 * bb + 256, &w));
+    float2 *in = (float2 *)w;
+    float2 *out = (float2 *)((char *)w + (bb + 255) / 256 * 256);
+    return block_autotune(ctx, desc->d_R, (const float *)U_block, in, out, (hipStream_t)stream);
+}
+
+bsm_status bsm_set_block_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t sites_per_wave,
+                              int32_t waves_per_group) {
+    CHECK(check_block(ctx, desc));
+    if (sites_per_wave != 1 && sites_per_wave != 2) return fail(BSM_ERR_ARG, "sites_per_wave must be 1 or 2");
+    if (waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4)
+        return fail(BSM_ERR_ARG, "waves_per_group must be 1, 2 or 4");
+    BlockPlan &b = ctx->block_plans[desc->d_R];
+    b.spw = sites_per_wave;
+    b.wpb = waves_per_group;
+    b.us = -1.f;   // set by hand: not tuned, and the batched solver keeps it
+    return BSM_OK;
+}
+
+bsm_status bsm_get_block_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t *sites_per_wave,
+                              int32_t *waves_per_group, float *us) {
+    CHECK(check_block(ctx, desc));
+    const BlockPlan &b = ctx->block_plans[desc->d_R];
+    if (sites_per_wave) *sites_per_wave = b.spw;
+    if (waves_per_group) *waves_per_group = b.wpb;
+    if (us) *us = b.us;
+    return BSM_OK;
 }
 
 bsm_status bsm_set_hop_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t order, int32_t tchunk) {

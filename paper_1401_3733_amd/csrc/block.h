@@ -26,10 +26,18 @@ struct BlockHopArgs {
     int dagger;
     int p0, np;
     double *norm_partials;   // [workgroup][kNR]
+    int spw = 1, wpb = 4;    // plan: sites per wavefront, wavefronts per workgroup
 };
 
 bsm_status launch_hop_block(const Geom &g, int d, const BlockHopArgs &a, hipStream_t st);
+// workgroups (= norm partials) of a launch under its plan
 int hop_block_grid(const Geom &g, const BlockHopArgs &a);
+// largest partial count of any plan (one site per workgroup), per parity
+inline int hop_block_grid_max(const Geom &g) { return g.Vh; }
+// time every plan on scratch block fields with the given links and keep the
+// fastest in ctx->block_plans[d]
+bsm_status block_autotune(bsm_ctx ctx, int d, const float *U_block, float2 *scratch_in, float2 *scratch_out,
+                          hipStream_t st);
 
 // layout conversions
 bsm_status launch_gauge_to_block(const Geom &g, int d, int link_prec, const void *U_rep, float *U_block,

@@ -59,92 +59,118 @@ __device__ inline void reconstruct_c(f4 (&acc)[4][2], float sg, float w, f4 g0r,
     }
 }
 
-template <int MU, int D>
-__device__ inline void hop_dir_block(const Geom &g, const BlockHopArgs &a, const Coords &c, int p, uint32_t h,
-                                     int r, int q, float eta, f4 (&acc)[4][2]) {
+// Both hops along MU for the S sites of this wavefront (S independent MFMA
+// chains, so the loads of one site overlap the products of the other).
+template <int MU, int D, int S>
+__device__ inline void hop_dir_block(const Geom &g, const BlockHopArgs &a, const Coords (&c)[S], int p,
+                                     const uint32_t (&h)[S], int r, int q, float eta, f4 (&acc)[S][4][2]) {
     constexpr int KB = (D + 3) / 4;
     constexpr size_t SITE = (size_t)D * 4 * kNR;
 #pragma unroll
     for (int dir = 0; dir < 2; dir++) {
         const bool back = dir == 1;
-        float w;
-        const uint32_t hn = neighbour<MU>(g, c, back, w);
-        const float2 *sp = a.in[p] + (size_t)hn * SITE;
-        float2 s[KB][4];
+        float w[S];
+        float2 sv[S][KB][4];
+        float A[S][KB];
 #pragma unroll
-        for (int kb = 0; kb < KB; kb++) {
-            const int cc = q + 4 * kb;
+        for (int j = 0; j < S; j++) {
+            const uint32_t hn = neighbour<MU>(g, c[j], back, w[j]);
+            const float2 *sp = a.in[p] + (size_t)hn * SITE;
 #pragma unroll
-            for (int si = 0; si < 4; si++)
-                s[kb][si] = cc < D ? sp[(cc * 4 + si) * kNR + r] : make_float2(0.f, 0.f);
-        }
-        const float *L = a.U + ((size_t)((back ? 1 - p : p) * 4 + MU) * g.Vh_pad + (back ? hn : h)) * (D * D);
-        float A[KB];
+            for (int kb = 0; kb < KB; kb++) {
+                const int cc = q + 4 * kb;
 #pragma unroll
-        for (int kb = 0; kb < KB; kb++) {
-            const int k = q + 4 * kb;
-            A[kb] = (r < D && k < D) ? __builtin_nontemporal_load(L + (back ? k * D + r : r * D + k)) : 0.f;
+                for (int si = 0; si < 4; si++)
+                    sv[j][kb][si] = cc < D ? sp[(cc * 4 + si) * kNR + r] : make_float2(0.f, 0.f);
+            }
+            const float *L =
+                a.U + ((size_t)((back ? 1 - p : p) * 4 + MU) * g.Vh_pad + (back ? hn : h[j])) * (D * D);
+#pragma unroll
+            for (int kb = 0; kb < KB; kb++) {
+                const int k = q + 4 * kb;
+                A[j][kb] = (r < D && k < D) ? __builtin_nontemporal_load(L + (back ? k * D + r : r * D + k)) : 0.f;
+            }
         }
         const float sg = back ? -eta : eta;
-        f4 g0r = {0.f, 0.f, 0.f, 0.f}, g0i = g0r, g1r = g0r, g1i = g0r;
 #pragma unroll
-        for (int kb = 0; kb < KB; kb++) {
-            float2 h0, h1;
-            project_c<MU>(s[kb], sg, h0, h1);
-            g0r = __builtin_amdgcn_mfma_f32_16x16x4f32(A[kb], h0.x, g0r, 0, 0, 0);
-            g0i = __builtin_amdgcn_mfma_f32_16x16x4f32(A[kb], h0.y, g0i, 0, 0, 0);
-            g1r = __builtin_amdgcn_mfma_f32_16x16x4f32(A[kb], h1.x, g1r, 0, 0, 0);
-            g1i = __builtin_amdgcn_mfma_f32_16x16x4f32(A[kb], h1.y, g1i, 0, 0, 0);
+        for (int j = 0; j < S; j++) {
+            f4 g0r = {0.f, 0.f, 0.f, 0.f}, g0i = g0r, g1r = g0r, g1i = g0r;
+#pragma unroll
+            for (int kb = 0; kb < KB; kb++) {
+                float2 h0, h1;
+                project_c<MU>(sv[j][kb], sg, h0, h1);
+                g0r = __builtin_amdgcn_mfma_f32_16x16x4f32(A[j][kb], h0.x, g0r, 0, 0, 0);
+                g0i = __builtin_amdgcn_mfma_f32_16x16x4f32(A[j][kb], h0.y, g0i, 0, 0, 0);
+                g1r = __builtin_amdgcn_mfma_f32_16x16x4f32(A[j][kb], h1.x, g1r, 0, 0, 0);
+                g1i = __builtin_amdgcn_mfma_f32_16x16x4f32(A[j][kb], h1.y, g1i, 0, 0, 0);
+            }
+            reconstruct_c<MU>(acc[j], sg, w[j], g0r, g0i, g1r, g1i);
         }
-        reconstruct_c<MU>(acc, sg, w, g0r, g0i, g1r, g1i);
     }
 }
 
-#ifndef BSM_BLOCK_WAVES
-#define BSM_BLOCK_WAVES 2
-#endif
-
-// 4 sites per 256-thread workgroup, one per wavefront.  The register budget
-// is capped so that several wavefronts per SIMD hide the load latency.
-template <int D>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BSM_BLOCK_WAVES)))
+// Launch plan (tuned per d_R by bsm_block_autotune):
+//   S  = sites per wavefront (1 or 2, interleaved), with a register budget of
+//        2 (S = 1) or 1 (S = 2) wavefronts per SIMD;
+//   WPB = wavefronts per workgroup (1, 2 or 4), from blockDim.x.
+// Workgroup w covers sites [w * WPB * S, (w + 1) * WPB * S); wavefront v owns
+// sites base + v + WPB * j, j < S.
+template <int D, int S>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == 1 ? 2 : 1)))
 void k_hop_block(Geom g, BlockHopArgs a, int nblk) {
     constexpr size_t SITE = (size_t)D * 4 * kNR;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
     const int r = lane & 15, q = lane >> 4;
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
     const int pi = lb >= (uint32_t)nblk ? 1 : 0;
-    const uint32_t h = (lb - pi * nblk) * 4 + wave;
+    const uint32_t base = (lb - pi * nblk) * (uint32_t)(wpb * S);
     const int p = a.p0 + pi;
+    uint32_t h[S];
+    bool live[S];
+#pragma unroll
+    for (int j = 0; j < S; j++) {
+        const uint32_t hj = base + wave + wpb * j;
+        live[j] = hj < (uint32_t)g.Vh;
+        h[j] = live[j] ? hj : base + wave;   // a dead second site repeats the first (never stored)
+    }
     double nrm = 0.0;
-    if (h < (uint32_t)g.Vh) {
-        f4 acc[4][2];
+    if (live[0]) {
+        f4 acc[S][4][2];
+        Coords c[S];
 #pragma unroll
-        for (int s = 0; s < 4; s++) acc[s][0] = acc[s][1] = f4{0.f, 0.f, 0.f, 0.f};
-        const Coords c = decode(g, h, p);
+        for (int j = 0; j < S; j++) {
+#pragma unroll
+            for (int sp = 0; sp < 4; sp++) acc[j][sp][0] = acc[j][sp][1] = f4{0.f, 0.f, 0.f, 0.f};
+            c[j] = decode(g, h[j], p);
+        }
         const float eta = a.dagger ? -1.f : 1.f;
-        hop_dir_block<0, D>(g, a, c, p, h, r, q, eta, acc);
-        hop_dir_block<1, D>(g, a, c, p, h, r, q, eta, acc);
-        hop_dir_block<2, D>(g, a, c, p, h, r, q, eta, acc);
-        hop_dir_block<3, D>(g, a, c, p, h, r, q, eta, acc);
+        hop_dir_block<0, D, S>(g, a, c, p, h, r, q, eta, acc);
+        hop_dir_block<1, D, S>(g, a, c, p, h, r, q, eta, acc);
+        hop_dir_block<2, D, S>(g, a, c, p, h, r, q, eta, acc);
+        hop_dir_block<3, D, S>(g, a, c, p, h, r, q, eta, acc);
         const float ar = a.a[r], br = a.b[r];
-        float2 *o = a.out[p] + (size_t)h * SITE;
-        const float2 *x = a.use_x ? a.x[p] + (size_t)h * SITE : nullptr;
 #pragma unroll
-        for (int v = 0; v < 4; v++) {
-            const int i = 4 * q + v;
-            if (i < D) {
+        for (int j = 0; j < S; j++) {
+            if (!live[j]) continue;
+            float2 *o = a.out[p] + (size_t)h[j] * SITE;
+            const float2 *x = a.use_x ? a.x[p] + (size_t)h[j] * SITE : nullptr;
 #pragma unroll
-                for (int s = 0; s < 4; s++) {
-                    const size_t e = (size_t)(i * 4 + s) * kNR + r;
-                    float re = br * acc[s][0][v], im = br * acc[s][1][v];
-                    if (x) {
-                        const float2 xv = x[e];
-                        re = fmaf(ar, xv.x, re);
-                        im = fmaf(ar, xv.y, im);
+            for (int v = 0; v < 4; v++) {
+                const int i = 4 * q + v;
+                if (i < D) {
+#pragma unroll
+                    for (int sp = 0; sp < 4; sp++) {
+                        const size_t e = (size_t)(i * 4 + sp) * kNR + r;
+                        float re = br * acc[j][sp][0][v], im = br * acc[j][sp][1][v];
+                        if (x) {
+                            const float2 xv = x[e];
+                            re = fmaf(ar, xv.x, re);
+                            im = fmaf(ar, xv.y, im);
+                        }
+                        o[e] = make_float2(re, im);
+                        nrm += (double)re * re + (double)im * im;
                     }
-                    o[e] = make_float2(re, im);
-                    nrm += (double)re * re + (double)im * im;
                 }
             }
         }
@@ -155,29 +181,87 @@ void k_hop_block(Geom g, BlockHopArgs a, int nblk) {
         __shared__ double ws[4][kNR];
         if (lane < kNR) ws[wave][lane] = nrm;
         __syncthreads();
-        if (threadIdx.x < kNR)
-            a.norm_partials[(size_t)lb * kNR + threadIdx.x] =
-                (ws[0][threadIdx.x] + ws[1][threadIdx.x]) + (ws[2][threadIdx.x] + ws[3][threadIdx.x]);
+        if (threadIdx.x < kNR) {
+            double t = ws[0][threadIdx.x];
+            for (int v = 1; v < wpb; v++) t += ws[v][threadIdx.x];
+            a.norm_partials[(size_t)lb * kNR + threadIdx.x] = t;
+        }
     }
 }
 
-int hop_block_grid(const Geom &g, const BlockHopArgs &a) { return (g.Vh + 3) / 4 * a.np; }
+static int block_sites_per_wg(const BlockHopArgs &a) { return a.wpb * a.spw; }
 
+int hop_block_grid(const Geom &g, const BlockHopArgs &a) {
+    const int per = block_sites_per_wg(a);
+    return (g.Vh + per - 1) / per * a.np;
+}
+
+// Only the adjoint representation has real links: d_R = N^2 - 1 in {3, 8, 15}.
 template <int D>
 struct BlockHopByD {
     static bsm_status run(const Geom &g, const BlockHopArgs &a, hipStream_t st) {
-        if constexpr (D <= 16) {
+        if constexpr (D == 3 || D == 8 || D == 15) {
             const int grid = hop_block_grid(g, a);
-            k_hop_block<D><<<grid, 256, 0, st>>>(g, a, grid / a.np);
+            const dim3 blk(64 * a.wpb);
+            if (a.spw == 2) k_hop_block<D, 2><<<grid, blk, 0, st>>>(g, a, grid / a.np);
+            else k_hop_block<D, 1><<<grid, blk, 0, st>>>(g, a, grid / a.np);
             BSM_HIP(hipGetLastError());
             return BSM_OK;
         }
-        return fail(BSM_ERR_UNSUPPORTED, "block hop d_R");
+        return fail(BSM_ERR_UNSUPPORTED, "block hop: real links exist only for d_R = 3, 8, 15");
     }
 };
 
 bsm_status launch_hop_block(const Geom &g, int d, const BlockHopArgs &a, hipStream_t st) {
+    if (a.spw != 1 && a.spw != 2) return fail(BSM_ERR_ARG, "block plan: sites per wavefront must be 1 or 2");
+    if (a.wpb != 1 && a.wpb != 2 && a.wpb != 4) return fail(BSM_ERR_ARG, "block plan: 1, 2 or 4 wavefronts");
     return dispatch_d<BlockHopByD>(d, g, a, st);
+}
+
+bsm_status block_autotune(bsm_ctx ctx, int d, const float *U_block, float2 *scratch_in, float2 *scratch_out,
+                          hipStream_t st) {
+    const Geom &g = ctx->g;
+    BSM_HIP(hipMemsetAsync(scratch_in, 0, block_parity_bytes(g, d), st));
+    hipEvent_t e0, e1;
+    BSM_HIP(hipEventCreate(&e0));
+    BSM_HIP(hipEventCreate(&e1));
+    BlockPlan best;
+    best.us = 0.f;
+    bsm_status status = BSM_OK;
+    for (int spw = 1; spw <= 2 && status == BSM_OK; spw++) {
+        for (int wpb : {1, 2, 4}) {
+            BlockHopArgs a{};
+            a.U = U_block;
+            a.p0 = 0;
+            a.np = 1;
+            a.in[0] = scratch_in;
+            a.out[0] = scratch_out;
+            for (int r = 0; r < kNR; r++) { a.a[r] = 0.f; a.b[r] = 1.f; }
+            a.spw = spw;
+            a.wpb = wpb;
+            const int reps = 5;
+            if ((status = launch_hop_block(g, d, a, st)) != BSM_OK) break;   // warm-up
+            if (hipEventRecord(e0, st) != hipSuccess) { status = fail(BSM_ERR_HIP, "event"); break; }
+            for (int k = 0; k < reps && status == BSM_OK; k++) status = launch_hop_block(g, d, a, st);
+            if (status != BSM_OK) break;
+            float ms = 0.f;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                status = fail(BSM_ERR_HIP, "block autotune timing");
+                break;
+            }
+            const float us = ms * 1000.f / reps;
+            if (best.us == 0.f || us < best.us) {
+                best.spw = spw;
+                best.wpb = wpb;
+                best.us = us;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status == BSM_OK) ctx->block_plans[d] = best;
+    return status;
 }
 
 // --------------------------------------------------------------- layouts

@@ -154,6 +154,12 @@ struct HopPlan {
     float us = 0.f;   // measured time per hop when tuned (0: default plan)
 };
 
+// multi-RHS hop plan per d_R (sites per wavefront, wavefronts per workgroup)
+struct BlockPlan {
+    int spw = 1, wpb = 4;
+    float us = 0.f;   // measured time per hop when tuned (0: default plan)
+};
+
 }  // namespace bsm
 
 // context (defined in api.cpp)
@@ -167,11 +173,17 @@ struct bsm_ctx_s {
     double *host_scal;      // pinned host mirror
     void *work;             // solver work buffer (lazily grown)
     size_t work_bytes;
+    void *work2;            // second scratch (FGCR: its fall back CG uses work)
+    size_t work2_bytes;
     bsm::HopPlan plans[16][2][3][3];   // [d_R][real][spinor prec][link prec]
+    bsm::BlockPlan block_plans[16];     // [d_R]
 };
 
 namespace bsm {
 constexpr int kMaxPartials = 1 << 16;
 constexpr int kScalars = 4096;
+// scratch that persists across calls, zero-filled when (re)allocated; slot 0
+// is the solvers' buffer, slot 1 a second one for callers of the solvers
 bsm_status ctx_work(bsm_ctx ctx, size_t bytes, void **out);
+bsm_status ctx_work_slot(bsm_ctx ctx, int slot, size_t bytes, void **out);
 }

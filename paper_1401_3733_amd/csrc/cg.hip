@@ -498,6 +498,8 @@ static bsm_status block_op(BlockSolve &B, int dagger, const float2 *in, float2 *
     a.U = B.Ublk;
     a.dagger = dagger;
     a.np = 1;
+    a.spw = B.ctx->block_plans[B.d].spw;
+    a.wpb = B.ctx->block_plans[B.d].wpb;
     // tmp_o = H_oe in_e
     a.p0 = 1;
     a.in[1] = in;
@@ -542,9 +544,8 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
     hipStream_t st = B.st;
     // ---- work memory
     const size_t linkB = block_link_bytes(g, d);
-    BlockHopArgs one{};
-    one.np = 1;
-    const size_t parts = std::max((size_t)hop_block_grid(g, one), (size_t)block_blas_grid(g, d, 1)) * kNR;
+    // partials for any plan (the autotuner below may change it)
+    const size_t parts = std::max((size_t)hop_block_grid_max(g), (size_t)block_blas_grid(g, d, 1)) * kNR;
     // 15 carve-outs below, each rounded up to 256 bytes
     size_t need = linkB + 6 * B.bbB + (size_t)(2 * n + 3) * B.bb64 + 2 * B.bb64 + parts * 8 +
                   block_scal_doubles() * 8 + 64 * sizeof(int) + 16 * 256;
@@ -562,6 +563,9 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
     B.mask = (int *)take(64 * sizeof(int));
     // ---- links in block layout, per-RHS FP64 operators and right-hand sides
     TRY(launch_gauge_to_block(g, d, BSM_F64, B.ops[0].U, B.Ublk, st));
+    // first batched solve for this d_R on the context: tune the block hop plan
+    // (t and q are outputs of every iteration, free to use as scratch here)
+    if (B.ctx->block_plans[d].us == 0.f) TRY(block_autotune(B.ctx, d, B.Ublk, B.t, B.q, st));
     BSM_HIP(hipMemsetAsync(B.x, 0, n * B.full64, st));
     B.bnorm2.assign(n, 0.0);
     B.rhs_norm2.assign(n, 0.0);

@@ -184,7 +184,9 @@ __device__ inline double hop_epilogue(const Geom &g, const HopArgs &a, int p, ui
             acc[k].im = fma(aa, xs[k].im, acc[k].im);
         }
     }
-    store_spinor<SP, D, T>(a.out[p], g.Vh_pad, h, acc);
+    // streaming stores: the output is not read again by this launch, and
+    // keeping it out of L2 leaves room for the input's neighbour re-reads
+    store_spinor_nt<SP, D, T>(a.out[p], g.Vh_pad, h, acc);
     double nrm = 0.0;
     if (a.norm_partials) {
 #pragma unroll

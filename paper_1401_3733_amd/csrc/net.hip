@@ -26,17 +26,19 @@ static bsm_status check_net_desc(bsm_ctx ctx, const bsm_field_desc *desc) {
 }
 
 // ------------------------------------------------------ FGCR vector kernels
-// Flat loops over the complex numbers of F64 full fields (n double2).  GCR
+// Flat loops over the complex numbers of F32 full fields (n float2; the
+// plane order is the same for every field, so sums over all components do
+// not depend on it).  Products are formed in FP32 and summed in FP64.  GCR
 // keeps the directions w_j = D z_j unnormalised with nn_j = |w_j|^2, so the
 // projections use coefficients <w_j, w> / nn_j.  Orthogonalisation is
 // classical Gram-Schmidt in one fused pass (all dots, then all updates),
 // equal to modified Gram-Schmidt in exact arithmetic; the residual stays
-// exact either way because r and x are updated with the same (w, z) pair.
+// consistent either way because r and x are updated with the same (w, z).
 constexpr int kGcrMax = 64;   // largest restart length
 constexpr int kZdotJ = 8;     // dot products per workgroup row
 constexpr int kZblocks = 1024;
 
-struct ZPtrs { const double2 *p[kGcrMax]; };
+struct ZPtrs { const float2 *p[kGcrMax]; };
 
 __device__ inline void block_sum2(double &re, double &im, double2 *ws, int slot, double2 *dst) {
 #pragma unroll
@@ -54,19 +56,19 @@ __device__ inline void block_sum2(double &re, double &im, double2 *ws, int slot,
 
 // partials[j][block] = sum conj(W_j) w over this workgroup's elements, for
 // j in [blockIdx.y * 8, min(k, +8))
-__global__ __launch_bounds__(256) void k_zmultidot(ZPtrs W, int k, const double2 *w, size_t n, double2 *partials) {
+__global__ __launch_bounds__(256) void k_zmultidot(ZPtrs W, int k, const float2 *w, size_t n, double2 *partials) {
     const int j0 = blockIdx.y * kZdotJ;
     double re[kZdotJ], im[kZdotJ];
 #pragma unroll
     for (int q = 0; q < kZdotJ; q++) re[q] = im[q] = 0.0;
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
-        const double2 y = w[e];
+        const float2 y = w[e];
 #pragma unroll
         for (int q = 0; q < kZdotJ; q++) {
             if (j0 + q >= k) break;
-            const double2 x = W.p[j0 + q][e];
-            re[q] += x.x * y.x + x.y * y.y;
-            im[q] += x.x * y.y - x.y * y.x;
+            const float2 x = W.p[j0 + q][e];
+            re[q] += (double)(x.x * y.x + x.y * y.y);
+            im[q] += (double)(x.x * y.y - x.y * y.x);
         }
     }
     __shared__ double2 ws[4 * kZdotJ];
@@ -78,7 +80,7 @@ __global__ __launch_bounds__(256) void k_zmultidot(ZPtrs W, int k, const double2
 }
 
 // one workgroup per column j: s = sum of nb partials (fixed order);
-// mode 0: coef[j] = s / nn[j] (0 when nn[j] is 0); mode 1: out[j] = s
+// mode 0: coef[j] = s / nn[j] (0 when nn[j] is 0); mode 1: coef[j] = s
 __global__ __launch_bounds__(256) void k_zcols(const double2 *partials, int nb, const double *nn, double2 *coef,
                                                int mode) {
     const int j = blockIdx.x;
@@ -101,16 +103,16 @@ __global__ __launch_bounds__(256) void k_zcols(const double2 *partials, int nb, 
 }
 
 // w -= sum_j coef_j W_j ; z -= sum_j coef_j Z_j ; partials of |w|^2 and <w, r>
-__global__ __launch_bounds__(256) void k_zorth(ZPtrs W, ZPtrs Z, int k, const double2 *coef, double2 *w, double2 *z,
-                                               const double2 *r, size_t n, double2 *partials) {
-    __shared__ double2 cs[kGcrMax];
-    if (threadIdx.x < k) cs[threadIdx.x] = coef[threadIdx.x];
+__global__ __launch_bounds__(256) void k_zorth(ZPtrs W, ZPtrs Z, int k, const double2 *coef, float2 *w, float2 *z,
+                                               const float2 *r, size_t n, double2 *partials) {
+    __shared__ float2 cs[kGcrMax];
+    if (threadIdx.x < k) cs[threadIdx.x] = make_float2((float)coef[threadIdx.x].x, (float)coef[threadIdx.x].y);
     __syncthreads();
     double nw = 0, dr = 0, di = 0;
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
-        double2 wv = w[e], zv = z[e];
+        float2 wv = w[e], zv = z[e];
         for (int j = 0; j < k; j++) {
-            const double2 c = cs[j], a = W.p[j][e], b = Z.p[j][e];
+            const float2 c = cs[j], a = W.p[j][e], b = Z.p[j][e];
             wv.x -= c.x * a.x - c.y * a.y;
             wv.y -= c.x * a.y + c.y * a.x;
             zv.x -= c.x * b.x - c.y * b.y;
@@ -120,10 +122,10 @@ __global__ __launch_bounds__(256) void k_zorth(ZPtrs W, ZPtrs Z, int k, const do
             w[e] = wv;
             z[e] = zv;
         }
-        const double2 rv = r[e];
-        nw += wv.x * wv.x + wv.y * wv.y;
-        dr += wv.x * rv.x + wv.y * rv.y;
-        di += wv.x * rv.y - wv.y * rv.x;
+        const float2 rv = r[e];
+        nw += (double)(wv.x * wv.x + wv.y * wv.y);
+        dr += (double)(wv.x * rv.x + wv.y * rv.y);
+        di += (double)(wv.x * rv.y - wv.y * rv.x);
     }
     __shared__ double2 ws[4 * kZdotJ];
     double zero = 0;
@@ -152,36 +154,24 @@ __global__ __launch_bounds__(256) void k_zalpha(const double2 *partials, int nb,
 }
 
 // x += alpha z ; r -= alpha w ; partials of |r|^2
-__global__ __launch_bounds__(256) void k_zupdate(double2 *x, double2 *r, const double2 *z, const double2 *w, size_t n,
+__global__ __launch_bounds__(256) void k_zupdate(float2 *x, float2 *r, const float2 *z, const float2 *w, size_t n,
                                                  const double2 *alpha, double2 *partials) {
-    const double ar = alpha->x, ai = alpha->y;
+    const float ar = (float)alpha->x, ai = (float)alpha->y;
     double rr = 0;
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
-        const double2 zv = z[e], wv = w[e];
-        double2 xv = x[e], rv = r[e];
+        const float2 zv = z[e], wv = w[e];
+        float2 xv = x[e], rv = r[e];
         xv.x += ar * zv.x - ai * zv.y;
         xv.y += ar * zv.y + ai * zv.x;
         rv.x -= ar * wv.x - ai * wv.y;
         rv.y -= ar * wv.y + ai * wv.x;
         x[e] = xv;
         r[e] = rv;
-        rr += rv.x * rv.x + rv.y * rv.y;
+        rr += (double)(rv.x * rv.x + rv.y * rv.y);
     }
     __shared__ double2 ws[4 * kZdotJ];
     double zero = 0;
     block_sum2(rr, zero, ws, 0, &partials[blockIdx.x]);
-}
-
-// |a|^2 partials (for |b|^2 and restart residuals)
-__global__ __launch_bounds__(256) void k_znorm(const double2 *a, size_t n, double2 *partials) {
-    double s = 0;
-    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
-        const double2 v = a[e];
-        s += v.x * v.x + v.y * v.y;
-    }
-    __shared__ double2 ws[4 * kZdotJ];
-    double zero = 0;
-    block_sum2(s, zero, ws, 0, &partials[blockIdx.x]);
 }
 
 #define TRY(x)                           \
@@ -392,14 +382,15 @@ bsm_status bsm_precond_pairs(bsm_ctx ctx, const bsm_field_desc *desc64, const vo
 bsm_status bsm_fgcr_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, const void *U_rep64,
                           const bsm_solver_params *prm, int32_t channels, const void *net, const void *bin,
                           void *xout, bsm_solver_stats *stats, void *stream) {
-    if (!ctx || !desc || !prm || !bin || !xout || !stats || !U_rep64) return fail(BSM_ERR_ARG, "null argument");
     if (stats) *stats = bsm_solver_stats{};
+    if (!ctx || !desc || !prm || !bin || !xout || !stats || !U_rep || !U_rep64) return fail(BSM_ERR_ARG, "null argument");
+    if (bsm_rep_dim(desc->N, desc->rep) != desc->d_R) return fail(BSM_ERR_ARG, "d_R does not match (N, rep)");
+    if (desc->prec != BSM_F32 || desc->link_prec != BSM_F32)
+        return fail(BSM_ERR_ARG, "the inner GCR runs on F32 spinors and F32 links");
     if (net) {
         TRY(check_net_desc(ctx, desc));
-        if (!U_rep) return fail(BSM_ERR_ARG, "the network needs F32 links");
         if (channels < 1 || channels > 64) return fail(BSM_ERR_ARG, "channels must be in [1, 64]");
     }
-    if (bsm_rep_dim(desc->N, desc->rep) != desc->d_R) return fail(BSM_ERR_ARG, "d_R does not match (N, rep)");
     if (!(prm->kappa > 0) || !(prm->tol > 0) || prm->max_iter < 1) return fail(BSM_ERR_ARG, "kappa, tol, max_iter");
     const int m = prm->restart > 0 ? prm->restart : 16;
     if (m > kGcrMax) return fail(BSM_ERR_ARG, "restart must be <= 64");
@@ -412,75 +403,70 @@ bsm_status bsm_fgcr_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U
     d64.link_prec = BSM_F64;
     const size_t f64 = 2 * spinor_block_bytes(BSM_F64, d, g.Vh_pad);
     const size_t f32 = 2 * spinor_block_bytes(BSM_F32, d, g.Vh_pad);
-    const size_t n = f64 / sizeof(double2);
+    const size_t n = f32 / sizeof(float2);
     const int nb = (int)std::min<size_t>((n + 255) / 256, kZblocks);
     auto t0 = std::chrono::steady_clock::now();
-    // own allocation: the fall back CG uses the context scratch
-    const size_t need = (2 * (size_t)m + 2) * f64 + (net ? (2 + (size_t)channels) * f32 : 0) +
+    // the context's second scratch: the fall back CG uses the first
+    const size_t need = (2 * (size_t)m + 2) * f32 + 2 * f64 + (net ? (size_t)channels * f32 : 0) +
                         (size_t)kGcrMax * nb * sizeof(double2) + 4 * kGcrMax * sizeof(double2) + 16 * 256;
     void *work = nullptr;
-    BSM_HIP(hipMalloc(&work, need));
+    TRY(ctx_work_slot(ctx, 1, need, &work));
     char *w = (char *)work;
     auto take = [&](size_t bytes) { char *r = w; w += (bytes + 255) / 256 * 256; return r; };
     ZPtrs Zp{}, Wp{};
     std::vector<char *> Z(m), Wv(m);
     for (int k = 0; k < m; k++) {
-        Z[k] = take(f64);
-        Wv[k] = take(f64);
-        Zp.p[k] = (const double2 *)Z[k];
-        Wp.p[k] = (const double2 *)Wv[k];
+        Z[k] = take(f32);
+        Wv[k] = take(f32);
+        Zp.p[k] = (const float2 *)Z[k];
+        Wp.p[k] = (const float2 *)Wv[k];
     }
-    char *r = take(f64), *t = take(f64);
-    char *r32 = net ? take(f32) : nullptr, *z32 = net ? take(f32) : nullptr;
+    char *rho = take(f32), *e = take(f32);
     char *h32 = net ? take((size_t)channels * f32) : nullptr;
+    char *r = take(f64), *t = take(f64);
     double2 *parts = (double2 *)take((size_t)kGcrMax * nb * sizeof(double2));
     double2 *coef = (double2 *)take(4 * kGcrMax * sizeof(double2));
     double *nn = (double *)(coef + kGcrMax);          // kGcrMax doubles
     double2 *alpha = coef + 2 * kGcrMax, *rr = coef + 3 * kGcrMax;
-    double2 hrr{};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    BSM_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    BSM_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
     const char *b = (const char *)bin;
     char *x = (char *)xout;
-    hipError_t he = hipSuccess;
-    auto readback = [&](double *out) -> bsm_status {
-        BSM_HIP(hipMemcpyAsync(&hrr, rr, sizeof(double2), hipMemcpyDeviceToHost, st));
-        BSM_HIP(hipStreamSynchronize(st));
-        *out = hrr.x;
+    const Vec none{nullptr, BSM_F64};
+    auto norm64 = [&](const void *v, double *out) -> bsm_status {
+        TRY(blas_dot(g, d, 2, Vec{(void *)v, BSM_F64}, none, ctx->partials, st));
+        *out = reduce_to_host(ctx, ctx->partials, blas_blocks(g, 2), st);
         return BSM_OK;
     };
-    auto norm2 = [&](const void *v, double *out) -> bsm_status {
-        k_znorm<<<nb, 256, 0, st>>>((const double2 *)v, n, parts);
-        k_zcols<<<1, 256, 0, st>>>(parts, nb, nullptr, rr, 1);
-        BSM_HIP(hipGetLastError());
-        return readback(out);
-    };
-    // r = b - D x, |r|^2
+    // FP64: r = b - D x, |r|^2
     auto residual = [&](double *out) -> bsm_status {
         TRY(bsm_dslash_apply(ctx, &d64, U_rep64, prm->kappa, 0, x, t, stream));
         TRY(blas_axpby(g, d, 2, Vec{r, BSM_F64}, 1.0, Vec{(void *)b, BSM_F64}, -1.0, Vec{t, BSM_F64}, nullptr, st));
-        return norm2(r, out);
+        return norm64(r, out);
     };
+    // one FP32 GCR step on D e = rho with direction k
     auto step = [&](int k) -> bsm_status {
-        // z_k = M(r)
         if (net) {
-            TRY(blas_axpby(g, d, 2, Vec{r32, BSM_F32}, 1.0, Vec{r, BSM_F64}, 0.0, Vec{nullptr, BSM_F64}, nullptr, st));
-            TRY(net_apply(ctx, desc, U_rep, channels, net, r32, h32, z32, st));
-            TRY(blas_axpby(g, d, 2, Vec{Z[k], BSM_F64}, 1.0, Vec{z32, BSM_F32}, 0.0, Vec{nullptr, BSM_F32}, nullptr,
-                           st));
+            TRY(net_apply(ctx, desc, U_rep, channels, net, rho, h32, Z[k], st));
         } else {
-            BSM_HIP(hipMemcpyAsync(Z[k], r, f64, hipMemcpyDeviceToDevice, st));
+            BSM_HIP(hipMemcpyAsync(Z[k], rho, f32, hipMemcpyDeviceToDevice, st));
         }
-        // w_k = D z_k, orthogonal to the earlier w_j
-        TRY(bsm_dslash_apply(ctx, &d64, U_rep64, prm->kappa, 0, Z[k], Wv[k], stream));
+        TRY(bsm_dslash_apply(ctx, desc, U_rep, prm->kappa, 0, Z[k], Wv[k], stream));
         if (k > 0) {
-            k_zmultidot<<<dim3(nb, (k + kZdotJ - 1) / kZdotJ), 256, 0, st>>>(Wp, k, (const double2 *)Wv[k], n, parts);
+            k_zmultidot<<<dim3(nb, (k + kZdotJ - 1) / kZdotJ), 256, 0, st>>>(Wp, k, (const float2 *)Wv[k], n, parts);
             k_zcols<<<k, 256, 0, st>>>(parts, nb, nn, coef, 0);
         }
-        k_zorth<<<nb, 256, 0, st>>>(Wp, Zp, k, coef, (double2 *)Wv[k], (double2 *)Z[k], (const double2 *)r, n, parts);
+        k_zorth<<<nb, 256, 0, st>>>(Wp, Zp, k, coef, (float2 *)Wv[k], (float2 *)Z[k], (const float2 *)rho, n, parts);
         k_zalpha<<<1, 256, 0, st>>>(parts, nb, nn, k, alpha);
-        k_zupdate<<<nb, 256, 0, st>>>((double2 *)x, (double2 *)r, (const double2 *)Z[k], (const double2 *)Wv[k], n,
+        k_zupdate<<<nb, 256, 0, st>>>((float2 *)e, (float2 *)rho, (const float2 *)Z[k], (const float2 *)Wv[k], n,
                                       alpha, parts);
         k_zcols<<<1, 256, 0, st>>>(parts, nb, nullptr, rr, 1);
         BSM_HIP(hipGetLastError());
+        // |rho|^2 to a pinned slot; the host reads it one step later, so the
+        // next step is already queued while this one finishes
+        BSM_HIP(hipMemcpyAsync(ctx->host_scal + S_TMP + (k & 1), rr, sizeof(double), hipMemcpyDeviceToHost, st));
+        BSM_HIP(hipEventRecord(ev[k & 1], st));
         return BSM_OK;
     };
 
@@ -488,10 +474,9 @@ bsm_status bsm_fgcr_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U
     double bn2 = 0, r2 = 0;
     int it = 0, cycles = 0, applies = 0;
     bool fallback = false;
-    he = hipMemsetAsync(work, 0, need, st);
-    if (he == hipSuccess) he = hipMemsetAsync(x, 0, f64, st);
+    hipError_t he = hipMemsetAsync(x, 0, f64, st);
     if (he != hipSuccess) status = hip_check(he, "fgcr init");
-    if (status == BSM_OK) status = norm2(b, &bn2);
+    if (status == BSM_OK) status = norm64(b, &bn2);
     if (status == BSM_OK && !std::isfinite(bn2)) status = fail(BSM_ERR_NONFINITE, "non-finite right-hand side");
     const double tol2 = prm->tol * prm->tol * bn2;
     if (status == BSM_OK && bn2 > 0) status = residual(&r2);
@@ -499,22 +484,32 @@ bsm_status bsm_fgcr_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U
         if (!std::isfinite(r2)) { fallback = true; break; }
         if (r2 <= tol2) break;
         const double r2_cycle = r2;
-        for (int k = 0; k < m && it < prm->max_iter; k++) {
+        // inner FP32 cycle on the correction: D e = r, e = 0
+        status = blas_axpby(g, d, 2, Vec{rho, BSM_F32}, 1.0, Vec{r, BSM_F64}, 0.0, none, nullptr, st);
+        if (status == BSM_OK && hipMemsetAsync(e, 0, f32, st) != hipSuccess) status = fail(BSM_ERR_HIP, "memset");
+        for (int k = 0; status == BSM_OK && k < m && it < prm->max_iter; k++) {
             if ((status = step(k)) != BSM_OK) break;
             if (net) applies++;
             it++;
-            double rk = 0;
-            if ((status = readback(&rk)) != BSM_OK) break;
-            if (!std::isfinite(rk) || rk <= tol2) break;
+            if (k > 0) {
+                // the previous step's residual (this step runs meanwhile and is kept)
+                if (hipEventSynchronize(ev[(k - 1) & 1]) != hipSuccess) { status = fail(BSM_ERR_HIP, "event"); break; }
+                const double rk = ctx->host_scal[S_TMP + ((k - 1) & 1)];
+                if (!std::isfinite(rk) || rk <= tol2) break;
+            }
         }
         if (status != BSM_OK) break;
         cycles++;
-        if ((status = residual(&r2)) != BSM_OK) break;   // restart from the FP64 true residual
+        // x += e in FP64 and the restart residual from scratch
+        if ((status = blas_axpby(g, d, 2, Vec{x, BSM_F64}, 1.0, Vec{x, BSM_F64}, 1.0, Vec{e, BSM_F32}, nullptr, st)) !=
+            BSM_OK)
+            break;
+        if ((status = residual(&r2)) != BSM_OK) break;
         if (r2 <= tol2) break;
         if (!std::isfinite(r2) || (it < prm->max_iter && r2 > 0.25 * r2_cycle)) { fallback = true; break; }
     }
     if (status == BSM_OK && fallback) {
-        // plain FP64 Schur CG on D e = r from the current x, then x += e
+        // plain FP64 Schur CG on D c = r from the current x, then x += c
         bsm_solver_params p = *prm;
         p.variant = BSM_SOLVER_PLAIN;
         p.schur = 1;
@@ -540,7 +535,8 @@ bsm_status bsm_fgcr_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U
         }
     }
     (void)hipStreamSynchronize(st);
-    (void)hipFree(work);
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
     stats->iters = it;
     stats->restarts = cycles;
     stats->fell_back = fallback ? 1 : 0;

@@ -58,8 +58,55 @@ __device__ inline void transport(const Geom &g, const char *U, size_t lblk, cons
     for (int k = 0; k < 4 * D; k++) t[k] = w * t[k];
 }
 
-// one thread per site of both parities; blockIdx.y selects a group of CG
-// output channels
+// geometry of path p >= 1 at site (px, h): source half index, boundary
+// factor, link block and the half index of the link
+struct PathSite {
+    uint32_t hn, hl;
+    float w;
+    const char *blk;
+    bool back;
+};
+
+__device__ inline PathSite path_site(const Geom &g, const char *U, size_t lblk, int px, uint32_t h,
+                                     const Coords &c, int path) {
+    PathSite ps;
+    const int mu = (path - 1) & 3;
+    ps.back = path > 4;
+    switch (mu) {
+    case 0: ps.hn = neighbour<0>(g, c, ps.back, ps.w); break;
+    case 1: ps.hn = neighbour<1>(g, c, ps.back, ps.w); break;
+    case 2: ps.hn = neighbour<2>(g, c, ps.back, ps.w); break;
+    default: ps.hn = neighbour<3>(g, c, ps.back, ps.w); break;
+    }
+    ps.blk = U + (size_t)((ps.back ? 1 - px : px) * 4 + mu) * lblk;
+    ps.hl = ps.back ? ps.hn : h;
+    return ps;
+}
+
+// acc[q] += W_p^{i0+q, j} t for the output channels of this workgroup
+template <int D, int CG>
+__device__ inline void mix_spin(const float2 *W, int cin, int cout, int i0, int j, int p, const cx<float> (&t)[4 * D],
+                                cx<float> (&acc)[CG][4 * D]) {
+#pragma unroll
+    for (int q = 0; q < CG; q++) {
+        const int i = i0 + q;
+        if (i >= cout) break;
+        const float2 *w = W + (((size_t)i * cin + j) * 9 + p) * 16;
+#pragma unroll
+        for (int sa = 0; sa < 4; sa++)
+#pragma unroll
+            for (int sb = 0; sb < 4; sb++) {
+                const float2 wv = w[sa * 4 + sb];
+                const cx<float> wc = mk<float>(wv.x, wv.y);
+#pragma unroll
+                for (int cc = 0; cc < D; cc++) acc[q][sa * D + cc] = cfma(wc, t[sb * D + cc], acc[q][sa * D + cc]);
+            }
+    }
+}
+
+// One thread per site of both parities; blockIdx.y selects a group of CG
+// output channels.  Paths outermost: the link of a path is loaded once into
+// registers and carries every input channel's neighbour.
 template <int D, int CG>
 __global__ __launch_bounds__(256) void k_ptc_layer(Geom g, PtcArgs a, int nblk) {
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -70,32 +117,112 @@ __global__ __launch_bounds__(256) void k_ptc_layer(Geom g, PtcArgs a, int nblk) 
     const size_t pblk = spinor_block_bytes(BSM_F32, D, g.Vh_pad);
     const size_t lblk = link_block_bytes(BSM_F32, false, D, g.Vh_pad);
     const Coords c = decode(g, h, px);
+    const float2 *W = (const float2 *)a.W;
+    const char *in = (const char *)a.in;
     cx<float> acc[CG][4 * D];
 #pragma unroll
     for (int q = 0; q < CG; q++)
 #pragma unroll
         for (int k = 0; k < 4 * D; k++) acc[q][k] = mk<float>(0.f, 0.f);
-    const float2 *W = (const float2 *)a.W;
+    // stay path
     for (int j = 0; j < a.cin; j++) {
-        const char *vj = (const char *)a.in + (size_t)j * 2 * pblk;
-        for (int p = 0; p < 9; p++) {
-            cx<float> t[4 * D];
-            transport<D>(g, (const char *)a.U, lblk, vj, pblk, px, h, c, p, t);
+        cx<float> t[4 * D];
+        load_spinor<BSM_F32, D, float>(in + (size_t)j * 2 * pblk + px * pblk, g.Vh_pad, h, t);
+        mix_spin<D, CG>(W, a.cin, a.cout, i0, j, 0, t, acc);
+    }
+    for (int p = 1; p < 9; p++) {
+        const PathSite ps = path_site(g, (const char *)a.U, lblk, px, h, c, p);
+        cx<float> u[D * D];
 #pragma unroll
-            for (int q = 0; q < CG; q++) {
-                const int i = i0 + q;
-                if (i >= a.cout) break;
-                const float2 *w = W + (((size_t)i * a.cin + j) * 9 + p) * 16;
+        for (int e = 0; e < D * D; e++) {
+            u[e] = load_link<BSM_F32, false, float>(ps.blk, g.Vh_pad, e, ps.hl);
+            u[e] = ps.w * u[e];
+        }
+        for (int j = 0; j < a.cin; j++) {
+            cx<float> s[4 * D], t[4 * D];
+            load_spinor<BSM_F32, D, float>(in + (size_t)j * 2 * pblk + (1 - px) * pblk, g.Vh_pad, ps.hn, s);
 #pragma unroll
-                for (int sa = 0; sa < 4; sa++)
+            for (int k = 0; k < 4 * D; k++) t[k] = mk<float>(0.f, 0.f);
+            if (!ps.back) {
 #pragma unroll
-                    for (int sb = 0; sb < 4; sb++) {
-                        const float2 wv = w[sa * 4 + sb];
-                        const cx<float> wc = mk<float>(wv.x, wv.y);
+                for (int i = 0; i < D; i++)
 #pragma unroll
-                        for (int cc = 0; cc < D; cc++) acc[q][sa * D + cc] = cfma(wc, t[sb * D + cc], acc[q][sa * D + cc]);
-                    }
+                    for (int jj = 0; jj < D; jj++)
+#pragma unroll
+                        for (int sa = 0; sa < 4; sa++) t[sa * D + i] = cfma(u[i * D + jj], s[sa * D + jj], t[sa * D + i]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < D; i++)
+#pragma unroll
+                    for (int jj = 0; jj < D; jj++)
+#pragma unroll
+                        for (int sa = 0; sa < 4; sa++)
+                            t[sa * D + jj] = cfma_conj(u[i * D + jj], s[sa * D + i], t[sa * D + jj]);
             }
+            mix_spin<D, CG>(W, a.cin, a.cout, i0, j, p, t, acc);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < CG; q++) {
+        const int i = i0 + q;
+        if (i >= a.cout) break;
+        char *oi = (char *)a.out + (size_t)i * 2 * pblk + px * pblk;
+        store_spinor<BSM_F32, D, float>(oi, g.Vh_pad, h, acc[q]);
+    }
+}
+
+// Mix first, transport after: the spin matrix W_p^{ij} acts on spin and the
+// transport T_p on colour and position, so W_p^{ij} T_p v_j = T_p (W_p^{ij} v_j)
+// and out_i(x) = sum_p T_p g_{i,p}(x) with g_{i,p}(y) = sum_j W_p^{ij} v_j(y)
+// formed at the source site y.  The mixing work is the same as in k_ptc_layer
+// and each path needs one link product per output channel instead of one per
+// input channel: the cheaper form when cin > cout.
+template <int D, int CG>
+__global__ __launch_bounds__(256) void k_ptc_layer_mt(Geom g, PtcArgs a, int nblk) {
+    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int px = lb >= (uint32_t)nblk ? 1 : 0;
+    const uint32_t h = (lb - px * nblk) * 256 + threadIdx.x;
+    if (h >= (uint32_t)g.Vh) return;
+    const int i0 = blockIdx.y * CG;
+    const size_t pblk = spinor_block_bytes(BSM_F32, D, g.Vh_pad);
+    const size_t lblk = link_block_bytes(BSM_F32, false, D, g.Vh_pad);
+    const Coords c = decode(g, h, px);
+    const float2 *W = (const float2 *)a.W;
+    const char *in = (const char *)a.in;
+    cx<float> acc[CG][4 * D];
+#pragma unroll
+    for (int q = 0; q < CG; q++)
+#pragma unroll
+        for (int k = 0; k < 4 * D; k++) acc[q][k] = mk<float>(0.f, 0.f);
+    // stay path: g = sum_j W_0 v_j at this site goes straight into acc
+    for (int j = 0; j < a.cin; j++) {
+        cx<float> t[4 * D];
+        load_spinor<BSM_F32, D, float>(in + (size_t)j * 2 * pblk + px * pblk, g.Vh_pad, h, t);
+        mix_spin<D, CG>(W, a.cin, a.cout, i0, j, 0, t, acc);
+    }
+    for (int p = 1; p < 9; p++) {
+        const PathSite ps = path_site(g, (const char *)a.U, lblk, px, h, c, p);
+        cx<float> gm[CG][4 * D];
+#pragma unroll
+        for (int q = 0; q < CG; q++)
+#pragma unroll
+            for (int k = 0; k < 4 * D; k++) gm[q][k] = mk<float>(0.f, 0.f);
+        for (int j = 0; j < a.cin; j++) {
+            cx<float> s[4 * D];
+            load_spinor<BSM_F32, D, float>(in + (size_t)j * 2 * pblk + (1 - px) * pblk, g.Vh_pad, ps.hn, s);
+            mix_spin<D, CG>(W, a.cin, a.cout, i0, j, p, s, gm);
+        }
+#pragma unroll
+        for (int e = 0; e < D * D; e++) {
+            const int i = e / D, jj = e % D;
+            const cx<float> u = ps.w * load_link<BSM_F32, false, float>(ps.blk, g.Vh_pad, e, ps.hl);
+#pragma unroll
+            for (int q = 0; q < CG; q++)
+#pragma unroll
+                for (int sa = 0; sa < 4; sa++) {
+                    if (!ps.back) acc[q][sa * D + i] = cfma(u, gm[q][sa * D + jj], acc[q][sa * D + i]);
+                    else acc[q][sa * D + jj] = cfma_conj(u, gm[q][sa * D + i], acc[q][sa * D + jj]);
+                }
         }
     }
 #pragma unroll
@@ -219,9 +346,23 @@ struct PtcByD {
         } else {
             const int nblk = (g.Vh + 255) / 256;
             if (mode == 0) {
-                constexpr int CG = 4;
+                // output channels per thread: as many as the registers hold
+                // next to a D x D link and two spinors
+                constexpr int CG = D <= 3 ? 4 : D <= 4 ? 2 : 1;
                 dim3 grid(2 * nblk, (a.cout + CG - 1) / CG);
-                k_ptc_layer<D, CG><<<grid, 256, 0, st>>>(g, a, nblk);
+                if (a.cin > a.cout) {
+                    // a mixed field per output channel of the thread's group
+                    // sits next to the accumulators
+                    if (D <= 3 && a.cout > 1) {
+                        dim3 gm(2 * nblk, (a.cout + 1) / 2);
+                        k_ptc_layer_mt<D, 2><<<gm, 256, 0, st>>>(g, a, nblk);
+                    } else {
+                        dim3 gm(2 * nblk, a.cout);
+                        k_ptc_layer_mt<D, 1><<<gm, 256, 0, st>>>(g, a, nblk);
+                    }
+                } else {
+                    k_ptc_layer<D, CG><<<grid, 256, 0, st>>>(g, a, nblk);
+                }
             } else {
                 dim3 grid(2 * nblk, a.cin * 9);
                 k_ptc_wgrad<D><<<grid, 256, 0, st>>>(g, a, nblk, partials);

@@ -80,12 +80,51 @@ __device__ inline void store_spinor(void *blk, int64_t stride, uint32_t h, const
 }
 
 typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+// store_spinor with streaming (non-temporal) stores for F32 and F64
+template <int P, int D, class T>
+__device__ inline void store_spinor_nt(void *blk, int64_t stride, uint32_t h, const cx<T> (&s)[4 * D]) {
+    if constexpr (P == BSM_F32) {
+        f32x4v *b = (f32x4v *)blk;
+#pragma unroll
+        for (int k = 0; k < 2 * D; k++) {
+            f32x4v v = {(float)s[2 * k].re, (float)s[2 * k].im, (float)s[2 * k + 1].re, (float)s[2 * k + 1].im};
+            __builtin_nontemporal_store(v, b + k * stride + h);
+        }
+    } else if constexpr (P == BSM_F64) {
+        typedef double f64x2v __attribute__((ext_vector_type(2)));
+        f64x2v *b = (f64x2v *)blk;
+#pragma unroll
+        for (int c = 0; c < 4 * D; c++) {
+            f64x2v v = {(double)s[c].re, (double)s[c].im};
+            __builtin_nontemporal_store(v, b + c * stride + h);
+        }
+    } else {
+        store_spinor<P, D, T>(blk, stride, h, s);
+    }
+}
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 // Link element (i, j) of a link block (complex or real) as cx<T>; NT: a
 // non-temporal (streaming) load.
 template <int LP, bool REAL, class T, bool NT = false>
 __device__ inline cx<T> load_link(const void *blk, int64_t stride, int e, uint32_t h) {
+#ifdef BSM_LINK_CPOL
+    // streaming link loads as buffer loads with an explicit cache policy
+    if constexpr (NT && !REAL && (LP == BSM_F32 || LP == BSM_F64)) {
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void *)blk, (short)0, 0x7fffffff, 0x00020000);
+        if constexpr (LP == BSM_F32) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)((e * stride + h) * 8), 0, BSM_LINK_CPOL);
+            const float2 f = *reinterpret_cast<const float2 *>(&v);
+            return mk<T>((T)f.x, (T)f.y);
+        } else {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)((e * stride + h) * 16), 0, BSM_LINK_CPOL);
+            const double2 f = *reinterpret_cast<const double2 *>(&v);
+            return mk<T>((T)f.x, (T)f.y);
+        }
+    }
+#endif
     if constexpr (NT && !REAL && LP == BSM_F32) {
         f32x2 v = __builtin_nontemporal_load((const f32x2 *)blk + e * stride + h);
         return mk<T>((T)v.x, (T)v.y);

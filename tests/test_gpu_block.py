@@ -149,3 +149,64 @@ def test_block_hop_full_size_sampled():
         for r in range(n_rhs):
             ref = oracle.dslash_sites(lat, UR, 1.0, psi[r], sample)
             assert rel(got[r][sample], ref) < 2e-6, (p, r, rel(got[r][sample], ref))
+
+
+PLANS = [(s, w) for s in (1, 2) for w in (1, 2, 4)]
+
+
+@pytest.mark.parametrize("N", [3, 4])
+@pytest.mark.parametrize("spw,wpb", PLANS)
+def test_every_block_plan_gives_the_same_operator(N, spw, wpb):
+    note(f"block plan spw={spw} wpb={wpb} N={N}")
+    lat = gen.Lattice(8, 6, 4, 6)
+    S, UR, Ub = _block_setup(lat, N, 760 + N)
+    S.ctx.bsm_set_block_plan(S.desc, spw, wpb)
+    assert S.ctx.bsm_get_block_plan(S.desc)["sites_per_wave"] == spw
+    d = S.d
+    psi = gen.gaussian_spinor(lat, d, 761, n_rhs=16)
+    A = S.ctx.new_block(S.desc)
+    S.ctx.bsm_pack_block(S.desc, c128(psi), A, 16)
+    nb = S.ctx.block_bytes(S.desc) // 2
+    par = oracle.parity_mask(lat)
+    for p in (0, 1):
+        out = S.ctx.new_block(S.desc)
+        S.ctx.bsm_dslash_eo_block(S.desc, Ub, p, 1, np.ones(16), A[p * nb:(p + 1) * nb], -0.1 * np.ones(16),
+                                  A[(1 - p) * nb:(2 - p) * nb], out[p * nb:(p + 1) * nb])
+        got = _unpack_block(S, out, 16)
+        for r in (0, 9, 15):
+            ref = psi[r] - 0.1 * oracle.hop(lat, UR, psi[r], dagger=True, parity=p)
+            m = par == p
+            assert rel(got[r][m], ref[m]) < 2e-6
+
+
+@pytest.mark.parametrize("spw,wpb", PLANS)
+def test_batched_solve_under_every_block_plan(spw, wpb):
+    """the fused per-RHS norms of the block hop depend on the plan's workgroup shape"""
+    import torch
+    note(f"batched solve plan spw={spw} wpb={wpb}")
+    lat = gen.Lattice(4, 4, 4, 6)
+    Uf = gen.gauge_links(lat, 3, "haar", 770)
+    S = Setup(lat, 3, "adj", Uf, prec="f64")
+    S.ctx.bsm_set_block_plan(S.desc, spw, wpb)
+    UR = oracle.represent(Uf, "adj").real.astype(np.complex128)
+    kappas = [0.11, 0.12, 0.125]
+    b = gen.gaussian_spinor(lat, 8, 771, n_rhs=3)
+    bb = S.pack(b, n_rhs=3)
+    x = torch.zeros_like(bb)
+    status, stats = S.ctx.bsm_batched_solve(S.desc, S.U, bsm.solver_params(0.1, 1e-10), kappas, bb, x)
+    assert status == 0
+    assert S.ctx.bsm_get_block_plan(S.desc)["us"] == -1.0     # a hand-set plan is kept
+    xs = S.unpack(x, n_rhs=3)
+    for r in range(3):
+        assert oracle.true_residual(lat, UR, kappas[r], b[r], xs[r]) <= 1e-10
+
+
+def test_block_autotune_picks_a_plan():
+    lat = gen.Lattice(8, 6, 4, 6)
+    S, UR, Ub = _block_setup(lat, 4, 780)
+    plan = S.ctx.bsm_block_autotune(S.desc, Ub)
+    assert plan["us"] > 0 and (plan["sites_per_wave"], plan["waves_per_group"]) in PLANS
+    with pytest.raises(bsm.BsmError):
+        S.ctx.bsm_set_block_plan(S.desc, 3, 4)
+    with pytest.raises(bsm.BsmError):
+        S.ctx.bsm_set_block_plan(S.desc, 1, 8)

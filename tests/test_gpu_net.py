@@ -237,7 +237,7 @@ def test_fgcr_without_net_is_gcr():
     if not stats["fell_back"]:
         D = lambda v: oracle.dslash(LAT, T.UR, KAPPA, v)
         _, it_or, _ = ptc.fgcr(D, lambda r: r, b, tol=1e-10, m=16)
-        assert abs(stats["iters"] - it_or) <= 2
+        assert abs(stats["iters"] - it_or) <= max(2, it_or // 10)
 
 
 def test_training_reduces_loss_and_fgcr_iterations():

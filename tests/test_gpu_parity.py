@@ -200,3 +200,44 @@ def test_autotune_and_plan_validation():
     S2 = Setup(lat2, 3, "fund", _links(lat2, 3, 603))
     with pytest.raises(_b.BsmError):
         S2.ctx.bsm_set_hop_plan(S2.desc, 3, 1)
+
+
+_FULL = {}
+
+
+def _full_fields(cfg):
+    """Links and a source of a full-size workload (generated once per run)."""
+    if cfg not in _FULL:
+        _FULL.clear()
+        lat = gen.config_lattice(cfg)
+        d = oracle.rep_dim(3, gen.CONFIGS[cfg]["rep"])
+        _FULL[cfg] = (lat, gen.config_links(cfg, lat), gen.gaussian_spinor(lat, d, 900 + cfg))
+    return _FULL[cfg]
+
+
+@pytest.mark.parametrize("cfg,prec,lprec,tol", [(2, "f32", "f32", 1e-6), (2, "f64", "f64", 1e-13),
+                                                (3, "f32", "f32", 1e-6), (3, "f16s", "f32", 2e-3),
+                                                (3, "f16s", "f16s", 2e-3)])
+def test_hop_full_size_sampled(cfg, prec, lprec, tol):
+    """32^3 x 64 lattices at full size, in the launch configuration bench.py
+    times (autotuned plan, even-odd block with out = x - H in, i.e. D at
+    kappa = 1 on the output parity): sampled sites against the oracle."""
+    note(f"full-size hop cfg{cfg} {prec}/{lprec}")
+    lat, Uf, psi = _full_fields(cfg)
+    rep = gen.CONFIGS[cfg]["rep"]
+    S = Setup(lat, 3, rep, Uf, prec=prec, link_prec=lprec)
+    UR = oracle.represent(Uf, rep)
+    S.ctx.bsm_autotune(S.desc, S.U)
+    inp = S.pack(psi)
+    par = oracle.parity_mask(lat)
+    rng = np.random.default_rng(cfg)
+    for p in (0, 1):
+        out = S.ctx.new_spinor(S.desc)
+        S.ctx.bsm_dslash_eo(S.desc, S.U, p, 0, 1.0, S.block(inp, p), -1.0, S.block(inp, 1 - p), S.block(out, p))
+        got = S.unpack(out)
+        sites = np.flatnonzero(par == p)
+        sample = np.concatenate([sites[:256], sites[-256:], rng.choice(sites, 2048, replace=False)])
+        ref = oracle.dslash_sites(lat, UR, 1.0, psi, sample)
+        err = rel(got[sample], ref)
+        print(f"cfg{cfg} {prec}/{lprec} parity {p}: sampled rel L2 error {err:.3e}")
+        assert err <= tol
