@@ -331,7 +331,7 @@ def bench_cfg5(bsm, gen, train_steps=300, n_pairs=32, channels=8):
     rows["mixed_f32"] = solve_row(s, st, base)
     for name, use_net in (("gcr_no_net", False), ("fgcr_net", True)):
         log(f"cfg5 {name} ...")
-        prm = bsm.solver_params(kappa, 1e-10, max_iter=20000, restart=16)
+        prm = bsm.solver_params(kappa, 1e-10, max_iter=20000, restart=8)
         s, st = ctx.bsm_fgcr_solve(d32, U32, U64, prm, channels, net if use_net else None, b, x, check=False)
         rows[name] = solve_row(s, st, base)
         rows[name].update(fell_back=st["fell_back"], precond_applies=st["precond_applies"],

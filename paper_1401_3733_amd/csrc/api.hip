@@ -27,8 +27,9 @@ bsm_status hip_check(hipError_t e, const char *what) {
 }
 
 bsm_status ctx_work_slot(bsm_ctx ctx, int slot, size_t bytes, void **out) {
-    void *&w = slot == 0 ? ctx->work : ctx->work2;
-    size_t &wb = slot == 0 ? ctx->work_bytes : ctx->work2_bytes;
+    if (slot < 0 || slot > 2) return fail(BSM_ERR_ARG, "scratch slot");
+    void *&w = ctx->work[slot];
+    size_t &wb = ctx->work_bytes[slot];
     if (bytes > wb) {
         if (w) BSM_HIP(hipFree(w));
         w = nullptr;
@@ -178,8 +179,8 @@ void bsm_ctx_destroy(bsm_ctx c) {
     if (c->partials) (void)hipFree(c->partials);
     if (c->scal) (void)hipFree(c->scal);
     if (c->host_scal) (void)hipHostFree(c->host_scal);
-    if (c->work) (void)hipFree(c->work);
-    if (c->work2) (void)hipFree(c->work2);
+    for (void *w : c->work)
+        if (w) (void)hipFree(w);
     delete c;
 }
 

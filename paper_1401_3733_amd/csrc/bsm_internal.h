@@ -171,10 +171,10 @@ struct bsm_ctx_s {
     double *partials;       // device, kMaxPartials doubles
     double *scal;           // device scalars for solvers (kScalars)
     double *host_scal;      // pinned host mirror
-    void *work;             // solver work buffer (lazily grown)
-    size_t work_bytes;
-    void *work2;            // second scratch (FGCR: its fall back CG uses work)
-    size_t work2_bytes;
+    // scratch buffers (lazily grown, zero-filled when allocated):
+    //   0: solvers, 1: FGCR (its fall back CG uses 0), 2: network layers
+    void *work[3];
+    size_t work_bytes[3];
     bsm::HopPlan plans[16][2][3][3];   // [d_R][real][spinor prec][link prec]
     bsm::BlockPlan block_plans[16];     // [d_R]
 };
@@ -183,7 +183,7 @@ namespace bsm {
 constexpr int kMaxPartials = 1 << 16;
 constexpr int kScalars = 4096;
 // scratch that persists across calls, zero-filled when (re)allocated; slot 0
-// is the solvers' buffer, slot 1 a second one for callers of the solvers
+// is the solvers' buffer, slot 1 FGCR's, slot 2 the network layers
 bsm_status ctx_work(bsm_ctx ctx, size_t bytes, void **out);
 bsm_status ctx_work_slot(bsm_ctx ctx, int slot, size_t bytes, void **out);
 }

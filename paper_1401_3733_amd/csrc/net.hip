@@ -180,17 +180,44 @@ __global__ __launch_bounds__(256) void k_zupdate(float2 *x, float2 *r, const flo
         if (_s != BSM_OK) return _s;     \
     } while (0)
 
+// one PTC layer with the matrix-core scratch (real-form weights, mixed
+// fields) from the context's layer buffer
+static size_t layer_scratch(const Geom &g, int d, int cin, int cout, size_t *na_out) {
+    const size_t na = (ptc_areal_floats(cin, cout) * sizeof(float) + 255) / 256 * 256;
+    if (na_out) *na_out = na;
+    return na + (cin > cout ? ptc_gmix_bytes(g, d, cin, cout) : 0);
+}
+
+static bsm_status layer(bsm_ctx ctx, int d, PtcArgs a, hipStream_t st) {
+    size_t na = 0;
+    const size_t need = layer_scratch(ctx->g, d, a.cin, a.cout, &na);
+    void *w = nullptr;
+    TRY(ctx_work_slot(ctx, 2, need, &w));
+    a.Areal = (float *)w;
+    a.Gmix = a.cin > a.cout ? (char *)w + na : nullptr;
+    return launch_ptc_layer(ctx->g, d, a, st);
+}
+
+// grow the layer scratch for a 1 -> C -> 1 network before any of its layers
+// is queued (the C -> 1 layer needs the most), so it is never reallocated
+// while a queued layer still reads it
+static bsm_status reserve_net(bsm_ctx ctx, int d, int C) {
+    void *w = nullptr;
+    return ctx_work_slot(ctx, 2, layer_scratch(ctx->g, d, C, 1, nullptr), &w);
+}
+
 // z = M(r) on F32 full fields; h: channels F32 full fields of scratch
 static bsm_status net_apply(bsm_ctx ctx, const bsm_field_desc *desc, const void *U, int C, const void *net,
                             const void *r, void *h, void *z, hipStream_t st) {
     const float2 *W1 = (const float2 *)net;
     const float2 *W2 = W1 + layer_weights(1, C);
+    TRY(reserve_net(ctx, desc->d_R, C));
     PtcArgs a{};
     a.U = U;
     a.W = W1; a.in = r; a.out = h; a.cin = 1; a.cout = C;
-    TRY(launch_ptc_layer(ctx->g, desc->d_R, a, st));
+    TRY(layer(ctx, desc->d_R, a, st));
     a.W = W2; a.in = h; a.out = z; a.cin = C; a.cout = 1;
-    return launch_ptc_layer(ctx->g, desc->d_R, a, st);
+    return layer(ctx, desc->d_R, a, st);
 }
 
 static uint64_t splitmix64(uint64_t x) {
@@ -219,7 +246,7 @@ bsm_status bsm_ptc_layer(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_
     if (in == out) return fail(BSM_ERR_ARG, "in and out must differ");
     PtcArgs a{};
     a.U = U_rep; a.W = W; a.in = in; a.out = out; a.cin = cin; a.cout = cout;
-    return launch_ptc_layer(ctx->g, desc->d_R, a, (hipStream_t)stream);
+    return layer(ctx, desc->d_R, a, (hipStream_t)stream);
 }
 
 bsm_status bsm_ptc_layer_adjoint(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, int32_t cin,
@@ -233,7 +260,7 @@ bsm_status bsm_ptc_layer_adjoint(bsm_ctx ctx, const bsm_field_desc *desc, const 
     TRY(launch_ptc_adjoint_weights(W, Wa, cin, cout, st));
     PtcArgs a{};
     a.U = U_rep; a.W = Wa; a.in = in; a.out = out; a.cin = cout; a.cout = cin;
-    return launch_ptc_layer(ctx->g, desc->d_R, a, st);
+    return layer(ctx, desc->d_R, a, st);
 }
 
 bsm_status bsm_ptc_weight_grad(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, int32_t cin,
@@ -313,7 +340,7 @@ bsm_status bsm_precond_train(bsm_ctx ctx, const bsm_field_desc *desc, const void
             // Gh = L2^dag Gy
             PtcArgs b{};
             b.U = U_rep; b.W = W2a; b.in = Gy; b.out = Gh; b.cin = 1; b.cout = C;
-            TRY(launch_ptc_layer(g, d, b, st));
+            TRY(layer(ctx, d, b, st));
             // dW1 += Gh conj(T r)
             a.in = r; a.G = Gh; a.cin = 1; a.cout = C;
             TRY(launch_ptc_wgrad(g, d, a, parts, grad, 1.0, true, st));

@@ -13,8 +13,14 @@ struct PtcArgs {
     void *out;          // cout F32 full fields
     const void *G;      // weight gradient: cout F32 full fields (output gradient)
     int cin, cout;
+    // matrix-core path (both nullable: then the vector-ALU kernels run)
+    float *Areal;       // real form of the mixing matrix, ptc_areal_floats()
+    char *Gmix;         // mixed fields for cin > cout: cout * 9 F32 full fields
 };
 
+// scratch of the matrix-core path
+size_t ptc_areal_floats(int cin, int cout);
+size_t ptc_gmix_bytes(const Geom &g, int d, int cin, int cout);
 bsm_status launch_ptc_layer(const Geom &g, int d, const PtcArgs &a, hipStream_t st);
 // dW (complex float, cout*cin*9*16) = scale * sum_x G (x) conj(T_p v); accumulate adds
 int ptc_wgrad_blocks(const Geom &g);

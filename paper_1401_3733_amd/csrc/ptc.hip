@@ -17,6 +17,8 @@
 
 namespace bsm {
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+
 // t = (T_p v)(x) for the site (p_x, h) with coordinates c
 template <int D>
 __device__ inline void transport(const Geom &g, const char *U, size_t lblk, const char *v_full, size_t pblk,
@@ -171,67 +173,240 @@ __global__ __launch_bounds__(256) void k_ptc_layer(Geom g, PtcArgs a, int nblk) 
     }
 }
 
-// Mix first, transport after: the spin matrix W_p^{ij} acts on spin and the
-// transport T_p on colour and position, so W_p^{ij} T_p v_j = T_p (W_p^{ij} v_j)
-// and out_i(x) = sum_p T_p g_{i,p}(x) with g_{i,p}(y) = sum_j W_p^{ij} v_j(y)
-// formed at the source site y.  The mixing work is the same as in k_ptc_layer
-// and each path needs one link product per output channel instead of one per
-// input channel: the cheaper form when cin > cout.
-template <int D, int CG>
-__global__ __launch_bounds__(256) void k_ptc_layer_mt(Geom g, PtcArgs a, int nblk) {
+// ------------------------------------------------------ matrix-core layers
+// The spin mixing is a dense complex contraction shared by every site, so it
+// runs on FP32 matrix cores (v_mfma_f32_16x16x4f32) in its real form
+//   [Re o; Im o] = [[Re W, -Im W], [Im W, Re W]] [Re t; Im t],
+// with the operand layout  A: lane l -> A[l%16][l/16],  B: lane l ->
+// B[l/16][l%16],  D: lane l -> D[4(l/16)+v][l%16], v < 4.  A wavefront owns
+// 16 consecutive sites; the N dimension of a tile is those 16 sites at one
+// colour, so the colour index never mixes.
+//   transport-then-mix (cin <= cout): rows m = (i, a, re/im), columns
+//     k = (j, p, b, re/im) of the transported fields, staged in LDS;
+//   mix-at-source (cin > cout): rows m = (i, p, a, re/im), columns
+//     k = (j, b, re/im) read straight from the input fields, giving
+//     G_{i,p} = sum_j W_p^{ij} v_j, then out_i = sum_p T_p G_{i,p}.
+__host__ __device__ inline int round16(int x) { return (x + 15) / 16 * 16; }
+
+size_t ptc_areal_floats(int cin, int cout) {
+    const size_t t = (size_t)(round16(cout * 8) + 16) * cin * 72, x = (size_t)(round16(cout * 72) + 16) * cin * 8;
+    return t > x ? t : x;
+}
+
+size_t ptc_gmix_bytes(const Geom &g, int d, int cin, int cout) {
+    return (size_t)cout * 9 * 2 * spinor_block_bytes(BSM_F32, d, g.Vh_pad);
+}
+
+// row stride of the transposed matrix: the two 16-lane row groups of a half
+// wavefront read rows k and k + 1, which then fall in disjoint LDS banks
+__host__ __device__ inline int at_stride(int Mp) { return Mp % 32 == 0 ? Mp + 16 : Mp; }
+
+// The real-form matrix, transposed: At[k * at_stride(Mp) + m] (pad entries 0).
+// mode 0: transport-then-mix layout; mode 1: mix-at-source layout
+__global__ void k_ptc_realform(const float2 *W, float *At, int cin, int cout, int mode) {
+    const int M = mode == 0 ? cout * 8 : cout * 72, Mp = round16(M), AS = at_stride(Mp);
+    const int K = mode == 0 ? cin * 72 : cin * 8;
+    const int n = AS * K;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const int k = e / AS, m = e % AS;
+        float v = 0.f;
+        if (m < M) {
+            int i, j, p, aa, bb;
+            const int ro = m & 1, ri = k & 1;
+            if (mode == 0) {
+                i = m / 8; aa = (m % 8) / 2;
+                j = k / 72; p = (k % 72) / 8; bb = (k % 8) / 2;
+            } else {
+                const int ia = m / 2;
+                i = ia / 36; p = (ia / 4) % 9; aa = ia % 4;
+                j = k / 8; bb = (k % 8) / 2;
+            }
+            const float2 w = W[(((size_t)i * cin + j) * 9 + p) * 16 + aa * 4 + bb];
+            v = ro == ri ? w.x : (ro == 0 ? -w.y : w.y);
+        }
+        At[e] = v;
+    }
+}
+
+// F32 full-field element access: complex component comp of site h in the
+// parity block starting at blk (float pointer)
+__device__ inline size_t f32_elem(int comp, int64_t stride, uint32_t h) {
+    return ((size_t)(comp >> 1) * stride + h) * 4 + (comp & 1) * 2;
+}
+
+// the real-form matrix, transposed ([k][m], Mp rows), into LDS by the
+// whole workgroup
+// Matrix-core kernels for the network's shapes (d_R <= 3): a workgroup of
+// 256 threads owns 64 consecutive sites of one parity.  Phase 1 stages the
+// B operand in LDS with one site per thread (all loads of the 64 sites in
+// flight together); phase 2 gives wavefront w the 16 sites 16w..16w+15 at
+// every colour, with the A fragments held in registers.
+constexpr int kMfmaMaxD = 3;
+
+// this lane's A fragments: a[mt][ks] = At[(4 ks + q) * AS + 16 mt + sl]
+template <int MT, int KS>
+__device__ inline void load_afrag(const float *At, int AS, int q, int sl, float (&af)[MT][KS]) {
+#pragma unroll
+    for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+        for (int ks = 0; ks < KS; ks++) af[mt][ks] = At[(size_t)(4 * ks + q) * AS + 16 * mt + sl];
+}
+
+// acc[c][mt] = sum_k A[16 mt + .][k] B[k][colour c, 16 sites]
+template <int D, int MT, int KS>
+__device__ inline void mfma_block(const float (&af)[MT][KS], const float *Bs, int w, int q, int sl,
+                                  f4v (&acc)[D][MT]) {
+#pragma unroll
+    for (int c = 0; c < D; c++)
+#pragma unroll
+        for (int mt = 0; mt < MT; mt++) acc[c][mt] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ks++) {
+        const int k = 4 * ks + q;
+        float bv[D];
+#pragma unroll
+        for (int c = 0; c < D; c++) bv[c] = Bs[((size_t)k * D + c) * 64 + 16 * w + sl];
+#pragma unroll
+        for (int c = 0; c < D; c++)
+#pragma unroll
+            for (int mt = 0; mt < MT; mt++)
+                acc[c][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mt][ks], bv[c], acc[c][mt], 0, 0, 0);
+    }
+}
+
+// transport-then-mix for cin = 1: rows m = (i, a, re/im), MT = ceil(8 cout / 16),
+// columns k = (p, b, re/im), K = 72
+template <int D, int MT>
+__global__ __launch_bounds__(256) void k_ptc_l1_mfma(Geom g, PtcArgs a, int nblk) {
+    constexpr int K = 72, KS = K / 4, Mp = 16 * MT;
+    __shared__ float Bs[K * D * 64];   // [k][colour][site]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane >> 4, sl = lane & 15;
+    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int px = lb >= (uint32_t)nblk ? 1 : 0;
+    const uint32_t hb = (lb - px * nblk) * 64;
+    const size_t pblk = spinor_block_bytes(BSM_F32, D, g.Vh_pad);
+    const size_t lblk = link_block_bytes(BSM_F32, false, D, g.Vh_pad);
+    {
+        // phase 1: site hb + (tid & 63), paths pg, pg + 4, pg + 8 with pg = tid >> 6
+        const int s = tid & 63, pg = tid >> 6;
+        const uint32_t h = hb + s;
+        const bool live = h < (uint32_t)g.Vh;
+        Coords c{};
+        if (live) c = decode(g, h, px);
+        for (int p = pg; p < 9; p += 4) {
+            cx<float> t[4 * D];
+            if (live) {
+                transport<D>(g, (const char *)a.U, lblk, (const char *)a.in, pblk, px, h, c, p, t);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4 * D; e++) t[e] = mk<float>(0.f, 0.f);
+            }
+#pragma unroll
+            for (int b = 0; b < 4; b++)
+#pragma unroll
+                for (int cc = 0; cc < D; cc++) {
+                    const int k = (p * 4 + b) * 2;
+                    Bs[((size_t)k * D + cc) * 64 + s] = t[b * D + cc].re;
+                    Bs[((size_t)(k + 1) * D + cc) * 64 + s] = t[b * D + cc].im;
+                }
+        }
+    }
+    float af[MT][KS];
+    load_afrag<MT, KS>(a.Areal, at_stride(Mp), q, sl, af);
+    __syncthreads();
+    f4v acc[D][MT];
+    mfma_block<D, MT, KS>(af, Bs, w, q, sl, acc);
+    const uint32_t h = hb + 16 * w + sl;
+    if (h >= (uint32_t)g.Vh) return;
+#pragma unroll
+    for (int cc = 0; cc < D; cc++)
+#pragma unroll
+        for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+            for (int v = 0; v < 4; v += 2) {
+                const int m = 16 * mt + 4 * q + v;   // (i, a, re); m + 1 is (i, a, im)
+                const int i = m / 8, sp = (m % 8) / 2;
+                if (i >= a.cout) continue;
+                float *oi = (float *)((char *)a.out + (size_t)i * 2 * pblk + px * pblk);
+                *(float2 *)(oi + f32_elem(sp * D + cc, g.Vh_pad, h)) = make_float2(acc[cc][mt][v], acc[cc][mt][v + 1]);
+            }
+}
+
+// mix-at-source for cout = 1: G_p(y) = sum_j W_p^{j} v_j(y); rows m = (p, a,
+// re/im) (72, MT = 5), columns k = (j, b, re/im), KS = 2 cin
+template <int D, int KS>
+__global__ __launch_bounds__(256) void k_ptc_mix1_mfma(Geom g, PtcArgs a, int nblk) {
+    constexpr int K = 4 * KS, MT = 5, Mp = 80;
+    __shared__ float Bs[K * D * 64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane >> 4, sl = lane & 15;
+    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int px = lb >= (uint32_t)nblk ? 1 : 0;
+    const uint32_t hb = (lb - px * nblk) * 64;
+    const size_t pblk = spinor_block_bytes(BSM_F32, D, g.Vh_pad);
+    {
+        const int s = tid & 63, grp = tid >> 6;
+        const uint32_t h = hb + s;
+        const bool live = h < (uint32_t)g.Vh;
+        for (int j = grp; j < K / 8; j += 4) {
+            cx<float> v[4 * D];
+            if (live) {
+                load_spinor<BSM_F32, D, float>((const char *)a.in + (size_t)j * 2 * pblk + px * pblk, g.Vh_pad, h, v);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4 * D; e++) v[e] = mk<float>(0.f, 0.f);
+            }
+#pragma unroll
+            for (int b = 0; b < 4; b++)
+#pragma unroll
+                for (int cc = 0; cc < D; cc++) {
+                    const int k = (j * 4 + b) * 2;
+                    Bs[((size_t)k * D + cc) * 64 + s] = v[b * D + cc].re;
+                    Bs[((size_t)(k + 1) * D + cc) * 64 + s] = v[b * D + cc].im;
+                }
+        }
+    }
+    float af[MT][KS];
+    load_afrag<MT, KS>(a.Areal, at_stride(Mp), q, sl, af);
+    __syncthreads();
+    f4v acc[D][MT];
+    mfma_block<D, MT, KS>(af, Bs, w, q, sl, acc);
+    const uint32_t h = hb + 16 * w + sl;
+    if (h >= (uint32_t)g.Vh) return;
+#pragma unroll
+    for (int cc = 0; cc < D; cc++)
+#pragma unroll
+        for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+            for (int v = 0; v < 4; v += 2) {
+                const int m = 16 * mt + 4 * q + v;   // (p, a, re)
+                if (m >= 72) continue;
+                const int p = m / 8, sp = (m % 8) / 2;
+                float *gf = (float *)(a.Gmix + (size_t)p * 2 * pblk + px * pblk);
+                *(float2 *)(gf + f32_elem(sp * D + cc, g.Vh_pad, h)) = make_float2(acc[cc][mt][v], acc[cc][mt][v + 1]);
+            }
+}
+
+// out_i(x) = G_{i,0}(x) + sum_{p >= 1} (T_p G_{i,p})(x); blockIdx.y = i
+template <int D>
+__global__ __launch_bounds__(256) void k_ptc_tsum(Geom g, PtcArgs a, int nblk) {
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
     const int px = lb >= (uint32_t)nblk ? 1 : 0;
     const uint32_t h = (lb - px * nblk) * 256 + threadIdx.x;
     if (h >= (uint32_t)g.Vh) return;
-    const int i0 = blockIdx.y * CG;
+    const int i = blockIdx.y;
     const size_t pblk = spinor_block_bytes(BSM_F32, D, g.Vh_pad);
     const size_t lblk = link_block_bytes(BSM_F32, false, D, g.Vh_pad);
     const Coords c = decode(g, h, px);
-    const float2 *W = (const float2 *)a.W;
-    const char *in = (const char *)a.in;
-    cx<float> acc[CG][4 * D];
-#pragma unroll
-    for (int q = 0; q < CG; q++)
-#pragma unroll
-        for (int k = 0; k < 4 * D; k++) acc[q][k] = mk<float>(0.f, 0.f);
-    // stay path: g = sum_j W_0 v_j at this site goes straight into acc
-    for (int j = 0; j < a.cin; j++) {
-        cx<float> t[4 * D];
-        load_spinor<BSM_F32, D, float>(in + (size_t)j * 2 * pblk + px * pblk, g.Vh_pad, h, t);
-        mix_spin<D, CG>(W, a.cin, a.cout, i0, j, 0, t, acc);
-    }
+    const char *G = a.Gmix + (size_t)i * 9 * 2 * pblk;
+    cx<float> acc[4 * D];
+    load_spinor<BSM_F32, D, float>(G + px * pblk, g.Vh_pad, h, acc);
     for (int p = 1; p < 9; p++) {
-        const PathSite ps = path_site(g, (const char *)a.U, lblk, px, h, c, p);
-        cx<float> gm[CG][4 * D];
+        cx<float> t[4 * D];
+        transport<D>(g, (const char *)a.U, lblk, G + (size_t)p * 2 * pblk, pblk, px, h, c, p, t);
 #pragma unroll
-        for (int q = 0; q < CG; q++)
-#pragma unroll
-            for (int k = 0; k < 4 * D; k++) gm[q][k] = mk<float>(0.f, 0.f);
-        for (int j = 0; j < a.cin; j++) {
-            cx<float> s[4 * D];
-            load_spinor<BSM_F32, D, float>(in + (size_t)j * 2 * pblk + (1 - px) * pblk, g.Vh_pad, ps.hn, s);
-            mix_spin<D, CG>(W, a.cin, a.cout, i0, j, p, s, gm);
-        }
-#pragma unroll
-        for (int e = 0; e < D * D; e++) {
-            const int i = e / D, jj = e % D;
-            const cx<float> u = ps.w * load_link<BSM_F32, false, float>(ps.blk, g.Vh_pad, e, ps.hl);
-#pragma unroll
-            for (int q = 0; q < CG; q++)
-#pragma unroll
-                for (int sa = 0; sa < 4; sa++) {
-                    if (!ps.back) acc[q][sa * D + i] = cfma(u, gm[q][sa * D + jj], acc[q][sa * D + i]);
-                    else acc[q][sa * D + jj] = cfma_conj(u, gm[q][sa * D + i], acc[q][sa * D + jj]);
-                }
-        }
+        for (int e = 0; e < 4 * D; e++) acc[e] = acc[e] + t[e];
     }
-#pragma unroll
-    for (int q = 0; q < CG; q++) {
-        const int i = i0 + q;
-        if (i >= a.cout) break;
-        char *oi = (char *)a.out + (size_t)i * 2 * pblk + px * pblk;
-        store_spinor<BSM_F32, D, float>(oi, g.Vh_pad, h, acc[q]);
-    }
+    store_spinor<BSM_F32, D, float>((char *)a.out + (size_t)i * 2 * pblk + px * pblk, g.Vh_pad, h, acc);
 }
 
 // Wa[j][i][rev p] = W[i][j][p]^dag
@@ -350,16 +525,34 @@ struct PtcByD {
                 // next to a D x D link and two spinors
                 constexpr int CG = D <= 3 ? 4 : D <= 4 ? 2 : 1;
                 dim3 grid(2 * nblk, (a.cout + CG - 1) / CG);
-                if (a.cin > a.cout) {
-                    // a mixed field per output channel of the thread's group
-                    // sits next to the accumulators
-                    if (D <= 3 && a.cout > 1) {
-                        dim3 gm(2 * nblk, (a.cout + 1) / 2);
-                        k_ptc_layer_mt<D, 2><<<gm, 256, 0, st>>>(g, a, nblk);
-                    } else {
-                        dim3 gm(2 * nblk, a.cout);
-                        k_ptc_layer_mt<D, 1><<<gm, 256, 0, st>>>(g, a, nblk);
+                const int nb64 = (g.Vh + 63) / 64;
+                if (a.Areal && D <= kMfmaMaxD && a.cin == 1 && a.cout <= 8) {
+                    const int MT = (8 * a.cout + 15) / 16;
+                    const int n = at_stride(16 * MT) * 72;
+                    k_ptc_realform<<<(n + 255) / 256, 256, 0, st>>>((const float2 *)a.W, a.Areal, 1, a.cout, 0);
+                    if constexpr (D <= kMfmaMaxD) {
+                        switch (MT) {
+                        case 1: k_ptc_l1_mfma<D, 1><<<2 * nb64, 256, 0, st>>>(g, a, nb64); break;
+                        case 2: k_ptc_l1_mfma<D, 2><<<2 * nb64, 256, 0, st>>>(g, a, nb64); break;
+                        case 3: k_ptc_l1_mfma<D, 3><<<2 * nb64, 256, 0, st>>>(g, a, nb64); break;
+                        default: k_ptc_l1_mfma<D, 4><<<2 * nb64, 256, 0, st>>>(g, a, nb64); break;
+                        }
                     }
+                } else if (a.Areal && a.Gmix && D <= kMfmaMaxD && a.cout == 1 && a.cin >= 2 && a.cin <= 8) {
+                    const int n = at_stride(80) * 8 * a.cin;
+                    k_ptc_realform<<<(n + 255) / 256, 256, 0, st>>>((const float2 *)a.W, a.Areal, a.cin, 1, 1);
+                    if constexpr (D <= kMfmaMaxD) {
+                        switch (a.cin) {
+                        case 2: k_ptc_mix1_mfma<D, 4><<<2 * nb64, 256, 0, st>>>(g, a, nb64); break;
+                        case 3: k_ptc_mix1_mfma<D, 6><<<2 * nb64, 256, 0, st>>>(g, a, nb64); break;
+                        case 4: k_ptc_mix1_mfma<D, 8><<<2 * nb64, 256, 0, st>>>(g, a, nb64); break;
+                        case 5: k_ptc_mix1_mfma<D, 10><<<2 * nb64, 256, 0, st>>>(g, a, nb64); break;
+                        case 6: k_ptc_mix1_mfma<D, 12><<<2 * nb64, 256, 0, st>>>(g, a, nb64); break;
+                        case 7: k_ptc_mix1_mfma<D, 14><<<2 * nb64, 256, 0, st>>>(g, a, nb64); break;
+                        default: k_ptc_mix1_mfma<D, 16><<<2 * nb64, 256, 0, st>>>(g, a, nb64); break;
+                        }
+                    }
+                    k_ptc_tsum<D><<<dim3(2 * nblk, 1), 256, 0, st>>>(g, a, nblk);
                 } else {
                     k_ptc_layer<D, CG><<<grid, 256, 0, st>>>(g, a, nblk);
                 }
