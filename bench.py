@@ -279,7 +279,7 @@ def bench_cfg4(bsm, gen):
     return out
 
 
-def bench_cfg5(bsm, gen, train_steps=300, n_pairs=32, channels=8):
+def bench_cfg5(bsm, gen, train_steps=300, n_pairs=32, channels=8, large_dims=True):
     """FGCR with the trained PTC network, 16^3 x 32 SU(3), kappa 0.1335."""
     import torch
     c = gen.CONFIGS[5]
@@ -338,16 +338,59 @@ def bench_cfg5(bsm, gen, train_steps=300, n_pairs=32, channels=8):
                           x_rel_diff_vs_plain=rel_diff(ctx, d64, x, x0))
         log(f"  {rows[name]}")
     gain = base - rows["fgcr_net"]["seconds"]
+    ctx.close()
+    torch.cuda.empty_cache()
+    large = bench_cfg5_large(bsm, gen, net, channels, kappa) if large_dims else None
     out = {"workload": "16^3x32 SU(3) fund, exp(0.5iH) links, kappa 0.1335, 1e-10 true residual",
            "net": f"2 PTC layers 1->{channels}->1, 9 paths, FP32",
            "training": dict(pairs=n_pairs, snapshot_iters=[0], steps=train_steps, batch=4, lr=5e-3,
                             seconds=round(t_train, 3), pairs_seconds=round(t_pairs, 3),
                             loss_first=losses[0], loss_last20=float(np.mean(losses[-20:]))),
            "solves": rows,
-           "break_even_solves": (round(t_train / gain, 1) if gain > 0 else None)}
+           "break_even_solves": (round(t_train / gain, 1) if gain > 0 else None),
+           "same_net_on_32x32x32x64": large}
+    return out
+
+
+def bench_cfg5_large(bsm, gen, net, channels, kappa):
+    """The network trained on 16^3 x 32 applied, unchanged, on a 32^3 x 64
+    lattice of the same link distribution (exp(0.5iH), own seeds): the layers
+    are local and gauge covariant, so the weights do not depend on the volume."""
+    import torch
+    lat = gen.Lattice(64, 32, 32, 32, bc=(-1, 1, 1, 1))
+    log("cfg5 transfer: generating 32^3x64 exp(0.5iH) links ...")
+    Uf = bsm.to_device_c128(gen.gauge_links(lat, 3, "near_identity", gen.SEED_GAUGE + 105, eps=0.5))
+    ctx = bsm.Context(lat.dims, lat.bc)
+    d64, d32 = bsm.desc(3, "fund", "f64"), bsm.desc(3, "fund", "f32")
+    U64, U32 = ctx.new_gauge(d64), ctx.new_gauge(d32)
+    ctx.bsm_gauge_represent(d64, Uf, U64)
+    ctx.bsm_gauge_represent(d32, Uf, U32)
+    del Uf
+    b = ctx.new_spinor(d64)
+    ctx.bsm_pack_spinor(d64, bsm.to_device_c128(gen.gaussian_spinor(lat, 3, gen.SEED_SOURCE + 105)), b)
+    x, x0 = ctx.new_spinor(d64), ctx.new_spinor(d64)
+    rows = {}
+    log("cfg5 transfer: plain FP64 Schur CG ...")
+    s, st = ctx.bsm_cg_solve(d64, U64, U64, bsm.solver_params(kappa, 1e-10, schur=True), b, x0, check=False)
+    base = st["seconds"]
+    rows["plain_f64"] = solve_row(s, st)
+    log(f"  {rows['plain_f64']}")
+    s, st = ctx.bsm_cg_solve(d32, U32, U64, bsm.solver_params(kappa, 1e-10, schur=True, variant=bsm.SOLVER_MIXED),
+                             b, x, check=False)
+    rows["mixed_f32"] = solve_row(s, st, base)
+    log(f"  mixed_f32 {rows['mixed_f32']}")
+    for name, use_net in (("gcr_no_net", False), ("fgcr_net", True)):
+        log(f"cfg5 transfer: {name} ...")
+        prm = bsm.solver_params(kappa, 1e-10, max_iter=20000, restart=8)
+        s, st = ctx.bsm_fgcr_solve(d32, U32, U64, prm, channels, net if use_net else None, b, x, check=False)
+        rows[name] = solve_row(s, st, base)
+        rows[name].update(fell_back=st["fell_back"], precond_applies=st["precond_applies"],
+                          x_rel_diff_vs_plain=rel_diff(ctx, d64, x, x0))
+        log(f"  {rows[name]}")
     ctx.close()
     torch.cuda.empty_cache()
-    return out
+    return {"workload": "32^3x64 SU(3) fund, exp(0.5iH) links (seed 1105), kappa 0.1335, net trained on 16^3x32",
+            "solves": rows}
 
 
 def _init_weights(channels, seed):

@@ -153,9 +153,12 @@ bsm_status bsm_dslash_eo(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_
  *   order 2: as order 0 without the per-XCD regrouping;
  *   order 3: column sweep: one thread per spatial site over tchunk
  *            consecutive time slices, time neighbours reused from registers
- *            (d_R <= 6).
+ *            (d_R <= 6);
+ *   order 4: XCD bands: each of the 8 XCDs owns 1/8 of the 256-site tiles
+ *            of every time slice and walks its band t-major, so time
+ *            neighbours are re-read from its own L2 (tchunk ignored).
  * Orders 1 and 3 need LX*LY*LZ/2 to be a multiple of 256 and T a multiple
- * of tchunk; BSM_ERR_ARG otherwise.  Links are always streamed with
+ * of tchunk, order 4 LX*LY*LZ/2 a multiple of 2048; BSM_ERR_ARG otherwise.  Links are always streamed with
  * non-temporal loads. */
 bsm_status bsm_set_hop_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t order, int32_t tchunk);
 /* us: measured time per hop of the chosen plan (0 if never tuned) */

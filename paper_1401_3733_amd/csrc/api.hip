@@ -56,6 +56,7 @@ static bool plan_fits(const Geom &g, const HopPlan &p, int d) {
     if (p.order == 0 || p.order == 2) return true;
     if (p.order == 3 && d > kColMaxD) return false;
     int64_t S3 = (int64_t)g.Vh / g.L[0];
+    if (p.order == 4) return S3 % (256 * kXcds) == 0;
     return p.tchunk >= 1 && S3 % 256 == 0 && g.L[0] % p.tchunk == 0;
 }
 
@@ -443,7 +444,7 @@ bsm_status bsm_set_hop_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t ord
     HopPlan p;
     p.order = order;
     p.tchunk = tchunk;
-    if (order < 0 || order > 3) return fail(BSM_ERR_ARG, "order must be 0, 1, 2 or 3");
+    if (order < 0 || order > 4) return fail(BSM_ERR_ARG, "order must be 0 ... 4");
     if (!plan_fits(ctx->g, p, desc->d_R)) return fail(BSM_ERR_ARG, "plan does not tile this lattice");
     ctx->plans[desc->d_R][desc->rep == BSM_REP_ADJ][desc->prec][desc->link_prec] = p;
     return BSM_OK;
@@ -464,6 +465,9 @@ bsm_status bsm_autotune(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_r
     {
         HopPlan p;
         cand.push_back(p);
+        p.order = 4;
+        p.tchunk = 1;
+        if (plan_fits(g, p, desc->d_R)) cand.push_back(p);
         for (int order : {1, 3})
             for (int tc : {2, 4, 8, 16, 32}) {
                 p.order = order;

@@ -69,6 +69,9 @@ struct HopArgs {
     //   order 2: as order 0 but workgroups are not regrouped per XCD
     //   order 3: column sweep, one thread per spatial site over tchunk time
     //            slices (time neighbours reused from registers)
+    //   order 4: XCD bands: each XCD owns 1/8 of the 256-site tiles of every
+    //            time slice and walks them t-major (sites per slice must be a
+    //            multiple of 2048)
     // Links are always streamed with non-temporal loads (each link is used
     // once per hop, so it should not displace spinors from L2).
     int order, tchunk;

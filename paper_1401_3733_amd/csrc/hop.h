@@ -224,10 +224,26 @@ __device__ inline uint32_t plan_site(const HopArgs &a, uint32_t bl, uint32_t S3,
 template <int D, bool REAL, int SP, int LP>
 __global__ __launch_bounds__(256) BSM_HOP_ATTR void k_hop(Geom g, HopArgs a, int nblk) {
     using T = typename Compute<SP>::T;
-    const uint32_t lb = a.order == 2 ? blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
-    const int pi = lb >= (uint32_t)nblk ? 1 : 0;
     const uint32_t S3 = (uint32_t)g.Vh / (uint32_t)g.L[0];
-    const uint32_t h = plan_site(a, lb - pi * nblk, S3, S3 / 256);
+    uint32_t lb;
+    int pi;
+    uint32_t h;
+    if (a.order == 4) {
+        // XCD bands: XCD e (the hardware deals workgroups to the 8 XCDs in
+        // turn) owns the band [e B/8, (e+1) B/8) of the B tiles of every time
+        // slice and walks it t-major, so a time neighbour was fetched by the
+        // same XCD a few workgroups earlier and is still in its L2
+        const uint32_t e = blockIdx.x % kXcds, k = blockIdx.x / kXcds;
+        const uint32_t B = S3 / 256, B8 = B / kXcds, per_par = (uint32_t)g.L[0] * B8;
+        pi = (int)(k / per_par);
+        const uint32_t r = k - pi * per_par, t = r / B8, j = r - t * B8;
+        lb = blockIdx.x;
+        h = (t * B + e * B8 + j) * 256 + threadIdx.x;
+    } else {
+        lb = a.order == 2 ? blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
+        pi = lb >= (uint32_t)nblk ? 1 : 0;
+        h = plan_site(a, lb - pi * nblk, S3, S3 / 256);
+    }
     const int p = a.p0 + pi;
     const bool active = h < (uint32_t)g.Vh;
     const size_t lblk = link_block_bytes(LP, REAL, D, g.Vh_pad);

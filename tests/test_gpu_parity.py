@@ -241,3 +241,40 @@ def test_hop_full_size_sampled(cfg, prec, lprec, tol):
         err = rel(got[sample], ref)
         print(f"cfg{cfg} {prec}/{lprec} parity {p}: sampled rel L2 error {err:.3e}")
         assert err <= tol
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 1e-6), ("f16s", 2e-3)])
+@pytest.mark.parametrize("bc", [(-1, 1, 1, 1), (1, -1, -1, 1)])
+def test_xcd_band_plan_gives_the_same_operator(prec, tol, bc):
+    note(f"plan order=4 prec={prec} bc={bc}")
+    lat = gen.Lattice(4, 16, 16, 16, bc=bc)   # 2048 sites per parity and time slice: 8 bands of one tile
+    Uf = _links(lat, 3, 610)
+    S = Setup(lat, 3, "fund", Uf, prec=prec)
+    S.ctx.bsm_set_hop_plan(S.desc, 4, 1)
+    assert S.ctx.bsm_get_hop_plan(S.desc)["order"] == 4
+    psi = gen.gaussian_spinor(lat, 3, 611)
+    for dag in (0, 1):
+        out = S.ctx.new_spinor(S.desc)
+        S.ctx.bsm_dslash_apply(S.desc, S.U, KAPPA, dag, S.pack(psi), out)
+        assert rel(S.unpack(out), oracle.dslash(lat, Uf, KAPPA, psi, dagger=bool(dag))) <= tol
+    par = oracle.parity_mask(lat)
+    inp = S.pack(psi)
+    out = S.ctx.new_spinor(S.desc)
+    S.ctx.bsm_dslash_eo(S.desc, S.U, 0, 1, 0.5, S.block(inp, 0), 2.0, S.block(inp, 1), S.block(out, 0))
+    ref = 0.5 * psi + 2.0 * oracle.hop(lat, Uf, psi, dagger=True, parity=0)
+    assert rel(S.unpack(out)[par == 0], ref[par == 0]) <= tol
+    if prec == "f64":
+        # the fused norms of the CG path under this plan: a Schur solve
+        from paper_1401_3733_amd import bsm as _b
+        import torch
+        x = torch.zeros_like(inp)
+        st, stats = S.ctx.bsm_cg_solve(S.desc, S.U, S.U, _b.solver_params(KAPPA, 1e-10, schur=True), inp, x)
+        assert st == 0 and oracle.true_residual(lat, Uf, KAPPA, psi, S.unpack(x)) <= 1e-10
+
+
+def test_xcd_band_plan_needs_whole_bands():
+    lat = gen.Lattice(4, 8, 8, 8)                      # 256 sites per slice: no 8 bands
+    S = Setup(lat, 3, "fund", _links(lat, 3, 612), prec="f32")
+    from paper_1401_3733_amd import bsm as _b
+    with pytest.raises(_b.BsmError):
+        S.ctx.bsm_set_hop_plan(S.desc, 4, 1)
