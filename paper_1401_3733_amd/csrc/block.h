@@ -62,8 +62,11 @@ bsm_status block_xpay(const Geom &g, int d, int nblk, float2 *p, const float2 *r
 bsm_status block_norm(const Geom &g, int d, int nblk, const float2 *v, double *partials, hipStream_t st);
 // per-RHS scalars: op 0: pAp -> alpha ; op 1: rr_new -> beta, rr, hist ; op 2: rr, hist
 // alpha/beta are zero for RHS whose mask entry is 0
+// (long partial lists are first summed in parallel into presum, which holds
+// kBlockPresum * kNR doubles; nullable)
+constexpr int kBlockPresum = 1024;
 bsm_status block_scalars(const double *partials, int nparts, double *scal, const int *mask, int op,
-                         int hist_slot, hipStream_t st);
+                         int hist_slot, double *presum, hipStream_t st);
 
 // device scalar layout for the batched solver (kNR doubles each)
 enum { B_RR = 0, B_PAP = 1, B_ALPHA = 2, B_BETA = 3, B_HIST = 4 };

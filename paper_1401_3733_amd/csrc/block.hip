@@ -471,9 +471,32 @@ __global__ __launch_bounds__(256) void k_block_scalars(const double *partials, i
     }
 }
 
+// first stage of a long per-RHS sum: workgroup b adds the contiguous range
+// [b chunk, (b + 1) chunk) of the partials (fixed order) into out[b][r]
+__global__ __launch_bounds__(256) void k_block_presum(const double *partials, int nparts, int chunk, double *out) {
+    const int r = threadIdx.x % kNR, grp = threadIdx.x / kNR;
+    const int i0 = blockIdx.x * chunk, i1 = min(nparts, i0 + chunk);
+    double s = 0;
+    for (int i = i0 + grp; i < i1; i += 16) s += partials[(size_t)i * kNR + r];
+    __shared__ double ws[16][kNR];
+    ws[grp][r] = s;
+    __syncthreads();
+    if (threadIdx.x >= kNR) return;
+    double tot = 0;
+    for (int k = 0; k < 16; k++) tot += ws[k][r];
+    out[(size_t)blockIdx.x * kNR + r] = tot;
+}
+
 bsm_status block_scalars(const double *partials, int nparts, double *scal, const int *mask, int op,
-                         int hist_slot, hipStream_t st) {
-    k_block_scalars<<<1, 256, 0, st>>>(partials, nparts, scal, mask, op, hist_slot);
+                         int hist_slot, double *presum, hipStream_t st) {
+    if (nparts > 4 * kBlockPresum && presum) {
+        const int chunk = (nparts + kBlockPresum - 1) / kBlockPresum;
+        const int nb = (nparts + chunk - 1) / chunk;
+        k_block_presum<<<nb, 256, 0, st>>>(partials, nparts, chunk, presum);
+        k_block_scalars<<<1, 256, 0, st>>>(presum, nb, scal, mask, op, hist_slot);
+    } else {
+        k_block_scalars<<<1, 256, 0, st>>>(partials, nparts, scal, mask, op, hist_slot);
+    }
     BSM_HIP(hipGetLastError());
     return BSM_OK;
 }

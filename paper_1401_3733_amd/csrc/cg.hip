@@ -487,7 +487,7 @@ struct BlockSolve {
     // FP32 block fields
     float *Ublk;
     float2 *p, *t, *q, *xlo, *rlo, *tmpB;
-    double *partials, *scal;
+    double *partials, *scal, *presum;
     int *mask;
     hipGraphExec_t graph = nullptr;
     int K;
@@ -531,10 +531,10 @@ static bsm_status block_iteration(BlockSolve &B, int k) {
     TRY(block_xpay(g, B.d, 1, B.p, B.rlo, B.scal + B_BETA * kNR, B.st));
     int np = 0;
     TRY(block_op(B, 0, B.p, B.t, true, &np));
-    TRY(block_scalars(B.partials, np, B.scal, B.mask, 0, 0, B.st));
+    TRY(block_scalars(B.partials, np, B.scal, B.mask, 0, 0, B.presum, B.st));
     TRY(block_op(B, 1, B.t, B.q, false, nullptr));
     TRY(block_update(g, B.d, 1, B.xlo, B.p, B.rlo, B.q, B.scal + B_ALPHA * kNR, B.partials, B.st));
-    TRY(block_scalars(B.partials, block_blas_grid(g, B.d, 1), B.scal, B.mask, 1, k, B.st));
+    TRY(block_scalars(B.partials, block_blas_grid(g, B.d, 1), B.scal, B.mask, 1, k, B.presum, B.st));
     return BSM_OK;
 }
 
@@ -546,9 +546,9 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
     const size_t linkB = block_link_bytes(g, d);
     // partials for any plan (the autotuner below may change it)
     const size_t parts = std::max((size_t)hop_block_grid_max(g), (size_t)block_blas_grid(g, d, 1)) * kNR;
-    // 15 carve-outs below, each rounded up to 256 bytes
+    // 16 carve-outs below, each rounded up to 256 bytes
     size_t need = linkB + 6 * B.bbB + (size_t)(2 * n + 3) * B.bb64 + 2 * B.bb64 + parts * 8 +
-                  block_scal_doubles() * 8 + 64 * sizeof(int) + 16 * 256;
+                  (size_t)kBlockPresum * kNR * 8 + block_scal_doubles() * 8 + 64 * sizeof(int) + 17 * 256;
     void *work = nullptr;
     TRY(ctx_work(B.ctx, need, &work));
     char *w = (char *)work;
@@ -559,6 +559,7 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
     B.bh = take(n * B.bb64); B.r64 = take(n * B.bb64);
     B.t64 = take(B.bb64); B.tmp64 = take(B.bb64); B.tfull = take(2 * B.bb64);
     B.partials = (double *)take(parts * 8);
+    B.presum = (double *)take((size_t)kBlockPresum * kNR * 8);
     B.scal = (double *)take(block_scal_doubles() * 8);
     B.mask = (int *)take(64 * sizeof(int));
     // ---- links in block layout, per-RHS FP64 operators and right-hand sides
