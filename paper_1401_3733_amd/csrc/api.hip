@@ -65,6 +65,7 @@ void apply_plan(bsm_ctx ctx, int d, bool real, int prec, int link_prec, HopArgs 
     if (!plan_fits(ctx->g, p, d)) p = HopPlan{};
     a.order = p.order;
     a.tchunk = p.tchunk;
+    a.wide = hop_wide_of(d, prec);
 }
 
 template <int SP, int LP>

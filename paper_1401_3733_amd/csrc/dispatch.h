@@ -75,13 +75,30 @@ struct HopArgs {
     // Links are always streamed with non-temporal loads (each link is used
     // once per hop, so it should not displace spinors from L2).
     int order, tchunk;
+    // colour split (set by apply_plan from d_R and precision, 0 = off):
+    // G threads share one output site, thread g owning colours g, g+G, ...,
+    // for the FP64 operators whose one-site-per-thread form spills
+    int wide;
 };
+
+// colour split used for (d_R, spinor precision): FP64 from d_R = 7 on (measured:
+// equal at d_R = 6, 1.4x faster at d_R = 15 than one thread per site)
+#ifndef BSM_WIDE_MIN_D
+#define BSM_WIDE_MIN_D 7
+#endif
+inline int hop_wide_of(int d, int prec) {
+    return prec == BSM_F64 && d >= BSM_WIDE_MIN_D ? (d <= 8 ? 2 : 4) : 0;
+}
 
 // largest d_R compiled with the column sweep (its register ring grows with d_R)
 constexpr int kColMaxD = 6;
 
 // workgroups of a hop launch under its plan (= number of norm partials)
 inline int hop_grid(const Geom &g, const HopArgs &a) {
+    if (a.wide > 0) {
+        const int spw = 256 / a.wide;   // sites per workgroup
+        return (g.Vh + spw - 1) / spw * a.np;
+    }
     int per = (g.Vh + 255) / 256;
     if (a.order == 3) per = (g.Vh / g.L[0] / 256) * (g.L[0] / a.tchunk);
     return per * a.np;

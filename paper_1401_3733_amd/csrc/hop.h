@@ -359,12 +359,192 @@ __global__ __launch_bounds__(256) void k_hop_col(Geom g, HopArgs a, int nblk) {
 // Launch for one (spinor precision, link precision, d_R); the definitions are
 // explicitly instantiated in the hop_*.hip sources (split so they build in
 // parallel).
+// ------------------------------------------------------------ colour split
+// FP64 spinors with large d_R: one thread per site would hold 4d complex
+// accumulators, 4d complex neighbour components and a link row in FP64 and
+// spill.  Here G threads share a site: thread (g, site) loads colours
+// j = g, g+G, ... of each neighbour, projects them (the projection is
+// colour-diagonal) into LDS, and after a barrier forms rows i = g, g+G, ...
+// of U h from the whole half spinor, accumulating its own output colours.
+// A workgroup holds 256/G sites; each wavefront has one colour group and 64
+// consecutive sites, so every plane access is coalesced.
+template <int MU>
+__device__ inline void project1(const double2 (&s)[4], double sg, double2 &h0, double2 &h1) {
+    const double2 s0 = s[0], s1 = s[1], s2 = s[2], s3 = s[3];
+    if constexpr (MU == 0) {
+        h0 = make_double2(fma(-sg, s2.x, s0.x), fma(-sg, s2.y, s0.y));
+        h1 = make_double2(fma(-sg, s3.x, s1.x), fma(-sg, s3.y, s1.y));
+    } else if constexpr (MU == 1) {
+        h0 = make_double2(fma(-sg, s3.y, s0.x), fma(sg, s3.x, s0.y));
+        h1 = make_double2(fma(-sg, s2.y, s1.x), fma(sg, s2.x, s1.y));
+    } else if constexpr (MU == 2) {
+        h0 = make_double2(fma(sg, s3.x, s0.x), fma(sg, s3.y, s0.y));
+        h1 = make_double2(fma(-sg, s2.x, s1.x), fma(-sg, s2.y, s1.y));
+    } else {
+        h0 = make_double2(fma(-sg, s2.y, s0.x), fma(sg, s2.x, s0.y));
+        h1 = make_double2(fma(sg, s3.y, s1.x), fma(-sg, s3.x, s1.y));
+    }
+}
+
+// acc (4 spins of one colour) += reconstruction of (g0, g1)
+template <int MU>
+__device__ inline void reconstruct1(cx<double> (&acc)[4], double sg, double w, cx<double> g0, cx<double> g1) {
+    const double v = -sg * w;
+    acc[0].re = fma(w, g0.re, acc[0].re); acc[0].im = fma(w, g0.im, acc[0].im);
+    acc[1].re = fma(w, g1.re, acc[1].re); acc[1].im = fma(w, g1.im, acc[1].im);
+    cx<double> &a2 = acc[2], &a3 = acc[3];
+    if constexpr (MU == 0) {
+        a2.re = fma(v, g0.re, a2.re); a2.im = fma(v, g0.im, a2.im);
+        a3.re = fma(v, g1.re, a3.re); a3.im = fma(v, g1.im, a3.im);
+    } else if constexpr (MU == 1) {
+        a2.re = fma(-v, g1.im, a2.re); a2.im = fma(v, g1.re, a2.im);
+        a3.re = fma(-v, g0.im, a3.re); a3.im = fma(v, g0.re, a3.im);
+    } else if constexpr (MU == 2) {
+        a2.re = fma(v, g1.re, a2.re); a2.im = fma(v, g1.im, a2.im);
+        a3.re = fma(-v, g0.re, a3.re); a3.im = fma(-v, g0.im, a3.im);
+    } else {
+        a2.re = fma(-v, g0.im, a2.re); a2.im = fma(v, g0.re, a2.im);
+        a3.re = fma(v, g1.im, a3.re); a3.im = fma(-v, g1.re, a3.im);
+    }
+}
+
+template <int MU, int D, bool REAL, int LP, int G>
+__device__ inline void hop_dir_wide(const Geom &g, const Coords &c, bool active, int p, uint32_t h, const char *U,
+                                    size_t lblk, const char *in, double eta, int gi, int sl, double2 *hs,
+                                    cx<double> (&acc)[(D + G - 1) / G][4]) {
+    constexpr int NC = (D + G - 1) / G, SPW = 256 / G;
+#pragma unroll
+    for (int dir = 0; dir < 2; dir++) {
+        const bool back = dir == 1;
+        float wf = 1.f;
+        const uint32_t hn = active ? neighbour<MU>(g, c, back, wf) : 0u;
+        const double sg = back ? -eta : eta;
+        const double2 *sp = (const double2 *)in;
+        // my colours of the neighbour, projected, into LDS [half][colour][site]
+#pragma unroll
+        for (int k = 0; k < NC; k++) {
+            const int j = gi + G * k;
+            if (j < D) {
+                double2 sv[4], h0 = make_double2(0.0, 0.0), h1 = h0;
+                if (active) {
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; s4++) sv[s4] = sp[(size_t)(s4 * D + j) * g.Vh_pad + hn];
+                    project1<MU>(sv, sg, h0, h1);
+                }
+                hs[(0 * D + j) * SPW + sl] = h0;
+                hs[(1 * D + j) * SPW + sl] = h1;
+            }
+        }
+        __syncthreads();
+        const char *blk = back ? link_block<MU, true>(U, lblk, p) : link_block<MU, false>(U, lblk, p);
+        const uint32_t hl = back ? hn : h;
+#pragma unroll
+        for (int k = 0; k < NC; k++) {
+            const int i = gi + G * k;
+            if (i < D && active) {
+                // the whole link row (forward) or column (backward) in flight first
+                cx<double> u[D];
+#pragma unroll
+                for (int j = 0; j < D; j++)
+                    u[j] = load_link<LP, REAL, double, true>(blk, g.Vh_pad, back ? j * D + i : i * D + j, hl);
+                cx<double> g0 = mk<double>(0.0, 0.0), g1 = g0;
+#pragma unroll
+                for (int j = 0; j < D; j++) {
+                    const double2 a0 = hs[(0 * D + j) * SPW + sl], a1 = hs[(1 * D + j) * SPW + sl];
+                    const cx<double> h0 = mk<double>(a0.x, a0.y), h1 = mk<double>(a1.x, a1.y);
+                    if (!back) {
+                        g0 = cfma(u[j], h0, g0);
+                        g1 = cfma(u[j], h1, g1);
+                    } else {
+                        // (U^dag h)_i = sum_j conj(U_ji) h_j
+                        g0 = cfma_conj(u[j], h0, g0);
+                        g1 = cfma_conj(u[j], h1, g1);
+                    }
+                }
+                reconstruct1<MU>(acc[k], sg, (double)wf, g0, g1);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int D, bool REAL, int LP, int G>
+__global__ __launch_bounds__(256) void k_hop_wide(Geom g, HopArgs a, int nblk) {
+    constexpr int NC = (D + G - 1) / G, SPW = 256 / G;
+    __shared__ double2 hs[2 * D * SPW];
+    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int pi = lb >= (uint32_t)nblk ? 1 : 0;
+    const int p = a.p0 + pi;
+    const int gi = threadIdx.x / SPW, sl = threadIdx.x % SPW;
+    const uint32_t h = (lb - pi * nblk) * SPW + sl;
+    const bool active = h < (uint32_t)g.Vh;
+    const size_t lblk = link_block_bytes(LP, REAL, D, g.Vh_pad);
+    cx<double> acc[NC][4];
+#pragma unroll
+    for (int k = 0; k < NC; k++)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; s4++) acc[k][s4] = mk<double>(0.0, 0.0);
+    Coords c{};
+    if (active) c = decode(g, h, p);
+    const char *in = (const char *)a.in[p];
+    const char *U = (const char *)a.U;
+    const double eta = a.dagger ? -1.0 : 1.0;
+    hop_dir_wide<0, D, REAL, LP, G>(g, c, active, p, h, U, lblk, in, eta, gi, sl, hs, acc);
+    hop_dir_wide<1, D, REAL, LP, G>(g, c, active, p, h, U, lblk, in, eta, gi, sl, hs, acc);
+    hop_dir_wide<2, D, REAL, LP, G>(g, c, active, p, h, U, lblk, in, eta, gi, sl, hs, acc);
+    hop_dir_wide<3, D, REAL, LP, G>(g, c, active, p, h, U, lblk, in, eta, gi, sl, hs, acc);
+    double nrm = 0.0;
+    if (active) {
+        const double bb = a.b, aa = a.a;
+        const double2 *x = (const double2 *)a.x[p];
+        double2 *o = (double2 *)a.out[p];
+#pragma unroll
+        for (int k = 0; k < NC; k++) {
+            const int i = gi + G * k;
+            if (i >= D) continue;
+#pragma unroll
+            for (int s4 = 0; s4 < 4; s4++) {
+                const size_t e = (size_t)(s4 * D + i) * g.Vh_pad + h;
+                double re = bb * acc[k][s4].re, im = bb * acc[k][s4].im;
+                if (aa != 0.0) {
+                    const double2 xv = x[e];
+                    re = fma(aa, xv.x, re);
+                    im = fma(aa, xv.y, im);
+                }
+                typedef double f64x2w __attribute__((ext_vector_type(2)));
+                f64x2w v = {re, im};
+                __builtin_nontemporal_store(v, (f64x2w *)o + e);
+                nrm += re * re + im * im;
+            }
+        }
+    }
+    if (a.norm_partials) {
+        const double s = block_sum_256(nrm);
+        if (threadIdx.x == 0) a.norm_partials[lb] = s;
+    }
+}
+
 template <int SP, int LP, int D>
 bsm_status hop_run(const Geom &g, bool real, const HopArgs &a, hipStream_t st) {
     const int grid = hop_grid(g, a);
     const int nblk = grid / a.np;
     if (real && !(D == 3 || D == 8 || D == 15))
         return fail(BSM_ERR_UNSUPPORTED, "real links only for adjoint d_R 3, 8, 15");
+    if (a.wide > 0) {
+        if constexpr (SP == BSM_F64 && D >= 5) {
+            if (a.wide != (D <= 8 ? 2 : 4)) return fail(BSM_ERR_ARG, "colour split does not match d_R");
+            constexpr int G = D <= 8 ? 2 : 4;
+            if (real) {
+                if constexpr (D == 8 || D == 15) k_hop_wide<D, true, LP, G><<<grid, 256, 0, st>>>(g, a, nblk);
+            } else {
+                k_hop_wide<D, false, LP, G><<<grid, 256, 0, st>>>(g, a, nblk);
+            }
+            BSM_HIP(hipGetLastError());
+            return BSM_OK;
+        } else {
+            return fail(BSM_ERR_ARG, "colour split only for FP64 spinors with d_R >= 5");
+        }
+    }
     if (a.order == 3) {
         if constexpr (D <= kColMaxD) {
             if (real) {
