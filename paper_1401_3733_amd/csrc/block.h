@@ -39,6 +39,32 @@ inline int hop_block_grid_max(const Geom &g) { return g.Vh; }
 bsm_status block_autotune(bsm_ctx ctx, int d, const float *U_block, float2 *scratch_in, float2 *scratch_out,
                           hipStream_t st);
 
+// FP64 block fields (the batched solver's reliable updates): [h][c][spin][rhs]
+// double2, links [q][mu][h][i*d + j] double
+inline size_t block64_parity_bytes(const Geom &g, int d) { return (size_t)d * 4 * kNR * 16 * g.Vh_pad; }
+inline size_t block64_link_bytes(const Geom &g, int d) { return (size_t)8 * g.Vh_pad * d * d * 8; }
+
+struct BlockHop64Args {
+    const double *U;
+    const double2 *in[2];
+    const double2 *x[2];
+    double2 *out[2];
+    double a[kNR], b[kNR];   // out_r = a_r x_r + b_r H in_r
+    int use_x;
+    int dagger;
+    int p0, np;
+};
+bsm_status launch_hop_block64(const Geom &g, int d, const BlockHop64Args &a, hipStream_t st);
+bsm_status launch_gauge_to_block64(const Geom &g, int d, const void *U_rep64, double *U_block, hipStream_t st);
+// mode 0: block = the parity block at std_off of the n_rhs F64 fields (stride std_stride), zero slots beyond;
+// mode 1: block32 = (float) block for the RHS selected in sel
+bsm_status launch_block64_io(const Geom &g, int d, int n_rhs, unsigned sel, const char *std64, size_t std_stride,
+                             size_t std_off, double2 *block, float2 *block32, int mode, hipStream_t st);
+bsm_status block64_sub(const Geom &g, int d, double2 *out, const double2 *a, const double2 *b, hipStream_t st);
+// per-RHS |v|^2 into dst[16] (device), partials: block64_norm_parts * 16 doubles
+bsm_status block64_norms(const Geom &g, int d, const double2 *v, double *partials, double *dst, hipStream_t st);
+int block64_norm_parts(const Geom &g, int d);
+
 // layout conversions
 bsm_status launch_gauge_to_block(const Geom &g, int d, int link_prec, const void *U_rep, float *U_block,
                                  hipStream_t st);

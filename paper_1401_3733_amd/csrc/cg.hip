@@ -482,8 +482,11 @@ struct BlockSolve {
     size_t full64, bb64, bbB;
     // FP64 per RHS
     std::vector<Op> ops;
-    char *bh, *r64, *t64, *tfull, *tmp64;
+    char *bh, *t64, *tfull, *tmp64;
     std::vector<double> bnorm2, rhs_norm2;
+    // FP64 block fields for the reliable updates (all RHS share each link load)
+    double *Ublk64;
+    double2 *X64, *BH64, *T1, *T2;
     // FP32 block fields
     float *Ublk;
     float2 *p, *t, *q, *xlo, *rlo, *tmpB;
@@ -524,6 +527,32 @@ static bsm_status block_op(BlockSolve &B, int dagger, const float2 *in, float2 *
     return launch_hop_block(B.g, B.d, c, B.st);
 }
 
+// FP64 Schur operator (or its adjoint) on FP64 block fields, T1 as the odd
+// intermediate: out_e = in_e - kappa_r^2 H_eo H_oe in_e
+static bsm_status block_op64(BlockSolve &B, int dagger, const double2 *in, double2 *out) {
+    BlockHop64Args a{};
+    a.U = B.Ublk64;
+    a.dagger = dagger;
+    a.np = 1;
+    a.p0 = 1;
+    a.in[1] = in;
+    a.out[1] = B.T1;
+    for (int r = 0; r < kNR; r++) { a.a[r] = 0.0; a.b[r] = 1.0; }
+    TRY(launch_hop_block64(B.g, B.d, a, B.st));
+    BlockHop64Args c = a;
+    c.p0 = 0;
+    c.in[0] = B.T1;
+    c.x[0] = in;
+    c.out[0] = out;
+    c.use_x = 1;
+    for (int r = 0; r < kNR; r++) {
+        const double k = r < B.n ? B.kappas[r] : 0.0;
+        c.a[r] = 1.0;
+        c.b[r] = -k * k;
+    }
+    return launch_hop_block64(B.g, B.d, c, B.st);
+}
+
 // one CG iteration on the block fields: p = r + beta p ; t = M p ; alpha ;
 // q = M^dag t ; x += alpha p ; r -= alpha q ; beta, |r|^2 -> history slot k
 static bsm_status block_iteration(BlockSolve &B, int k) {
@@ -546,9 +575,11 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
     const size_t linkB = block_link_bytes(g, d);
     // partials for any plan (the autotuner below may change it)
     const size_t parts = std::max((size_t)hop_block_grid_max(g), (size_t)block_blas_grid(g, d, 1)) * kNR;
-    // 16 carve-outs below, each rounded up to 256 bytes
-    size_t need = linkB + 6 * B.bbB + (size_t)(2 * n + 3) * B.bb64 + 2 * B.bb64 + parts * 8 +
-                  (size_t)kBlockPresum * kNR * 8 + block_scal_doubles() * 8 + 64 * sizeof(int) + 17 * 256;
+    // 20 carve-outs below, each rounded up to 256 bytes
+    const size_t link64 = block64_link_bytes(g, d), bb64B = block64_parity_bytes(g, d);
+    size_t need = linkB + 6 * B.bbB + (size_t)(n + 4) * B.bb64 + parts * 8 +
+                  (size_t)kBlockPresum * kNR * 8 + block_scal_doubles() * 8 + 64 * sizeof(int) + link64 +
+                  4 * bb64B + 22 * 256;
     void *work = nullptr;
     TRY(ctx_work(B.ctx, need, &work));
     char *w = (char *)work;
@@ -556,14 +587,18 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
     B.Ublk = (float *)take(linkB);
     B.p = (float2 *)take(B.bbB); B.t = (float2 *)take(B.bbB); B.q = (float2 *)take(B.bbB);
     B.xlo = (float2 *)take(B.bbB); B.rlo = (float2 *)take(B.bbB); B.tmpB = (float2 *)take(B.bbB);
-    B.bh = take(n * B.bb64); B.r64 = take(n * B.bb64);
+    B.bh = take(n * B.bb64);
     B.t64 = take(B.bb64); B.tmp64 = take(B.bb64); B.tfull = take(2 * B.bb64);
     B.partials = (double *)take(parts * 8);
     B.presum = (double *)take((size_t)kBlockPresum * kNR * 8);
     B.scal = (double *)take(block_scal_doubles() * 8);
     B.mask = (int *)take(64 * sizeof(int));
+    B.Ublk64 = (double *)take(link64);
+    B.X64 = (double2 *)take(bb64B); B.BH64 = (double2 *)take(bb64B);
+    B.T1 = (double2 *)take(bb64B); B.T2 = (double2 *)take(bb64B);
     // ---- links in block layout, per-RHS FP64 operators and right-hand sides
     TRY(launch_gauge_to_block(g, d, BSM_F64, B.ops[0].U, B.Ublk, st));
+    TRY(launch_gauge_to_block64(g, d, B.ops[0].U, B.Ublk64, st));
     // first batched solve for this d_R on the context: tune the block hop plan
     // (t and q are outputs of every iteration, free to use as scratch here)
     if (B.ctx->block_plans[d].us == 0.f) TRY(block_autotune(B.ctx, d, B.Ublk, B.t, B.q, st));
@@ -590,17 +625,22 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
     // ---- residuals: r64_r = M_r^dag (bhat_r - M_r x_r) for the selected RHS,
     //      copied into the block residual; returns |r64_r|^2
     std::vector<double> rr(kNR, 0.0), maxrr(kNR, 0.0), trig(n, B.prm->tol), res(n, INFINITY);
-    auto refresh = [&](unsigned sel) -> bsm_status {
-        for (int r = 0; r < n; r++) {
-            if (!((sel >> r) & 1u)) continue;
-            char *r64r = B.r64 + r * B.bb64;
-            TRY(normal_residual(B.ops[r], B.bh + r * B.bb64, B.x + r * B.full64, B.t64, r64r, st));
-            TRY(blas_dot(g, d, 1, Vec{r64r, BSM_F64}, none, B.ctx->partials, st));
-            rr[r] = reduce_to_host(B.ctx, B.ctx->partials, blas_blocks(g, 1), st);
-        }
-        return launch_std_block(g, d, n, sel, B.r64, B.bb64, 0, B.rlo, 0, st);
-    };
+    //      (FP64 block operator: every RHS at once, sharing the link loads)
     const unsigned all = n >= 32 ? 0xffffffffu : ((1u << n) - 1u);
+    TRY(launch_block64_io(g, d, n, all, B.bh, B.bb64, 0, B.BH64, nullptr, 0, st));
+    auto refresh = [&](unsigned sel) -> bsm_status {
+        TRY(launch_block64_io(g, d, n, all, B.x, B.full64, 0, B.X64, nullptr, 0, st));
+        TRY(block_op64(B, 0, B.X64, B.T2));                 // M x
+        TRY(block64_sub(g, d, B.T2, B.BH64, B.T2, st));      // bhat - M x
+        TRY(block_op64(B, 1, B.T2, B.X64));                 // M^dag (...)
+        TRY(block64_norms(g, d, B.X64, B.partials, B.presum, st));
+        double h16[kNR];
+        BSM_HIP(hipMemcpyAsync(h16, B.presum, sizeof h16, hipMemcpyDeviceToHost, st));
+        BSM_HIP(hipStreamSynchronize(st));
+        for (int r = 0; r < n; r++)
+            if ((sel >> r) & 1u) rr[r] = h16[r];
+        return launch_block64_io(g, d, n, sel, nullptr, 0, 0, B.X64, B.rlo, 1, st);
+    };
     TRY(refresh(all));
     BSM_HIP(hipMemsetAsync(B.xlo, 0, B.bbB, st));
     BSM_HIP(hipMemsetAsync(B.p, 0, B.bbB, st));
