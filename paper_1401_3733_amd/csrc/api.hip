@@ -78,8 +78,13 @@ struct HopSel {
     };
 };
 
-bsm_status launch_hop(const Geom &g, int d, bool real, int prec, int link_prec, const HopArgs &a,
+bsm_status launch_hop(const Geom &g, int d, bool real, int prec, int link_prec, const HopArgs &a_in,
                       hipStream_t st) {
+    // Without fused norms the kernel choice is invisible to the caller, so the
+    // colour split is used wherever it applies; with norms the caller sized
+    // the partials for a.wide (apply_plan and hop_grid) and that is kept.
+    HopArgs a = a_in;
+    if (!a.norm_partials) a.wide = hop_wide_of(d, prec);
     if (prec == BSM_F64 && link_prec == BSM_F64)
         return dispatch_d<HopSel<BSM_F64, BSM_F64>::ByD>(d, g, real, a, st);
     if (prec == BSM_F32 && link_prec == BSM_F32)

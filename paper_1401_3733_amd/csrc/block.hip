@@ -66,7 +66,8 @@ __device__ inline void hop_dir_block(const Geom &g, const BlockHopArgs &a, const
                                      const uint32_t (&h)[S], int r, int q, float eta, f4 (&acc)[S][4][2]) {
     constexpr int KB = (D + 3) / 4;
     constexpr size_t SITE = (size_t)D * 4 * kNR;
-#pragma unroll
+    // one direction at a time keeps the operands of a single hop in registers
+#pragma unroll 1
     for (int dir = 0; dir < 2; dir++) {
         const bool back = dir == 1;
         float w[S];
@@ -116,7 +117,7 @@ __device__ inline void hop_dir_block(const Geom &g, const BlockHopArgs &a, const
 // Workgroup w covers sites [w * WPB * S, (w + 1) * WPB * S); wavefront v owns
 // sites base + v + WPB * j, j < S.
 template <int D, int S>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == 1 ? 2 : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == 1 ? 3 : 1)))
 void k_hop_block(Geom g, BlockHopArgs a, int nblk) {
     constexpr size_t SITE = (size_t)D * 4 * kNR;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

@@ -60,7 +60,8 @@ __device__ inline void hop_dir_block64(const Geom &g, const BlockHop64Args &a, c
                                        int r, int q, double eta, d4 (&acc)[4][2]) {
     constexpr int KB = (D + 3) / 4;
     constexpr size_t SITE = (size_t)D * 4 * kNR;
-#pragma unroll
+    // one direction at a time: its operands alone fill the register budget
+#pragma unroll 1
     for (int dir = 0; dir < 2; dir++) {
         const bool back = dir == 1;
         float wf;
@@ -95,9 +96,11 @@ __device__ inline void hop_dir_block64(const Geom &g, const BlockHop64Args &a, c
     }
 }
 
-// 4 sites per 256-thread workgroup, one per wavefront
+// 4 sites per 256-thread workgroup, one per wavefront; the register budget
+// is capped so that two wavefronts per SIMD overlap their loads
 template <int D>
-__global__ __launch_bounds__(256) void k_hop_block64(Geom g, BlockHop64Args a, int nblk) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void k_hop_block64(Geom g, BlockHop64Args a, int nblk) {
     constexpr size_t SITE = (size_t)D * 4 * kNR;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, q = lane >> 4;
