@@ -329,14 +329,8 @@ def bench_cfg5(bsm, gen, train_steps=300, n_pairs=32, channels=8, large_dims=Tru
     s, st = ctx.bsm_cg_solve(d32, U32, U64, bsm.solver_params(kappa, 1e-10, schur=True, variant=bsm.SOLVER_MIXED),
                              b, x, check=False)
     rows["mixed_f32"] = solve_row(s, st, base)
-    for name, use_net in (("gcr_no_net", False), ("fgcr_net", True)):
-        log(f"cfg5 {name} ...")
-        prm = bsm.solver_params(kappa, 1e-10, max_iter=20000, restart=8)
-        s, st = ctx.bsm_fgcr_solve(d32, U32, U64, prm, channels, net if use_net else None, b, x, check=False)
-        rows[name] = solve_row(s, st, base)
-        rows[name].update(fell_back=st["fell_back"], precond_applies=st["precond_applies"],
-                          x_rel_diff_vs_plain=rel_diff(ctx, d64, x, x0))
-        log(f"  {rows[name]}")
+    _fgcr_rows(bsm, ctx, d32, d64, U32, U64, kappa, channels, net, b, x, x0, base, rows, "cfg5")
+    apply_us = _time_net_apply(bsm, ctx, d32, U32, channels, net, b)
     gain = base - rows["fgcr_net"]["seconds"]
     ctx.close()
     torch.cuda.empty_cache()
@@ -347,6 +341,7 @@ def bench_cfg5(bsm, gen, train_steps=300, n_pairs=32, channels=8, large_dims=Tru
                             seconds=round(t_train, 3), pairs_seconds=round(t_pairs, 3),
                             loss_first=losses[0], loss_last20=float(np.mean(losses[-20:]))),
            "solves": rows,
+           "net_apply_us": apply_us,
            "break_even_solves": (round(t_train / gain, 1) if gain > 0 else None),
            "same_net_on_32x32x32x64": large}
     return out
@@ -379,18 +374,52 @@ def bench_cfg5_large(bsm, gen, net, channels, kappa):
                              b, x, check=False)
     rows["mixed_f32"] = solve_row(s, st, base)
     log(f"  mixed_f32 {rows['mixed_f32']}")
-    for name, use_net in (("gcr_no_net", False), ("fgcr_net", True)):
-        log(f"cfg5 transfer: {name} ...")
-        prm = bsm.solver_params(kappa, 1e-10, max_iter=20000, restart=8)
+    _fgcr_rows(bsm, ctx, d32, d64, U32, U64, kappa, channels, net, b, x, x0, base, rows, "cfg5 transfer")
+    apply_us = _time_net_apply(bsm, ctx, d32, U32, channels, net, b)
+    ctx.close()
+    torch.cuda.empty_cache()
+    return {"workload": "32^3x64 SU(3) fund, exp(0.5iH) links (seed 1105), kappa 0.1335, net trained on 16^3x32",
+            "solves": rows, "net_apply_us": apply_us}
+
+
+def _fgcr_rows(bsm, ctx, d32, d64, U32, U64, kappa, channels, net, b, x, x0, base, rows, tag):
+    """GCR(8) without the net, FGCR(8) with the collapsed FP16 net (the
+    default) and with the FP32 layers."""
+    for name, use_net, layers in (("gcr_no_net", False, 0), ("fgcr_net", True, 0),
+                                  ("fgcr_net_layers_f32", True, 1)):
+        log(f"{tag} {name} ...")
+        prm = bsm.solver_params(kappa, 1e-10, max_iter=20000, restart=8, precond_layers=layers)
         s, st = ctx.bsm_fgcr_solve(d32, U32, U64, prm, channels, net if use_net else None, b, x, check=False)
         rows[name] = solve_row(s, st, base)
         rows[name].update(fell_back=st["fell_back"], precond_applies=st["precond_applies"],
                           x_rel_diff_vs_plain=rel_diff(ctx, d64, x, x0))
         log(f"  {rows[name]}")
-    ctx.close()
-    torch.cuda.empty_cache()
-    return {"workload": "32^3x64 SU(3) fund, exp(0.5iH) links (seed 1105), kappa 0.1335, net trained on 16^3x32",
-            "solves": rows}
+
+
+def _time_net_apply(bsm, ctx, d32, U32, channels, net, b64, reps=20):
+    """Mean duration of one network application, collapsed and layered (HIP
+    events on the stream the calls are queued on)."""
+    import torch
+    f32 = ctx.spinor_bytes(d32, 2, 1)
+    r = torch.zeros(f32 // 4, dtype=torch.float32, device="cuda")
+    z = torch.zeros_like(r)
+    # r: the source rounded to F32 (an internal field with zero padding)
+    canon = torch.zeros(int(np.prod(ctx.dims)) * 4 * 3, dtype=torch.complex128, device="cuda")
+    ctx.bsm_unpack_spinor(bsm.desc(3, "fund", "f64"), b64, canon)
+    ctx.bsm_pack_spinor(d32, canon, r)
+    out = {}
+    for name, fn in (("collapsed_fp16", ctx.bsm_precond_apply_collapsed), ("layers_f32", ctx.bsm_precond_apply)):
+        for _ in range(3):
+            fn(d32, U32, channels, net, r, z)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn(d32, U32, channels, net, r, z)
+        e1.record()
+        e1.synchronize()
+        out[name] = round(e0.elapsed_time(e1) * 1e3 / reps, 1)
+    log(f"  net apply us {out}")
+    return out
 
 
 def _init_weights(channels, seed):

@@ -204,6 +204,9 @@ typedef struct {
     double delta;          /* reliable update threshold (MIXED), e.g. 0.1 */
     int32_t check_every;   /* iterations between host convergence checks (>= 1) */
     int32_t restart;       /* FGCR: Krylov vectors per cycle (e.g. 16) */
+    int32_t precond_layers; /* FGCR: 0 applies the network as one collapsed operator
+                               (bsm_precond_apply_collapsed) where d_R <= 3; 1 always
+                               applies it layer by layer in FP32 (bsm_precond_apply) */
 } bsm_solver_params;
 
 typedef struct {
@@ -253,6 +256,17 @@ bsm_status bsm_ptc_weight_grad(bsm_ctx ctx, const bsm_field_desc *desc, const vo
 /* z = M(r) for F32 full fields r, z */
 bsm_status bsm_precond_apply(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, int32_t channels,
                              const void *net, const void *r, void *z, void *stream);
+/* z = M(r) with the two layers collapsed into one operator, which both
+ * layers being linear allows (spin matrices commute with the transports):
+ *   z = sum_p T_p G_p,  G_p(y) = sum_q C_pq (T_q r)(y),  C_pq = sum_j W2_p^{0j} W1_q^{j0}.
+ * Transports in FP32; the 36 x 36 complex mixing runs on FP16 matrix cores
+ * with FP32 accumulation on per-site scaled fields, and the nine mixed fields
+ * are kept in FP16 with that scale, so z agrees with bsm_precond_apply to a
+ * relative O(1e-3) (norm-wise).  Non-finite components of r give non-finite
+ * components of z.  d_R <= 3 (BSM_ERR_UNSUPPORTED otherwise); scratch from
+ * the context.  Asynchronous on stream. */
+bsm_status bsm_precond_apply_collapsed(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep,
+                                       int32_t channels, const void *net, const void *r, void *z, void *stream);
 
 typedef struct {
     float lr, beta1, beta2, eps;   /* Adam (e.g. 1e-3, 0.9, 0.999, 1e-8) */
@@ -278,7 +292,8 @@ bsm_status bsm_precond_pairs(bsm_ctx ctx, const bsm_field_desc *desc64, const vo
                              int32_t n_solves, const void *x_star, int32_t n_snap, const int32_t *iters,
                              void *r_out, void *e_out, void *stream);
 /* Flexible GCR(params->restart) on D x = b with z = M(r) from the network
- * (net nullable: M = 1).  Each restart cycle solves the correction equation
+ * (net nullable: M = 1; params->precond_layers picks the collapsed FP16 or
+ * the layered FP32 form of M).  Each restart cycle solves the correction equation
  * D e = r in FP32 (directions, D, Gram-Schmidt; sums in FP64), then
  * x += e in FP64 and r = b - D x is recomputed in FP64 (the judge).  A cycle
  * that reduces |r| by less than a factor 2, or meets a non-finite value,

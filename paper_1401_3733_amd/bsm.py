@@ -41,7 +41,7 @@ class FieldDesc(C.Structure):
 class SolverParams(C.Structure):
     _fields_ = [("variant", C.c_int32), ("schur", C.c_int32), ("kappa", C.c_double),
                 ("tol", C.c_double), ("max_iter", C.c_int32), ("delta", C.c_double),
-                ("check_every", C.c_int32), ("restart", C.c_int32)]
+                ("check_every", C.c_int32), ("restart", C.c_int32), ("precond_layers", C.c_int32)]
 
 
 class SolverStats(C.Structure):
@@ -103,6 +103,7 @@ _SIGS = {
                                         _vp]),
     "bsm_ptc_weight_grad": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp]),
     "bsm_precond_apply": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, _vp, _vp, _vp, _vp]),
+    "bsm_precond_apply_collapsed": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, _vp, _vp, _vp, _vp]),
     "bsm_precond_train": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, _vp, _vp, _vp, _vp, C.c_int32,
                                     C.POINTER(TrainParams), C.POINTER(C.c_float), _vp]),
     "bsm_precond_pairs": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_double, C.c_int32, _vp, C.c_int32,
@@ -349,6 +350,10 @@ class Context:
         _check(lib().bsm_precond_apply(self.handle, C.byref(d), _ptr(U_rep), int(channels), _ptr(net), _ptr(r),
                                        _ptr(z), _stream(stream)), "bsm_precond_apply")
 
+    def bsm_precond_apply_collapsed(self, d, U_rep, channels, net, r, z, stream=None):
+        _check(lib().bsm_precond_apply_collapsed(self.handle, C.byref(d), _ptr(U_rep), int(channels), _ptr(net),
+                                                 _ptr(r), _ptr(z), _stream(stream)), "bsm_precond_apply_collapsed")
+
     def bsm_precond_train(self, d, U_rep, channels, net, adam_state, r_pairs, e_pairs, n_pairs,
                           params: TrainParams, stream=None):
         losses = (C.c_float * max(1, params.steps))()
@@ -383,9 +388,9 @@ def _darr(vals, n=None):
 
 
 def solver_params(kappa, tol=1e-10, schur=True, variant=SOLVER_PLAIN, max_iter=100000, delta=0.1,
-                  check_every=8, restart=16) -> SolverParams:
+                  check_every=8, restart=16, precond_layers=0) -> SolverParams:
     return SolverParams(variant, int(schur), float(kappa), float(tol), int(max_iter), float(delta),
-                        int(check_every), int(restart))
+                        int(check_every), int(restart), int(precond_layers))
 
 
 def train_params(lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, batch=4, steps=100, seed=0, step0=0) -> TrainParams:

@@ -220,6 +220,17 @@ static bsm_status net_apply(bsm_ctx ctx, const bsm_field_desc *desc, const void 
     return layer(ctx, desc->d_R, a, st);
 }
 
+// the collapsed network: scratch in the network slot, C from the weights
+static bsm_status net_fast_prepare(bsm_ctx ctx, int d, int C, const void *net, const void *U, NetFastArgs &a,
+                                   hipStream_t st) {
+    void *w = nullptr;
+    TRY(ctx_work_slot(ctx, 2, net_fast_bytes(ctx->g, d), &w));
+    a = NetFastArgs{};
+    a.U = U;
+    net_fast_carve(ctx->g, d, w, a);
+    return launch_net_collapse(net, C, a, st);
+}
+
 static uint64_t splitmix64(uint64_t x) {
     x += 0x9E3779B97F4A7C15ull;
     x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -284,6 +295,21 @@ bsm_status bsm_precond_apply(bsm_ctx ctx, const bsm_field_desc *desc, const void
     void *h = nullptr;
     TRY(ctx_work(ctx, channels * f32, &h));
     return net_apply(ctx, desc, U_rep, channels, net, r, h, z, (hipStream_t)stream);
+}
+
+bsm_status bsm_precond_apply_collapsed(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep,
+                                       int32_t channels, const void *net, const void *r, void *z, void *stream) {
+    TRY(check_net_desc(ctx, desc));
+    if (!U_rep || !net || !r || !z) return fail(BSM_ERR_ARG, "null pointer");
+    if (channels < 1 || channels > 64) return fail(BSM_ERR_ARG, "channels must be in [1, 64]");
+    if (r == z) return fail(BSM_ERR_ARG, "r and z must differ");
+    if (!net_fast_supported(desc->d_R)) return fail(BSM_ERR_UNSUPPORTED, "the collapsed network runs for d_R <= 3");
+    hipStream_t st = (hipStream_t)stream;
+    NetFastArgs a;
+    TRY(net_fast_prepare(ctx, desc->d_R, channels, net, U_rep, a, st));
+    a.in = r;
+    a.out = z;
+    return launch_net_fast(ctx->g, desc->d_R, a, st);
 }
 
 bsm_status bsm_precond_train(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, int32_t channels,
@@ -434,7 +460,8 @@ bsm_status bsm_fgcr_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U
     const int nb = (int)std::min<size_t>((n + 255) / 256, kZblocks);
     auto t0 = std::chrono::steady_clock::now();
     // the context's second scratch: the fall back CG uses the first
-    const size_t need = (2 * (size_t)m + 2) * f32 + 2 * f64 + (net ? (size_t)channels * f32 : 0) +
+    const bool fast = net && prm->precond_layers == 0 && net_fast_supported(d);
+    const size_t need = (2 * (size_t)m + 2) * f32 + 2 * f64 + (net && !fast ? (size_t)channels * f32 : 0) +
                         (size_t)kGcrMax * nb * sizeof(double2) + 4 * kGcrMax * sizeof(double2) + 16 * 256;
     void *work = nullptr;
     TRY(ctx_work_slot(ctx, 1, need, &work));
@@ -449,7 +476,9 @@ bsm_status bsm_fgcr_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U
         Wp.p[k] = (const float2 *)Wv[k];
     }
     char *rho = take(f32), *e = take(f32);
-    char *h32 = net ? take((size_t)channels * f32) : nullptr;
+    char *h32 = net && !fast ? take((size_t)channels * f32) : nullptr;
+    NetFastArgs fa{};
+    if (fast) TRY(net_fast_prepare(ctx, d, channels, net, U_rep, fa, st));
     char *r = take(f64), *t = take(f64);
     double2 *parts = (double2 *)take((size_t)kGcrMax * nb * sizeof(double2));
     double2 *coef = (double2 *)take(4 * kGcrMax * sizeof(double2));
@@ -474,7 +503,11 @@ bsm_status bsm_fgcr_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U
     };
     // one FP32 GCR step on D e = rho with direction k
     auto step = [&](int k) -> bsm_status {
-        if (net) {
+        if (fast) {
+            fa.in = rho;
+            fa.out = Z[k];
+            TRY(launch_net_fast(g, d, fa, st));
+        } else if (net) {
             TRY(net_apply(ctx, desc, U_rep, channels, net, rho, h32, Z[k], st));
         } else {
             BSM_HIP(hipMemcpyAsync(Z[k], rho, f32, hipMemcpyDeviceToDevice, st));

@@ -298,3 +298,118 @@ def test_fgcr_errors():
     assert st == bsm.ERR_NONFINITE
     st, _, _ = _fgcr(T, None, 1, b, restart=65)
     assert st == bsm.ERR_ARG
+
+
+# ------------------------------------------------- collapsed FP16 network
+# The collapsed operator rounds the per-site scaled transports, C / max|C|
+# and the mixed fields to binary16 (unit roundoff u = 2^-11 ~ 4.9e-4) and
+# accumulates in FP32; three roundings of O(1) terms that enter with random
+# signs give a norm-wise relative error of a few u (3e-4 measured in an FP64
+# model of the same roundings), bounded here by 4e-3 (8 u).  A wrong path,
+# spin or colour index gives an O(1) error.
+COLLAPSED_TOL = 4e-3
+
+
+def _net_weights(seed, C=8, scale=0.05):
+    W1, W2 = ptc.init_weights(C, gen.SEED_NET)
+    W1 = _f32_exact(W1 + _rand_w(W1.shape, seed, scale))
+    W2 = _f32_exact(W2 + _rand_w(W2.shape, seed + 1, scale))
+    return W1, W2
+
+
+def _net_dev(W1, W2):
+    import torch
+    return torch.cat([_w_dev(W1).reshape(-1), _w_dev(W2).reshape(-1)])
+
+
+@pytest.mark.parametrize("N,C", [(3, 8), (2, 8), (3, 3)])
+def test_collapsed_net_matches_oracle(N, C):
+    note(f"collapsed precond N={N} C={C}")
+    S = NetSetup(N, "fund", 140 + N)
+    W1, W2 = _net_weights(16, C)
+    net = _net_dev(W1, W2)
+    r = _f32_exact(gen.gaussian_spinor(LAT, S.d, 17))
+    z = S.out(1)
+    S.ctx.bsm_precond_apply_collapsed(S.desc, S.U, C, net, S.fields(r[None]), z)
+    got = S.get(z, 1)[0]
+    ref = ptc.net_apply(LAT, S.UR32, W1, W2, r)
+    print("collapsed rel err", rel(got, ref))
+    assert rel(got, ref) < COLLAPSED_TOL
+    # and against the FP32 layers on the GPU
+    zl = S.out(1)
+    S.ctx.bsm_precond_apply(S.desc, S.U, C, net, S.fields(r[None]), zl)
+    assert rel(got, S.get(zl, 1)[0]) < COLLAPSED_TOL
+
+
+def test_collapsed_net_trained_weights_and_point_source():
+    """Trained-looking weights (the Wilson operator's layer composed with a
+    random one) and a field concentrated on one site: the per-site scale
+    keeps the FP16 range."""
+    note("collapsed precond point source")
+    S = NetSetup(3, "fund", 150)
+    W1, W2 = _net_weights(18, 8, 0.2)
+    net = _net_dev(W1, W2)
+    r = np.zeros((LAT.V, 4, 3), np.complex128)
+    r[37] = _f32_exact(1e20 * gen.gaussian_spinor(LAT, 3, 19)[37])
+    r[500, 2, 1] = 1e-25
+    z = S.out(1)
+    S.ctx.bsm_precond_apply_collapsed(S.desc, S.U, 8, net, S.fields(r[None]), z)
+    got = S.get(z, 1)[0]
+    ref = ptc.net_apply(LAT, S.UR32, W1, W2, r)
+    assert np.all(np.isfinite(got))
+    assert rel(got, ref) < COLLAPSED_TOL
+
+
+def test_collapsed_net_is_exactly_scale_covariant_and_zero_preserving():
+    """Scaling r by 2^k scales every per-site scale by 2^k and leaves the
+    FP16 operands bit for bit the same, so z scales exactly; r = 0 gives 0."""
+    import torch
+    note("collapsed precond scale covariance")
+    S = NetSetup(3, "fund", 151)
+    W1, W2 = _net_weights(20)
+    net = _net_dev(W1, W2)
+    r = _f32_exact(gen.gaussian_spinor(LAT, 3, 21))
+    z1, z2, z0 = S.out(1), S.out(1), S.out(1)
+    S.ctx.bsm_precond_apply_collapsed(S.desc, S.U, 8, net, S.fields(r[None]), z1)
+    S.ctx.bsm_precond_apply_collapsed(S.desc, S.U, 8, net, S.fields((2.0 ** 40 * r)[None]), z2)
+    S.ctx.bsm_precond_apply_collapsed(S.desc, S.U, 8, net, S.fields(np.zeros_like(r)[None]), z0)
+    torch.cuda.synchronize()
+    assert torch.equal(z2, z1 * 2.0 ** 40)
+    assert torch.count_nonzero(z0).item() == 0
+
+
+def test_collapsed_net_rejects_unsupported_shapes():
+    S = NetSetup(3, "sym", 152)
+    W1, W2 = _net_weights(22)
+    net = _net_dev(W1, W2)
+    r = S.fields(_f32_exact(gen.gaussian_spinor(LAT, S.d, 23))[None])
+    z = S.out(1)
+    with pytest.raises(bsm.BsmError) as e:
+        S.ctx.bsm_precond_apply_collapsed(S.desc, S.U, 8, net, r, z)
+    assert e.value.status == bsm.ERR_UNSUPPORTED
+    S3 = NetSetup(3, "fund", 153)
+    with pytest.raises(bsm.BsmError):
+        S3.ctx.bsm_precond_apply_collapsed(S3.desc, S3.U, 0, net, S3.fields(np.zeros((1, LAT.V, 4, 3))), S3.out(1))
+
+
+def test_fgcr_collapsed_and_layered_nets_agree():
+    """FGCR with the collapsed FP16 net and with the FP32 layers: both reach
+    the FP64 judge, and their iteration counts agree to within 10 %."""
+    import torch
+    T = Trainer()
+    net, _ = _net_trained(T, steps=120)
+    b = gen.gaussian_spinor(LAT, 3, 96)
+    S, S64 = T.S, T.S64
+    res = {}
+    for layers in (0, 1):
+        bb = S64.pack(b)
+        x = torch.zeros_like(bb)
+        prm = bsm.solver_params(KAPPA, 1e-10, max_iter=5000, restart=8, precond_layers=layers)
+        note(f"fgcr precond_layers={layers}")
+        st, stats = S.ctx.bsm_fgcr_solve(S.desc, S.U, S64.U, prm, 8, net, bb, x, check=False)
+        xs = S64.unpack(x)
+        assert st == 0 and stats["converged"] and not stats["fell_back"]
+        assert oracle.true_residual(LAT, T.UR, KAPPA, b, xs) <= 1e-10
+        res[layers] = stats["iters"]
+    print("iters collapsed / layered", res)
+    assert abs(res[0] - res[1]) <= max(2, res[1] // 10)
