@@ -383,12 +383,12 @@ def bench_cfg5_large(bsm, gen, net, channels, kappa):
 
 
 def _fgcr_rows(bsm, ctx, d32, d64, U32, U64, kappa, channels, net, b, x, x0, base, rows, tag):
-    """GCR(8) without the net, FGCR(8) with the collapsed FP16 net (the
+    """GCR(6) without the net, FGCR(6) with the collapsed FP16 net (the
     default) and with the FP32 layers."""
     for name, use_net, layers in (("gcr_no_net", False, 0), ("fgcr_net", True, 0),
                                   ("fgcr_net_layers_f32", True, 1)):
         log(f"{tag} {name} ...")
-        prm = bsm.solver_params(kappa, 1e-10, max_iter=20000, restart=8, precond_layers=layers)
+        prm = bsm.solver_params(kappa, 1e-10, max_iter=20000, restart=6, precond_layers=layers)
         s, st = ctx.bsm_fgcr_solve(d32, U32, U64, prm, channels, net if use_net else None, b, x, check=False)
         rows[name] = solve_row(s, st, base)
         rows[name].update(fell_back=st["fell_back"], precond_applies=st["precond_applies"],

@@ -9,11 +9,13 @@
 // are never formed.
 //
 // Precision: the transports are FP32.  The mixing runs on FP16 matrix cores
-// with FP32 accumulation: each site's nine transported fields are divided by
-// their largest |component| before rounding to FP16, C by its largest entry;
-// the nine mixed fields are stored in FP16 with that per-site scale.  The
-// result agrees with the FP32 layers to a relative O(1e-3), which is what a
-// preconditioner of a flexible Krylov method needs.
+// with FP32 accumulation: the transported fields are divided by a bound on
+// their largest |component| (per site and group of paths) before rounding to
+// FP16, C by its largest entry; the nine mixed fields are stored in FP16 with
+// a per-site scale.  The scales only keep the values inside the FP16 range
+// (its relative precision does not depend on them).  The result agrees with
+// the FP32 layers to a relative O(1e-3), which is what a preconditioner of a
+// flexible Krylov method needs.
 #include "dispatch.h"
 #include "ptc.h"
 #include "ptc_dev.h"
@@ -25,12 +27,14 @@ typedef _Float16 h4v __attribute__((ext_vector_type(4)));
 constexpr int kFastMaxD = 3;    // colour dimensions of the matrix-core mixing
 constexpr int kFastRows = 72;   // (path, spin, re/im) of the real form
 constexpr int kFastTiles = 5;   // 16-row tiles covering 72 rows (and 16-deep K steps covering 72)
-constexpr int kFastKq = 18;     // groups of 4 K values per site and colour
+constexpr int kFastSites = 128; // sites per block of the mixing kernel (4 threads each)
+constexpr int kFastSlotsKq = 20;   // groups of 4 K values incl. the zero slot
+__host__ __device__ inline int fast_slot_path(int slot);
 
 // C (36 x 36 complex, FP64 sums) -> FP16 real form / cs in the lane order of
 // the 16x16x16 matrix-core fragments: frag[(mt * 5 + ks) * 64 + lane] holds
-// A[16 mt + lane % 16][16 ks + 4 (lane / 16) + 0..3]; cs = max |Re|, |Im|.
-// One workgroup.
+// A[16 mt + lane % 16][16 ks + 4 (lane / 16) + 0..3] with the K index in the
+// slot order of k_net_mix16; cs = max |Re|, |Im|.  One workgroup.
 __global__ __launch_bounds__(256) void k_net_collapse(const float2 *W1, const float2 *W2, int C, h4v *frag,
                                                       float *cs_out) {
     __shared__ float2 Cm[36 * 36];
@@ -64,9 +68,11 @@ __global__ __launch_bounds__(256) void k_net_collapse(const float2 *W1, const fl
         const int m = 16 * mt + lane % 16;
         float v[4];
         for (int j = 0; j < 4; j++) {
-            const int k = 16 * ks + 4 * (lane / 16) + j;
+            // reordered K index -> (path, spin, re/im) of the transported fields
+            const int kq = 4 * ks + lane / 16, path = fast_slot_path(kq / 2);
+            const int k = 8 * path + 4 * (kq % 2) + j;
             v[j] = 0.f;
-            if (m < kFastRows && k < kFastRows) {
+            if (m < kFastRows && path >= 0) {
                 const int ro = m & 1, ri = k & 1;
                 const float2 z = Cm[(m / 2) * 36 + k / 2];
                 v[j] = (ro == ri ? z.x : (ro == 0 ? -z.y : z.y)) * inv;
@@ -93,7 +99,7 @@ __device__ inline void load_g16(const NetFastArgs &a, const Geom &g, int p, int 
     for (int bp = 0; bp < 2; bp++)
 #pragma unroll
         for (int cc = 0; cc < D; cc++) {
-            const h4v x = G[g16_index<D>(g, p, par, bp * D + cc, h)];
+            const h4v x = __builtin_nontemporal_load(&G[g16_index<D>(g, p, par, bp * D + cc, h)]);
             v[(2 * bp) * D + cc] = mk<float>((float)x[0] * s, (float)x[1] * s);
             v[(2 * bp + 1) * D + cc] = mk<float>((float)x[2] * s, (float)x[3] * s);
         }
@@ -120,6 +126,14 @@ __device__ inline void link_apply(const Geom &g, const PathSite &ps, const cx<fl
     for (int k = 0; k < 4 * D; k++) t[k] = ps.w * t[k];
 }
 
+// workgroup barrier ordering LDS only: the wavefront's outstanding global
+// stores (the mixed fields of the previous block) are not waited for
+__device__ inline void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <int D>
 __device__ inline float maxabs(const cx<float> (&t)[4 * D], float m) {
 #pragma unroll
@@ -127,96 +141,159 @@ __device__ inline float maxabs(const cx<float> (&t)[4 * D], float m) {
     return m;
 }
 
-// write t * inv as FP16 into the B tile: Bh[(colour * 18 + 2 p + spin pair) * 64 + site]
+// K order of the matrix-core operand: slots of 8 K values (one path's four
+// spins, re/im) in the order p0 p4 p8 - p1 p5 p2 p6 p3 p7 ('-' is zero), so
+// that each 16-deep K step belongs to one thread of a site's four: steps 0
+// and 1 to thread 0 (paths 0, 4, 8), step 1 + g to thread g (paths g, g + 4).
+__host__ __device__ inline int fast_slot_path(int slot) {
+    constexpr int sp[10] = {0, 4, 8, -1, 1, 5, 2, 6, 3, 7};
+    return sp[slot];
+}
+__device__ inline int fast_path_slot(int p) {
+    constexpr int ps[9] = {0, 4, 6, 8, 1, 5, 7, 9, 2};
+    return ps[p];
+}
+
+// write t * inv as FP16 into the B tile: Bh[(colour * 20 + 2 slot + spin pair) * sites + site]
 template <int D>
-__device__ inline void stage_path(h4v *Bh, int p, int s, float inv, const cx<float> (&t)[4 * D]) {
+__device__ inline void stage_path(h4v *Bh, int slot, int s, float inv, const cx<float> (&t)[4 * D]) {
 #pragma unroll
     for (int bp = 0; bp < 2; bp++)
 #pragma unroll
         for (int cc = 0; cc < D; cc++) {
             const cx<float> x0 = t[(2 * bp) * D + cc], x1 = t[(2 * bp + 1) * D + cc];
-            Bh[(cc * kFastKq + 2 * p + bp) * 64 + s] =
+            Bh[(cc * kFastSlotsKq + 2 * slot + bp) * kFastSites + s] =
                 h4v{(_Float16)(x0.re * inv), (_Float16)(x0.im * inv), (_Float16)(x1.re * inv), (_Float16)(x1.im * inv)};
         }
 }
 
-// G'_p(y) = sum_q (C / cs) (T_q v)(y) / s(y) for 64 sites of one parity per
-// workgroup of 256 threads.  Phase 1: thread (site, path group pg) forms the
-// transports of paths pg, pg + 4 (and 8 for pg = 0), the site's scale s(y)
-// is their largest |component|, then they go to LDS in FP16.  Phase 2:
-// wavefront w multiplies the 72 x 72 real form with the K x 16 tile of its
-// sites 16w..16w+15, one colour at a time, and stores G' in FP16.
+// source site of path p at (px, h): the site itself or its neighbour
 template <int D>
-__global__ __launch_bounds__(256) void k_net_mix16(Geom g, NetFastArgs a, int nblk) {
-    __shared__ h4v Bh[D * kFastKq * 64];
-    __shared__ float smax[4 * 64];
+__device__ inline float source_maxabs(const Geom &g, const char *v, size_t pblk, int px, uint32_t h,
+                                      const PathSite &ps, int p, float m) {
+    cx<float> s[4 * D];
+    if (p == 0) load_spinor<BSM_F32, D, float>(v + px * pblk, g.Vh_pad, h, s);
+    else load_spinor<BSM_F32, D, float>(v + (1 - px) * pblk, g.Vh_pad, ps.hn, s);
+    return maxabs<D>(s, m);
+}
+
+template <int D>
+__device__ inline void stage_transport(const Geom &g, const char *v, size_t pblk, int px, uint32_t h,
+                                       const PathSite &ps, int p, float inv, h4v *Bh, int site) {
+    cx<float> s[4 * D];
+    if (p == 0) {
+        load_spinor<BSM_F32, D, float>(v + px * pblk, g.Vh_pad, h, s);
+        stage_path<D>(Bh, fast_path_slot(0), site, inv, s);
+    } else {
+        load_spinor<BSM_F32, D, float>(v + (1 - px) * pblk, g.Vh_pad, ps.hn, s);
+        cx<float> t[4 * D];
+        link_apply<D>(g, ps, s, t);
+        stage_path<D>(Bh, fast_path_slot(p), site, inv, t);
+    }
+}
+
+// G'_p(y) = sum_q (C / cs) (T_q v)(y) / S(y) for blocks of 128 sites of one
+// parity; a workgroup of 512 threads walks a contiguous range of blocks with
+// the matrix fragments in LDS.  Phase 1: thread (site, group g) bounds the
+// transports of its paths by sqrt(2 D) max |component| of their sources
+// (|U v|_i <= |v|_2 for unitary U), then forms them in FP32, scales them by
+// that bound and writes them to LDS in FP16.  Phase 2: wavefront w takes
+// sites 16w..16w+15 of the block: each 16-deep K step is one thread's, so its product is
+// rescaled by that thread's bound before it is summed; S(y) is the largest
+// of the site's four bounds and G' = G / S is stored in FP16 (|G'| <= 72).
+template <int D>
+__global__ __launch_bounds__(4 * kFastSites) void k_net_mix16(Geom g, NetFastArgs a, int nblk, int per_wg) {
+    __shared__ h4v Bh[D * kFastSlotsKq * kFastSites];
+    __shared__ h4v Afs[kFastTiles * kFastTiles * 64];
+    __shared__ float sb[4 * kFastSites];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane >> 4, sl = lane & 15;
-    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int px = lb >= (uint32_t)nblk ? 1 : 0;
-    const uint32_t hb = (lb - px * nblk) * 64;
+    const int pg = tid / kFastSites, site = tid % kFastSites;
     const size_t pblk = spinor_block_bytes(BSM_F32, D, g.Vh_pad);
     const size_t lblk = link_block_bytes(BSM_F32, false, D, g.Vh_pad);
-    {
-        const int s = tid & 63, pg = tid >> 6;
-        const uint32_t h = hb + s;
-        const bool live = h < (uint32_t)g.Vh;
-        cx<float> t0[4 * D], t1[4 * D], t2[4 * D];
+    const char *U = (const char *)a.U, *v = (const char *)a.in;
+    for (int e = tid; e < kFastTiles * kFastTiles * 64; e += 4 * kFastSites) Afs[e] = ((const h4v *)a.Afrag)[e];
+    // the zero slot (thread group 0 owns it)
+    if (pg == 0)
 #pragma unroll
-        for (int e = 0; e < 4 * D; e++) t0[e] = t1[e] = t2[e] = mk<float>(0.f, 0.f);
-        float mx = 0.f;
-        if (live) {
-            const Coords c = decode(g, h, px);
-            const char *U = (const char *)a.U, *v = (const char *)a.in;
-            transport<D>(g, U, lblk, v, pblk, px, h, c, pg, t0);
-            transport<D>(g, U, lblk, v, pblk, px, h, c, pg + 4, t1);
-            if (pg == 0) transport<D>(g, U, lblk, v, pblk, px, h, c, 8, t2);
-            mx = maxabs<D>(t2, maxabs<D>(t1, maxabs<D>(t0, 0.f)));
+        for (int cc = 0; cc < D; cc++) {
+            Bh[(cc * kFastSlotsKq + 6) * kFastSites + site] = h4v{0, 0, 0, 0};
+            Bh[(cc * kFastSlotsKq + 7) * kFastSites + site] = h4v{0, 0, 0, 0};
         }
-        smax[pg * 64 + s] = mx;
-        __syncthreads();
-        const float m = fmaxf(fmaxf(smax[s], smax[64 + s]), fmaxf(smax[128 + s], smax[192 + s]));
-        const float inv = m > 0.f ? 1.f / m : 0.f;
-        stage_path<D>(Bh, pg, s, inv, t0);
-        stage_path<D>(Bh, pg + 4, s, inv, t1);
-        if (pg == 0) stage_path<D>(Bh, 8, s, inv, t2);
-    }
-    __syncthreads();
-    const uint32_t h = hb + 16 * w + sl;
-    const bool live = h < (uint32_t)g.Vh;
-    if (live && q == 0) {
-        const int s = 16 * w + sl;
-        a.S[(size_t)px * g.Vh_pad + h] =
-            fmaxf(fmaxf(smax[s], smax[64 + s]), fmaxf(smax[128 + s], smax[192 + s]));
-    }
-    const h4v *fr = (const h4v *)a.Afrag;
-    h4v af[kFastTiles][kFastTiles];
-#pragma unroll
-    for (int mt = 0; mt < kFastTiles; mt++)
-#pragma unroll
-        for (int ks = 0; ks < kFastTiles; ks++) af[mt][ks] = fr[(mt * kFastTiles + ks) * 64 + lane];
+    const uint32_t wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int b0 = wg * per_wg, b1 = min(b0 + per_wg, 2 * nblk);
     h4v *G = (h4v *)a.G;
+    for (int blk = b0; blk < b1; blk++) {
+        const int px = blk >= nblk ? 1 : 0;
+        const uint32_t hb = (blk - px * nblk) * kFastSites;
+        {
+            const uint32_t h = hb + site;
+            const bool live = h < (uint32_t)g.Vh;
+            const int pA = pg, pB = pg + 4;
+            float bound = 0.f;
+            PathSite sA{}, sB{}, sC{};
+            if (live) {
+                const Coords c = decode(g, h, px);
+                if (pA > 0) sA = path_site(g, U, lblk, px, h, c, pA);
+                sB = path_site(g, U, lblk, px, h, c, pB);
+                if (pg == 0) sC = path_site(g, U, lblk, px, h, c, 8);
+                float m = source_maxabs<D>(g, v, pblk, px, h, sA, pA, 0.f);
+                m = source_maxabs<D>(g, v, pblk, px, h, sB, pB, m);
+                if (pg == 0) m = source_maxabs<D>(g, v, pblk, px, h, sC, 8, m);
+                bound = m * sqrtf(2.f * D);
+            }
+            const float inv = bound > 0.f ? 1.f / bound : 0.f;
+            if (live) {
+                stage_transport<D>(g, v, pblk, px, h, sA, pA, inv, Bh, site);
+                stage_transport<D>(g, v, pblk, px, h, sB, pB, inv, Bh, site);
+                if (pg == 0) stage_transport<D>(g, v, pblk, px, h, sC, 8, inv, Bh, site);
+            } else {
+                cx<float> z[4 * D];
 #pragma unroll
-    for (int cc = 0; cc < D; cc++) {
-        f4v acc[kFastTiles];
-#pragma unroll
-        for (int mt = 0; mt < kFastTiles; mt++) acc[mt] = f4v{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < kFastTiles; ks++) {
-            const int kq = 4 * ks + q;
-            const h4v b = kq < kFastKq ? Bh[(cc * kFastKq + kq) * 64 + 16 * w + sl] : h4v{0, 0, 0, 0};
-#pragma unroll
-            for (int mt = 0; mt < kFastTiles; mt++)
-                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16f16(af[mt][ks], b, acc[mt], 0, 0, 0);
+                for (int e = 0; e < 4 * D; e++) z[e] = mk<float>(0.f, 0.f);
+                stage_path<D>(Bh, fast_path_slot(pA), site, 0.f, z);
+                stage_path<D>(Bh, fast_path_slot(pB), site, 0.f, z);
+                if (pg == 0) stage_path<D>(Bh, fast_path_slot(8), site, 0.f, z);
+            }
+            sb[pg * kFastSites + site] = bound;
         }
-        if (!live) continue;
-        // rows 16 mt + 4 q + v: path 2 mt + q / 2, spins 2 (q % 2) and 2 (q % 2) + 1
+        lds_barrier();
+        const int col = 16 * w + sl;
+        const uint32_t h = hb + col;
+        const bool live = h < (uint32_t)g.Vh;
+        const float S = fmaxf(fmaxf(sb[col], sb[kFastSites + col]), fmaxf(sb[2 * kFastSites + col], sb[3 * kFastSites + col]));
+        const float invS = S > 0.f ? 1.f / S : 0.f;
+        if (live && q == 0) a.S[(size_t)px * g.Vh_pad + h] = S;
 #pragma unroll
-        for (int mt = 0; mt < kFastTiles; mt++) {
-            const int p = 2 * mt + q / 2;
-            if (p >= 9) continue;
-            G[g16_index<D>(g, p, px, (q & 1) * D + cc, h)] =
-                h4v{(_Float16)acc[mt][0], (_Float16)acc[mt][1], (_Float16)acc[mt][2], (_Float16)acc[mt][3]};
+        for (int cc = 0; cc < D; cc++) {
+            f4v acc[kFastTiles];
+#pragma unroll
+            for (int mt = 0; mt < kFastTiles; mt++) acc[mt] = f4v{0.f, 0.f, 0.f, 0.f};
+            // one K step at a time (its thread's bound rescales the product),
+            // fragments read from LDS, so few registers stay live
+#pragma unroll 1
+            for (int ks = 0; ks < kFastTiles; ks++) {
+                const h4v b = Bh[(cc * kFastSlotsKq + 4 * ks + q) * kFastSites + col];
+                const float f = sb[(ks < 2 ? 0 : ks - 1) * kFastSites + col] * invS;
+#pragma unroll
+                for (int mt = 0; mt < kFastTiles; mt++) {
+                    const f4v t = __builtin_amdgcn_mfma_f32_16x16x16f16(Afs[(mt * kFastTiles + ks) * 64 + lane], b,
+                                                                         f4v{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                    acc[mt] += f * t;
+                }
+            }
+            if (!live) continue;
+            // rows 16 mt + 4 q + v: path 2 mt + q / 2, spins 2 (q % 2) and 2 (q % 2) + 1
+#pragma unroll
+            for (int mt = 0; mt < kFastTiles; mt++) {
+                const int p = 2 * mt + q / 2;
+                if (p >= 9) continue;
+                // streamed: each value is read once, by the transport sum
+                __builtin_nontemporal_store(
+                    h4v{(_Float16)acc[mt][0], (_Float16)acc[mt][1], (_Float16)acc[mt][2], (_Float16)acc[mt][3]},
+                    &G[g16_index<D>(g, p, px, (q & 1) * D + cc, h)]);
+            }
         }
+        lds_barrier();
     }
 }
 
@@ -283,8 +360,11 @@ struct NetFastByD {
         if constexpr (D > kFastMaxD) {
             return fail(BSM_ERR_UNSUPPORTED, "the collapsed network runs for d_R <= 3");
         } else {
-            const int nb64 = (g.Vh + 63) / 64, nb256 = (g.Vh + 255) / 256;
-            k_net_mix16<D><<<2 * nb64, 256, 0, st>>>(g, a, nb64);
+            const int nbm = (g.Vh + kFastSites - 1) / kFastSites, nb256 = (g.Vh + 255) / 256;
+            // up to 4096 workgroups (two fit a CU), each over a contiguous range of blocks
+            const int per_wg = std::max(1, (2 * nbm + 4095) / 4096);
+            const int grid = (2 * nbm + per_wg - 1) / per_wg;
+            k_net_mix16<D><<<grid, 4 * kFastSites, 0, st>>>(g, a, nbm, per_wg);
             k_net_tsum16<D><<<2 * nb256, 256, 0, st>>>(g, a, nb256);
             BSM_HIP(hipGetLastError());
             return BSM_OK;
