@@ -452,10 +452,35 @@ def cpu_baseline(lat, Uf, psi, bytes_per_hop, min_seconds=10.0):
         total += time.perf_counter() - t0
         n *= 2
     rate = bytes_per_hop * reps / total / 1e9
+    # one thread: a short sample of the same hop
+    oracle.set_num_threads(1)
+    t0, reps1 = time.perf_counter(), 0
+    while reps1 < 2 or time.perf_counter() - t0 < 2.0:
+        oracle.hop(lat, Uf, psi, parity=reps1 & 1)
+        reps1 += 1
+    rate1 = bytes_per_hop * reps1 / (time.perf_counter() - t0) / 1e9
+    oracle.set_num_threads(cores)
     return {"value": rate, "unit": "GB/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "value_1_thread": rate1,
             "sample": f"{reps} FP64 even-odd hops of the full 32^3x64 SU(3) workload on the host "
-                      f"({total:.1f} s, doubling loop); GB/s counts the same algorithmic bytes per hop "
-                      f"as the GPU FP32 figure, so the ratio is a ratio of hop rates"}
+                      f"({total:.1f} s, doubling loop; {reps1} more on one thread); GB/s counts the same "
+                      f"algorithmic bytes per hop as the GPU FP32 figure, so the ratio is a ratio of hop rates"}
+
+
+def cpu_cg_small():
+    """The oracle's FP64 Schur CG to a 1e-10 true residual on the 16^3 x 32
+    SU(3) workload (kappa 0.1335, the same links and source as the GPU solves
+    of the learned-preconditioner section), on all host cores."""
+    import oracle
+    from paper_1401_3733_amd import inputs as gen
+    lat = gen.config_lattice(5)
+    U = oracle.represent(gen.config_links(5, lat), "fund")
+    b = gen.config_source(5, 3, lat)
+    t0 = time.perf_counter()
+    _, info = oracle.solve(lat, U, gen.CONFIGS[5]["kappa"], b, tol=1e-10, schur=True)
+    return {"seconds": round(time.perf_counter() - t0, 3), "iters": info["iters"], "true_rel_res": info["true_res"],
+            "cores": oracle.num_threads(),
+            "workload": "16^3x32 SU(3) fund, exp(0.5iH) links, kappa 0.1335, plain FP64 Schur CG to 1e-10"}
 
 
 def main():
@@ -529,7 +554,10 @@ def main():
     if "cpu" in sections:
         log("CPU oracle baseline ...")
         cpu = cpu_baseline(lat, Uf, psi, res["f32"]["bytes"])
-        log(f"  {cpu['value']:.2f} GB/s on {cpu['cores']} threads")
+        log(f"  {cpu['value']:.2f} GB/s on {cpu['cores']} threads, {cpu['value_1_thread']:.2f} GB/s on one")
+        log("CPU oracle CG on 16^3x32 ...")
+        cpu["cg_tts_16x16x16x32"] = cpu_cg_small()
+        log(f"  {cpu['cg_tts_16x16x16x32']}")
 
     r32 = res["f32"]
     traffic, traffic_note = measured_traffic()
