@@ -331,17 +331,20 @@ bsm_status bsm_dslash_eo_block(bsm_ctx ctx, const bsm_field_desc *desc, const vo
                                int32_t out_parity, int32_t dagger, const double *a, const void *x,
                                const double *b, const void *in, void *out, void *stream);
 /* Block hop launch plan per d_R: sites per wavefront (1, or 2 processed
- * interleaved with half the register budget per wavefront) and wavefronts
- * per workgroup (1, 2, 4).  bsm_block_autotune times every plan on the
+ * interleaved with half the register budget per wavefront), wavefronts
+ * per workgroup (1, 2, 4) and the site order (tiled = 1: tiles of a few
+ * lattice rows in t, z and y, so the neighbours of a site are visited close
+ * together and their 16-RHS blocks are fetched fewer times; needs T
+ * divisible by 2 or 3 and LY, LZ even, else BSM_ERR_ARG).  bsm_block_autotune times every plan on the
  * given block links (scratch fields owned by the context) and keeps the
  * fastest; the batched solver tunes once per d_R and context unless a plan
  * was set by hand.  us: time per hop of the tuned plan (0: default plan,
  * -1: set by hand).  Synchronous. */
 bsm_status bsm_block_autotune(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_block, void *stream);
 bsm_status bsm_set_block_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t sites_per_wave,
-                              int32_t waves_per_group);
+                              int32_t waves_per_group, int32_t tiled);
 bsm_status bsm_get_block_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t *sites_per_wave,
-                              int32_t *waves_per_group, float *us);
+                              int32_t *waves_per_group, int32_t *tiled, float *us);
 /* Solve D(kappa_r) x_r = b_r for n_rhs right-hand sides with their own
  * kappa_r (Section II.B's inversion, for a family of masses).  b and x are
  * n_rhs consecutive full internal FP64 fields; U_rep64 are FP64 links.

@@ -407,6 +407,7 @@ bsm_status bsm_dslash_eo_block(bsm_ctx ctx, const bsm_field_desc *desc, const vo
     h.np = 1;
     h.spw = ctx->block_plans[desc->d_R].spw;
     h.wpb = ctx->block_plans[desc->d_R].wpb;
+    if (ctx->block_plans[desc->d_R].tiled) h.tile = block_tile_for(ctx->g);
     return launch_hop_block(ctx->g, desc->d_R, h, (hipStream_t)stream);
 }
 
@@ -422,24 +423,29 @@ bsm_status bsm_block_autotune(bsm_ctx ctx, const bsm_field_desc *desc, const voi
 }
 
 bsm_status bsm_set_block_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t sites_per_wave,
-                              int32_t waves_per_group) {
+                              int32_t waves_per_group, int32_t tiled) {
     CHECK(check_block(ctx, desc));
     if (sites_per_wave != 1 && sites_per_wave != 2) return fail(BSM_ERR_ARG, "sites_per_wave must be 1 or 2");
     if (waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4)
         return fail(BSM_ERR_ARG, "waves_per_group must be 1, 2 or 4");
+    if (tiled != 0 && tiled != 1) return fail(BSM_ERR_ARG, "tiled must be 0 or 1");
+    if (tiled && block_tile_for(ctx->g).tt == 0)
+        return fail(BSM_ERR_ARG, "tiled order needs T divisible by 2 or 3 and LY, LZ even");
     BlockPlan &b = ctx->block_plans[desc->d_R];
     b.spw = sites_per_wave;
     b.wpb = waves_per_group;
+    b.tiled = tiled;
     b.us = -1.f;   // set by hand: not tuned, and the batched solver keeps it
     return BSM_OK;
 }
 
 bsm_status bsm_get_block_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t *sites_per_wave,
-                              int32_t *waves_per_group, float *us) {
+                              int32_t *waves_per_group, int32_t *tiled, float *us) {
     CHECK(check_block(ctx, desc));
     const BlockPlan &b = ctx->block_plans[desc->d_R];
     if (sites_per_wave) *sites_per_wave = b.spw;
     if (waves_per_group) *waves_per_group = b.wpb;
+    if (tiled) *tiled = b.tiled;
     if (us) *us = b.us;
     return BSM_OK;
 }

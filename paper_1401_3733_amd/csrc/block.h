@@ -16,6 +16,30 @@ inline size_t block_site_bytes(int d) { return (size_t)d * 4 * kNR * 8; }
 inline size_t block_parity_bytes(const Geom &g, int d) { return block_site_bytes(d) * g.Vh_pad; }
 inline size_t block_link_bytes(const Geom &g, int d) { return (size_t)8 * g.Vh_pad * d * d * 4; }
 
+// Site order of the block hops.  Logical site s walks tiles of tt x tz x ty
+// lattice rows (full x extent), rows y-fastest inside a tile, tiles in
+// (t, z, y) order, so all eight neighbours of a site lie within a few
+// hundred sites of it in the walk (a plain half-index walk puts the z and t
+// neighbours 2 LX/2 LY and LX/2 LY LZ sites away, beyond what is in flight,
+// and re-fetches their 16-RHS blocks).  tt = 0: the plain walk.
+struct BlockTile { int tt = 0, tz = 0, ty = 0; };
+// largest extents from {6, 4, 3, 2} (t) and {4, 2} (z, y) dividing the
+// lattice; tt = 0 when no tiling fits
+BlockTile block_tile_for(const Geom &g);
+__device__ inline uint32_t block_site(const Geom &g, const BlockTile &b, uint32_t s) {
+    if (b.tt == 0) return s;
+    const uint32_t row = g.div_xh.div(s), xh = s - row * g.LXh;
+    uint32_t r = row;
+    const uint32_t yi = r % b.ty; r /= b.ty;
+    const uint32_t zi = r % b.tz; r /= b.tz;
+    const uint32_t ti = r % b.tt; r /= b.tt;
+    const uint32_t nyb = g.L[2] / b.ty, nzb = g.L[3] / b.tz;
+    const uint32_t yb = r % nyb; r /= nyb;
+    const uint32_t zb = r % nzb, tb = r / nzb;
+    const uint32_t t = tb * b.tt + ti, z = zb * b.tz + zi, y = yb * b.ty + yi;
+    return ((t * g.L[3] + z) * g.L[2] + y) * g.LXh + xh;
+}
+
 struct BlockHopArgs {
     const float *U;          // block links
     const float2 *in[2];     // in[p]: parity block read for output parity p
@@ -27,6 +51,7 @@ struct BlockHopArgs {
     int p0, np;
     double *norm_partials;   // [workgroup][kNR]
     int spw = 1, wpb = 4;    // plan: sites per wavefront, wavefronts per workgroup
+    BlockTile tile;          // plan: site order
 };
 
 bsm_status launch_hop_block(const Geom &g, int d, const BlockHopArgs &a, hipStream_t st);
@@ -53,6 +78,7 @@ struct BlockHop64Args {
     int use_x;
     int dagger;
     int p0, np;
+    BlockTile tile;          // site order (block_tile_for)
 };
 bsm_status launch_hop_block64(const Geom &g, int d, const BlockHop64Args &a, hipStream_t st);
 bsm_status launch_gauge_to_block64(const Geom &g, int d, const void *U_rep64, double *U_block, hipStream_t st);

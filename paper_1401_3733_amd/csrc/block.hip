@@ -133,7 +133,7 @@ void k_hop_block(Geom g, BlockHopArgs a, int nblk) {
     for (int j = 0; j < S; j++) {
         const uint32_t hj = base + wave + wpb * j;
         live[j] = hj < (uint32_t)g.Vh;
-        h[j] = live[j] ? hj : base + wave;   // a dead second site repeats the first (never stored)
+        h[j] = block_site(g, a.tile, live[j] ? hj : base + wave);   // a dead second site repeats the first (never stored)
     }
     double nrm = 0.0;
     if (live[0]) {
@@ -190,6 +190,18 @@ void k_hop_block(Geom g, BlockHopArgs a, int nblk) {
     }
 }
 
+BlockTile block_tile_for(const Geom &g) {
+    BlockTile b;
+    for (int t : {6, 4, 3, 2})
+        if (g.L[0] % t == 0) { b.tt = t; break; }
+    for (int z : {4, 2})
+        if (g.L[3] % z == 0) { b.tz = z; break; }
+    for (int y : {4, 2})
+        if (g.L[2] % y == 0) { b.ty = y; break; }
+    if (b.tt == 0 || b.tz == 0 || b.ty == 0) b = BlockTile{};
+    return b;
+}
+
 static int block_sites_per_wg(const BlockHopArgs &a) { return a.wpb * a.spw; }
 
 int hop_block_grid(const Geom &g, const BlockHopArgs &a) {
@@ -229,6 +241,8 @@ bsm_status block_autotune(bsm_ctx ctx, int d, const float *U_block, float2 *scra
     BlockPlan best;
     best.us = 0.f;
     bsm_status status = BSM_OK;
+    const BlockTile tile = block_tile_for(g);
+    for (int tiled = 0; tiled <= (tile.tt ? 1 : 0) && status == BSM_OK; tiled++)
     for (int spw = 1; spw <= 2 && status == BSM_OK; spw++) {
         for (int wpb : {1, 2, 4}) {
             BlockHopArgs a{};
@@ -240,6 +254,7 @@ bsm_status block_autotune(bsm_ctx ctx, int d, const float *U_block, float2 *scra
             for (int r = 0; r < kNR; r++) { a.a[r] = 0.f; a.b[r] = 1.f; }
             a.spw = spw;
             a.wpb = wpb;
+            if (tiled) a.tile = tile;
             const int reps = 5;
             if ((status = launch_hop_block(g, d, a, st)) != BSM_OK) break;   // warm-up
             if (hipEventRecord(e0, st) != hipSuccess) { status = fail(BSM_ERR_HIP, "event"); break; }
@@ -255,6 +270,7 @@ bsm_status block_autotune(bsm_ctx ctx, int d, const float *U_block, float2 *scra
             if (best.us == 0.f || us < best.us) {
                 best.spw = spw;
                 best.wpb = wpb;
+                best.tiled = tiled;
                 best.us = us;
             }
         }

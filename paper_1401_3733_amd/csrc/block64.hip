@@ -106,9 +106,10 @@ void k_hop_block64(Geom g, BlockHop64Args a, int nblk) {
     const int r = lane & 15, q = lane >> 4;
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
     const int pi = lb >= (uint32_t)nblk ? 1 : 0;
-    const uint32_t h = (lb - pi * nblk) * 4 + wave;
+    const uint32_t s = (lb - pi * nblk) * 4 + wave;
     const int p = a.p0 + pi;
-    if (h >= (uint32_t)g.Vh) return;
+    if (s >= (uint32_t)g.Vh) return;
+    const uint32_t h = block_site(g, a.tile, s);
     d4 acc[4][2];
 #pragma unroll
     for (int s = 0; s < 4; s++) acc[s][0] = acc[s][1] = d4{0.0, 0.0, 0.0, 0.0};

@@ -157,6 +157,7 @@ struct HopPlan {
 // multi-RHS hop plan per d_R (sites per wavefront, wavefronts per workgroup)
 struct BlockPlan {
     int spw = 1, wpb = 4;
+    int tiled = 0;    // 1: tiled site order (block_tile_for)
     float us = 0.f;   // measured time per hop when tuned (0: default plan)
 };
 

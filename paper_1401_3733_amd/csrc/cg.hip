@@ -503,6 +503,7 @@ static bsm_status block_op(BlockSolve &B, int dagger, const float2 *in, float2 *
     a.np = 1;
     a.spw = B.ctx->block_plans[B.d].spw;
     a.wpb = B.ctx->block_plans[B.d].wpb;
+    if (B.ctx->block_plans[B.d].tiled) a.tile = block_tile_for(B.g);
     // tmp_o = H_oe in_e
     a.p0 = 1;
     a.in[1] = in;
@@ -533,6 +534,8 @@ static bsm_status block_op64(BlockSolve &B, int dagger, const double2 *in, doubl
     BlockHop64Args a{};
     a.U = B.Ublk64;
     a.dagger = dagger;
+    // the FP64 blocks follow the site order tuned for the FP32 ones
+    if (B.ctx->block_plans[B.d].tiled) a.tile = block_tile_for(B.g);
     a.np = 1;
     a.p0 = 1;
     a.in[1] = in;

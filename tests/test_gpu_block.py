@@ -155,13 +155,17 @@ PLANS = [(s, w) for s in (1, 2) for w in (1, 2, 4)]
 
 
 @pytest.mark.parametrize("N", [3, 4])
+@pytest.mark.parametrize("tiled", [0, 1])
 @pytest.mark.parametrize("spw,wpb", PLANS)
-def test_every_block_plan_gives_the_same_operator(N, spw, wpb):
-    note(f"block plan spw={spw} wpb={wpb} N={N}")
+def test_every_block_plan_gives_the_same_operator(N, spw, wpb, tiled):
+    """every site is visited once under every plan: the tiled order (tiles of
+    4 x 2 x 4 rows here, t x z x y) and the plain one give the same operator"""
+    note(f"block plan spw={spw} wpb={wpb} tiled={tiled} N={N}")
     lat = gen.Lattice(8, 6, 4, 6)
     S, UR, Ub = _block_setup(lat, N, 760 + N)
-    S.ctx.bsm_set_block_plan(S.desc, spw, wpb)
-    assert S.ctx.bsm_get_block_plan(S.desc)["sites_per_wave"] == spw
+    S.ctx.bsm_set_block_plan(S.desc, spw, wpb, tiled)
+    plan = S.ctx.bsm_get_block_plan(S.desc)
+    assert plan["sites_per_wave"] == spw and plan["tiled"] == tiled
     d = S.d
     psi = gen.gaussian_spinor(lat, d, 761, n_rhs=16)
     A = S.ctx.new_block(S.desc)
@@ -179,15 +183,17 @@ def test_every_block_plan_gives_the_same_operator(N, spw, wpb):
             assert rel(got[r][m], ref[m]) < 2e-6
 
 
+@pytest.mark.parametrize("tiled", [0, 1])
 @pytest.mark.parametrize("spw,wpb", PLANS)
-def test_batched_solve_under_every_block_plan(spw, wpb):
-    """the fused per-RHS norms of the block hop depend on the plan's workgroup shape"""
+def test_batched_solve_under_every_block_plan(spw, wpb, tiled):
+    """the fused per-RHS norms of the block hop depend on the plan's workgroup
+    shape and site order; the FP64 block hop follows the site order"""
     import torch
-    note(f"batched solve plan spw={spw} wpb={wpb}")
+    note(f"batched solve plan spw={spw} wpb={wpb} tiled={tiled}")
     lat = gen.Lattice(4, 4, 4, 6)
     Uf = gen.gauge_links(lat, 3, "haar", 770)
     S = Setup(lat, 3, "adj", Uf, prec="f64")
-    S.ctx.bsm_set_block_plan(S.desc, spw, wpb)
+    S.ctx.bsm_set_block_plan(S.desc, spw, wpb, tiled)
     UR = oracle.represent(Uf, "adj").real.astype(np.complex128)
     kappas = [0.11, 0.12, 0.125]
     b = gen.gaussian_spinor(lat, 8, 771, n_rhs=3)
@@ -206,6 +212,9 @@ def test_block_autotune_picks_a_plan():
     S, UR, Ub = _block_setup(lat, 4, 780)
     plan = S.ctx.bsm_block_autotune(S.desc, Ub)
     assert plan["us"] > 0 and (plan["sites_per_wave"], plan["waves_per_group"]) in PLANS
+    assert plan["tiled"] in (0, 1)
+    with pytest.raises(bsm.BsmError):
+        S.ctx.bsm_set_block_plan(S.desc, 1, 4, 2)
     with pytest.raises(bsm.BsmError):
         S.ctx.bsm_set_block_plan(S.desc, 3, 4)
     with pytest.raises(bsm.BsmError):
