@@ -83,7 +83,8 @@ struct BlockHop64Args {
 bsm_status launch_hop_block64(const Geom &g, int d, const BlockHop64Args &a, hipStream_t st);
 bsm_status launch_gauge_to_block64(const Geom &g, int d, const void *U_rep64, double *U_block, hipStream_t st);
 // mode 0: block = the parity block at std_off of the n_rhs F64 fields (stride std_stride), zero slots beyond;
-// mode 1: block32 = (float) block for the RHS selected in sel
+// mode 1: block32 = (float) block for the RHS selected in sel;
+// mode 2: the parity block at std_off of the RHS selected in sel = block (std64 is written)
 bsm_status launch_block64_io(const Geom &g, int d, int n_rhs, unsigned sel, const char *std64, size_t std_stride,
                              size_t std_off, double2 *block, float2 *block32, int mode, hipStream_t st);
 bsm_status block64_sub(const Geom &g, int d, double2 *out, const double2 *a, const double2 *b, hipStream_t st);

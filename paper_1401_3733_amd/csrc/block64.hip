@@ -193,6 +193,7 @@ __global__ __launch_bounds__(256) void k_block64_io(Geom g, int d, int n_rhs, un
             }
             continue;
         }
+        if (mode == 2 && (r >= n_rhs || !((sel >> r) & 1u))) continue;
         if (r >= n_rhs) {
             block[e] = make_double2(0.0, 0.0);
             continue;
@@ -202,7 +203,15 @@ __global__ __launch_bounds__(256) void k_block64_io(Geom g, int d, int n_rhs, un
         const size_t hc = hcs / 4;
         const int c = (int)(hc % d);
         const size_t h = hc / d;
-        block[e] = *((const double2 *)(std64 + r * std_stride + std_off) + (size_t)(s * d + c) * g.Vh_pad + h);
+        const size_t se = (size_t)(s * d + c) * g.Vh_pad + h;
+        if (mode == 2) {
+            // std64 is the caller's writable field in this mode; its padding
+            // sites stay untouched (the block's may hold stale values)
+            if (h >= (size_t)g.Vh) continue;
+            ((double2 *)(const_cast<char *>(std64) + r * std_stride + std_off))[se] = block[e];
+            continue;
+        }
+        block[e] = *((const double2 *)(std64 + r * std_stride + std_off) + se);
     }
 }
 
@@ -224,9 +233,11 @@ __global__ __launch_bounds__(256) void k_block64_sub(size_t n, double2 *out, con
     }
 }
 
-__global__ __launch_bounds__(256) void k_block64_norm(size_t n, const double2 *v, double *partials) {
+// padding sites (h >= Vh) are skipped: operator outputs never write them
+__global__ __launch_bounds__(256) void k_block64_norm(size_t n, size_t live, const double2 *v, double *partials) {
     double nrm = 0;
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+        if (e >= live) break;
         const double2 t = v[e];
         nrm += t.x * t.x + t.y * t.y;
     }
@@ -269,7 +280,7 @@ bsm_status block64_sub(const Geom &g, int d, double2 *out, const double2 *a, con
 
 bsm_status block64_norms(const Geom &g, int d, const double2 *v, double *partials, double *dst, hipStream_t st) {
     const int nb = block64_grid(g, d);
-    k_block64_norm<<<nb, 256, 0, st>>>((size_t)g.Vh_pad * d * 4 * kNR, v, partials);
+    k_block64_norm<<<nb, 256, 0, st>>>((size_t)g.Vh_pad * d * 4 * kNR, (size_t)g.Vh * d * 4 * kNR, v, partials);
     k_block64_total<<<1, 256, 0, st>>>(partials, nb, dst);
     BSM_HIP(hipGetLastError());
     return BSM_OK;

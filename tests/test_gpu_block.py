@@ -76,8 +76,10 @@ def test_block_hop_without_x():
         assert rel(got[r][par == 0], ref[par == 0]) < 2e-6
 
 
-@pytest.mark.parametrize("n_rhs", [16, 3])
+@pytest.mark.parametrize("n_rhs", [16, 7, 3])
 def test_batched_solve_adjoint(n_rhs):
+    """16 and 7 RHS retire together and take the block operator's FP64 true
+    residual (and odd-site rebuild); 3 RHS take the per-RHS one"""
     note(f"batched solve adjoint n_rhs={n_rhs}")
     lat = gen.Lattice(8, 4, 4, 6)
     Uf = gen.gauge_links(lat, 4, "haar", 720)
