@@ -482,7 +482,7 @@ struct BlockSolve {
     size_t full64, bb64, bbB;
     // FP64 per RHS
     std::vector<Op> ops;
-    char *bh, *t64, *tfull, *tmp64;
+    char *t64, *tfull, *tmp64;
     std::vector<double> bnorm2, rhs_norm2;
     // FP64 block fields for the reliable updates (all RHS share each link load)
     double *Ublk64;
@@ -578,9 +578,9 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
     const size_t linkB = block_link_bytes(g, d);
     // partials for any plan (the autotuner below may change it)
     const size_t parts = std::max((size_t)hop_block_grid_max(g), (size_t)block_blas_grid(g, d, 1)) * kNR;
-    // 21 carve-outs below, each rounded up to 256 bytes
+    // 20 carve-outs below, each rounded up to 256 bytes
     const size_t link64 = block64_link_bytes(g, d), bb64B = block64_parity_bytes(g, d);
-    size_t need = linkB + 6 * B.bbB + (size_t)(n + 4) * B.bb64 + parts * 8 +
+    size_t need = linkB + 6 * B.bbB + (size_t)4 * B.bb64 + parts * 8 +
                   (size_t)kBlockPresum * kNR * 8 + block_scal_doubles() * 8 + 64 * sizeof(int) + link64 +
                   5 * bb64B + 22 * 256;
     void *work = nullptr;
@@ -590,7 +590,6 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
     B.Ublk = (float *)take(linkB);
     B.p = (float2 *)take(B.bbB); B.t = (float2 *)take(B.bbB); B.q = (float2 *)take(B.bbB);
     B.xlo = (float2 *)take(B.bbB); B.rlo = (float2 *)take(B.bbB); B.tmpB = (float2 *)take(B.bbB);
-    B.bh = take(n * B.bb64);
     B.t64 = take(B.bb64); B.tmp64 = take(B.bb64); B.tfull = take(2 * B.bb64);
     B.partials = (double *)take(parts * 8);
     B.presum = (double *)take((size_t)kBlockPresum * kNR * 8);
@@ -608,46 +607,8 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
     BSM_HIP(hipMemsetAsync(B.x, 0, n * B.full64, st));
     B.bnorm2.assign(n, 0.0);
     B.rhs_norm2.assign(n, 0.0);
-    Vec none{nullptr, BSM_F64};
-    for (int r = 0; r < n; r++) {
-        Op &o = B.ops[r];
-        o.tmp = B.tmp64;
-        const char *br = B.b + r * B.full64;
-        char *bhr = B.bh + r * B.bb64;
-        HopArgs a{};
-        a.U = o.U; a.p0 = 0; a.np = 1;
-        a.in[0] = br + B.bb64; a.x[0] = br; a.out[0] = bhr;
-        a.a = 1.0; a.b = o.kappa;
-        TRY(launch_hop(g, d, o.real, BSM_F64, BSM_F64, a, st));
-        TRY(blas_dot(g, d, 2, Vec{(void *)br, BSM_F64}, none, B.ctx->partials, st));
-        B.bnorm2[r] = reduce_to_host(B.ctx, B.ctx->partials, blas_blocks(g, 2), st);
-        TRY(op_apply(o, 1, bhr, B.t64, false, nullptr, st));
-        TRY(blas_dot(g, d, 1, Vec{B.t64, BSM_F64}, none, B.ctx->partials, st));
-        B.rhs_norm2[r] = reduce_to_host(B.ctx, B.ctx->partials, blas_blocks(g, 1), st);
-    }
-    // ---- residuals: r64_r = M_r^dag (bhat_r - M_r x_r) for the selected RHS,
-    //      copied into the block residual; returns |r64_r|^2
-    std::vector<double> rr(kNR, 0.0), maxrr(kNR, 0.0), trig(n, B.prm->tol), res(n, INFINITY);
-    //      (FP64 block operator: every RHS at once, sharing the link loads)
+    for (int r = 0; r < n; r++) B.ops[r].tmp = B.tmp64;
     const unsigned all = n >= 32 ? 0xffffffffu : ((1u << n) - 1u);
-    TRY(launch_block64_io(g, d, n, all, B.bh, B.bb64, 0, B.BH64, nullptr, 0, st));
-    auto refresh = [&](unsigned sel) -> bsm_status {
-        TRY(launch_block64_io(g, d, n, all, B.x, B.full64, 0, B.X64, nullptr, 0, st));
-        TRY(block_op64(B, 0, B.X64, B.T2));                 // M x
-        TRY(block64_sub(g, d, B.T2, B.BH64, B.T2, st));      // bhat - M x
-        TRY(block_op64(B, 1, B.T2, B.X64));                 // M^dag (...)
-        TRY(block64_norms(g, d, B.X64, B.partials, B.presum, st));
-        double h16[kNR];
-        BSM_HIP(hipMemcpyAsync(h16, B.presum, sizeof h16, hipMemcpyDeviceToHost, st));
-        BSM_HIP(hipStreamSynchronize(st));
-        for (int r = 0; r < n; r++)
-            if ((sel >> r) & 1u) rr[r] = h16[r];
-        return launch_block64_io(g, d, n, sel, nullptr, 0, 0, B.X64, B.rlo, 1, st);
-    };
-    // FP64 true residuals |b_r - D_r x_r| / |b_r| of every RHS at once with the
-    // block operator (one link load for all): the odd sites are rebuilt,
-    // x_o = b_o + kappa_r H_oe x_e, and written back for the RHS in sel; then
-    // r_o = b_o - (x_o - kappa_r H_oe x_e) and r_e = b_e - (x_e - kappa_r H_eo x_o)
     auto hop64 = [&](int p0, const double2 *in, const double2 *xin, double sgn, double2 *out) -> bsm_status {
         BlockHop64Args a{};
         a.U = B.Ublk64;
@@ -665,6 +626,45 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
         }
         return launch_hop_block64(g, d, a, st);
     };
+    // ---- right-hand sides on the FP64 block operator, every RHS at once:
+    //      |b_r|^2, bhat_e = b_e + kappa_r H_eo b_o, |M_r^dag bhat_r|^2
+    {
+        double h48[3 * kNR];
+        TRY(launch_block64_io(g, d, n, all, B.b, B.full64, B.bb64, B.T2, nullptr, 0, st));   // b_o
+        TRY(launch_block64_io(g, d, n, all, B.b, B.full64, 0, B.T3, nullptr, 0, st));        // b_e
+        TRY(block64_norms(g, d, B.T2, B.partials, B.presum, st));
+        TRY(block64_norms(g, d, B.T3, B.partials, B.presum + kNR, st));
+        TRY(hop64(0, B.T2, B.T3, 1.0, B.BH64));
+        TRY(block_op64(B, 1, B.BH64, B.X64));
+        TRY(block64_norms(g, d, B.X64, B.partials, B.presum + 2 * kNR, st));
+        BSM_HIP(hipMemcpyAsync(h48, B.presum, sizeof h48, hipMemcpyDeviceToHost, st));
+        BSM_HIP(hipStreamSynchronize(st));
+        for (int r = 0; r < n; r++) {
+            B.bnorm2[r] = h48[r] + h48[kNR + r];
+            B.rhs_norm2[r] = h48[2 * kNR + r];
+        }
+    }
+    // ---- residuals: r64_r = M_r^dag (bhat_r - M_r x_r) for the selected RHS,
+    //      copied into the block residual; returns |r64_r|^2
+    std::vector<double> rr(kNR, 0.0), maxrr(kNR, 0.0), trig(n, B.prm->tol), res(n, INFINITY);
+    //      (FP64 block operator: every RHS at once, sharing the link loads)
+    auto refresh = [&](unsigned sel) -> bsm_status {
+        TRY(launch_block64_io(g, d, n, all, B.x, B.full64, 0, B.X64, nullptr, 0, st));
+        TRY(block_op64(B, 0, B.X64, B.T2));                 // M x
+        TRY(block64_sub(g, d, B.T2, B.BH64, B.T2, st));      // bhat - M x
+        TRY(block_op64(B, 1, B.T2, B.X64));                 // M^dag (...)
+        TRY(block64_norms(g, d, B.X64, B.partials, B.presum, st));
+        double h16[kNR];
+        BSM_HIP(hipMemcpyAsync(h16, B.presum, sizeof h16, hipMemcpyDeviceToHost, st));
+        BSM_HIP(hipStreamSynchronize(st));
+        for (int r = 0; r < n; r++)
+            if ((sel >> r) & 1u) rr[r] = h16[r];
+        return launch_block64_io(g, d, n, sel, nullptr, 0, 0, B.X64, B.rlo, 1, st);
+    };
+    // FP64 true residuals |b_r - D_r x_r| / |b_r| of every RHS at once with the
+    // block operator (one link load for all): the odd sites are rebuilt,
+    // x_o = b_o + kappa_r H_oe x_e, and written back for the RHS in sel; then
+    // r_o = b_o - (x_o - kappa_r H_oe x_e) and r_e = b_e - (x_e - kappa_r H_eo x_o)
     auto block_residuals = [&](unsigned sel, std::vector<double> &res_out) -> bsm_status {
         const size_t off_o = B.bb64;
         TRY(launch_block64_io(g, d, n, all, B.x, B.full64, 0, B.X64, nullptr, 0, st));       // x_e
