@@ -104,6 +104,9 @@ bsm_status launch_pack_block(const Geom &g, int d, int n_rhs, const void *canon,
 //   mode 0: block = std (RHS slots >= n_rhs are zeroed) ;  mode 1: std += block
 bsm_status launch_std_block(const Geom &g, int d, int n_rhs, unsigned sel, char *std64, size_t std_stride,
                             size_t std_off, float2 *block, int mode, hipStream_t st);
+// the same for an FP64 block: mode 0 block = std, mode 2 std = block (sites < Vh)
+bsm_status launch_block64_std(const Geom &g, int d, int n_rhs, unsigned sel, char *std64, size_t std_stride,
+                              size_t std_off, double2 *block, int mode, hipStream_t st);
 
 // per-RHS vector kernels on nblk parity blocks of block fields (F32)
 // partials layout [workgroup][kNR]; returns the workgroup count

@@ -341,41 +341,96 @@ bsm_status launch_pack_block(const Geom &g, int d, int n_rhs, const void *canon,
 }
 
 // element e of one parity block: r = e % 16, (h, c, s) from e / 16
-__global__ __launch_bounds__(256) void k_std_block(Geom g, int d, int n_rhs, unsigned sel, char *std64,
-                                                   size_t std_stride, size_t std_off, float2 *block, int mode) {
-    const size_t n = (size_t)g.Vh_pad * d * 4 * kNR;
-    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
-        const int r = (int)(e % kNR);
-        const size_t hcs = e / kNR;
-        const int s = (int)(hcs % 4);
-        const size_t hc = hcs / 4;
-        const int c = (int)(hc % d);
-        const size_t h = hc / d;
-        if (r >= n_rhs) {
-            if (mode == 0) block[e] = make_float2(0.f, 0.f);
-            continue;
+// Block <-> standard layout through an LDS tile: a workgroup owns one
+// (colour, spin) plane of 64 consecutive sites for all 16 RHS, reads one side
+// with consecutive lanes on consecutive addresses (16 RHS of a site on the
+// block side, 64 sites of one RHS on the standard side), transposes in LDS
+// and writes the other side the same way.
+//   OP 0: block = std (RHS >= n_rhs zeroed, other unselected RHS untouched)
+//   OP 1: std += block  (selected RHS)
+//   OP 2: std = block   (selected RHS, sites < Vh only)
+__device__ inline float2 blk_from(double2 x, float2) { return make_float2((float)x.x, (float)x.y); }
+__device__ inline double2 blk_from(double2 x, double2) { return x; }
+__device__ inline double2 blk_to64(float2 v) { return make_double2((double)v.x, (double)v.y); }
+__device__ inline double2 blk_to64(double2 v) { return v; }
+
+template <class BT, int OP>
+__global__ __launch_bounds__(256) void k_block_std(Geom g, int d, int n_rhs, unsigned sel, char *std64,
+                                                   size_t std_stride, size_t std_off, BT *block) {
+    __shared__ BT tile[kNR][65];
+    const uint32_t nth = ((uint32_t)g.Vh_pad + 63) / 64;
+    const uint32_t hb = blockIdx.x % nth, cs = blockIdx.x / nth;
+    const int c = (int)(cs / 4), sp = (int)(cs % 4);
+    const uint32_t h0 = hb * 64;
+    const int t = threadIdx.x;
+    const size_t plane = (size_t)(sp * d + c) * g.Vh_pad;
+    auto bidx = [&](int r, uint32_t h) { return (((size_t)h * d + c) * 4 + sp) * kNR + r; };
+    auto sptr = [&](int r, uint32_t h) { return (double2 *)(std64 + (size_t)r * std_stride + std_off) + plane + h; };
+    if constexpr (OP == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int j = t + 256 * k, hl = j & 63, r = j >> 6;
+            const uint32_t h = h0 + hl;
+            BT v{};
+            if (h < (uint32_t)g.Vh_pad && r < n_rhs) v = blk_from(*sptr(r, h), BT{});
+            tile[r][hl] = v;
         }
-        if (!((sel >> r) & 1u)) continue;
-        double2 *sv = (double2 *)(std64 + r * std_stride + std_off) + (size_t)(s * d + c) * g.Vh_pad + h;
-        if (mode == 0) {
-            const double2 v = *sv;
-            block[e] = make_float2((float)v.x, (float)v.y);
-        } else {
-            const float2 v = block[e];
-            sv->x += (double)v.x;
-            sv->y += (double)v.y;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int i = t + 256 * k, r = i & 15, hl = i >> 4;
+            const uint32_t h = h0 + hl;
+            if (h >= (uint32_t)g.Vh_pad) continue;
+            if (r < n_rhs && !((sel >> r) & 1u)) continue;
+            block[bidx(r, h)] = tile[r][hl];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int i = t + 256 * k, r = i & 15, hl = i >> 4;
+            const uint32_t h = h0 + hl;
+            tile[r][hl] = h < (uint32_t)g.Vh_pad ? block[bidx(r, h)] : BT{};
+        }
+        __syncthreads();
+        const uint32_t hmax = OP == 2 ? (uint32_t)g.Vh : (uint32_t)g.Vh_pad;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int j = t + 256 * k, hl = j & 63, r = j >> 6;
+            const uint32_t h = h0 + hl;
+            if (h >= hmax || r >= n_rhs || !((sel >> r) & 1u)) continue;
+            double2 *sv = sptr(r, h);
+            const double2 v = blk_to64(tile[r][hl]);
+            if constexpr (OP == 1) {
+                double2 o = *sv;
+                o.x += v.x;
+                o.y += v.y;
+                *sv = o;
+            } else {
+                *sv = v;
+            }
         }
     }
 }
 
-bsm_status launch_std_block(const Geom &g, int d, int n_rhs, unsigned sel, char *std64, size_t std_stride,
-                            size_t std_off, float2 *block, int mode, hipStream_t st) {
-    const size_t n = (size_t)g.Vh_pad * d * 4 * kNR;
-    size_t nb = (n + 255) / 256;
-    if (nb > 65536) nb = 65536;
-    k_std_block<<<(int)nb, 256, 0, st>>>(g, d, n_rhs, sel, std64, std_stride, std_off, block, mode);
+template <class BT, int OP>
+static bsm_status run_block_std(const Geom &g, int d, int n_rhs, unsigned sel, char *std64, size_t std_stride,
+                                size_t std_off, BT *block, hipStream_t st) {
+    const size_t nwg = (size_t)((g.Vh_pad + 63) / 64) * d * 4;
+    k_block_std<BT, OP><<<(unsigned)nwg, 256, 0, st>>>(g, d, n_rhs, sel, std64, std_stride, std_off, block);
     BSM_HIP(hipGetLastError());
     return BSM_OK;
+}
+
+bsm_status launch_std_block(const Geom &g, int d, int n_rhs, unsigned sel, char *std64, size_t std_stride,
+                            size_t std_off, float2 *block, int mode, hipStream_t st) {
+    if (mode == 0) return run_block_std<float2, 0>(g, d, n_rhs, sel, std64, std_stride, std_off, block, st);
+    return run_block_std<float2, 1>(g, d, n_rhs, sel, std64, std_stride, std_off, block, st);
+}
+
+bsm_status launch_block64_std(const Geom &g, int d, int n_rhs, unsigned sel, char *std64, size_t std_stride,
+                              size_t std_off, double2 *block, int mode, hipStream_t st) {
+    if (mode == 0) return run_block_std<double2, 0>(g, d, n_rhs, sel, std64, std_stride, std_off, block, st);
+    return run_block_std<double2, 2>(g, d, n_rhs, sel, std64, std_stride, std_off, block, st);
 }
 
 // ------------------------------------------------------------ vector ops

@@ -180,47 +180,28 @@ bsm_status launch_gauge_to_block64(const Geom &g, int d, const void *U_rep64, do
 // element e of one FP64 parity block: r = e % 16, (h, c, s) from e / 16
 // mode 0: block = std parity block of RHS r (r < n_rhs; zero for r >= n_rhs)
 // mode 1: block32[e] = (float) block[e] for the RHS selected in sel
-__global__ __launch_bounds__(256) void k_block64_io(Geom g, int d, int n_rhs, unsigned sel, const char *std64,
-                                                    size_t std_stride, size_t std_off, double2 *block,
-                                                    float2 *block32, int mode) {
+// block32 = (float) block for the RHS selected in sel (same layout)
+__global__ __launch_bounds__(256) void k_block64_to32(Geom g, int d, int n_rhs, unsigned sel, const double2 *block,
+                                                      float2 *block32) {
     const size_t n = (size_t)g.Vh_pad * d * 4 * kNR;
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
         const int r = (int)(e % kNR);
-        if (mode == 1) {
-            if (r < n_rhs && ((sel >> r) & 1u)) {
-                const double2 v = block[e];
-                block32[e] = make_float2((float)v.x, (float)v.y);
-            }
-            continue;
+        if (r < n_rhs && ((sel >> r) & 1u)) {
+            const double2 v = block[e];
+            block32[e] = make_float2((float)v.x, (float)v.y);
         }
-        if (mode == 2 && (r >= n_rhs || !((sel >> r) & 1u))) continue;
-        if (r >= n_rhs) {
-            block[e] = make_double2(0.0, 0.0);
-            continue;
-        }
-        const size_t hcs = e / kNR;
-        const int s = (int)(hcs % 4);
-        const size_t hc = hcs / 4;
-        const int c = (int)(hc % d);
-        const size_t h = hc / d;
-        const size_t se = (size_t)(s * d + c) * g.Vh_pad + h;
-        if (mode == 2) {
-            // std64 is the caller's writable field in this mode; its padding
-            // sites stay untouched (the block's may hold stale values)
-            if (h >= (size_t)g.Vh) continue;
-            ((double2 *)(const_cast<char *>(std64) + r * std_stride + std_off))[se] = block[e];
-            continue;
-        }
-        block[e] = *((const double2 *)(std64 + r * std_stride + std_off) + se);
     }
 }
 
 bsm_status launch_block64_io(const Geom &g, int d, int n_rhs, unsigned sel, const char *std64, size_t std_stride,
                              size_t std_off, double2 *block, float2 *block32, int mode, hipStream_t st) {
+    if (mode != 1)   // layout changes go through the LDS transpose
+        return launch_block64_std(g, d, n_rhs, sel, const_cast<char *>(std64), std_stride, std_off, block,
+                                  mode == 0 ? 0 : 2, st);
     const size_t n = (size_t)g.Vh_pad * d * 4 * kNR;
     size_t nb = (n + 255) / 256;
     if (nb > 65536) nb = 65536;
-    k_block64_io<<<(int)nb, 256, 0, st>>>(g, d, n_rhs, sel, std64, std_stride, std_off, block, block32, mode);
+    k_block64_to32<<<(int)nb, 256, 0, st>>>(g, d, n_rhs, sel, block, block32);
     BSM_HIP(hipGetLastError());
     return BSM_OK;
 }
