@@ -133,30 +133,29 @@ __global__ __launch_bounds__(256) void k_zorth(ZPtrs W, ZPtrs Z, int k, const do
     block_sum2(dr, di, ws, 1, &partials[(size_t)gridDim.x + blockIdx.x]);
 }
 
-// nn[k] = sum partials[0][*]; alpha = (sum partials[1][*]) / nn[k]
-__global__ __launch_bounds__(256) void k_zalpha(const double2 *partials, int nb, double *nn, int k, double2 *alpha) {
-    double a = 0, b = 0, c = 0;
-    for (int i = threadIdx.x; i < nb; i += 256) {
-        a += partials[i].x;
-        b += partials[nb + i].x;
-        c += partials[nb + i].y;
-    }
+// alpha = <w, r> / |w|^2 from the nb workgroup partials of k_zorth (every
+// workgroup sums them in the same fixed order, so all get the same alpha and
+// no separate reduction launch is needed; workgroup 0 records nn[k] = |w|^2);
+// then x += alpha z ; r -= alpha w ; per-workgroup |r|^2 into rr_parts
+__global__ __launch_bounds__(256) void k_zupdate(float2 *x, float2 *r, const float2 *z, const float2 *w, size_t n,
+                                                 const double2 *orth, int nb, double *nn, int k, double *rr_parts) {
     __shared__ double2 ws[4 * kZdotJ];
     __shared__ double2 s0, s1;
-    double zero = 0;
-    block_sum2(a, zero, ws, 0, &s0);
-    block_sum2(b, c, ws, 1, &s1);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        nn[k] = s0.x;
-        *alpha = s0.x > 0 ? make_double2(s1.x / s0.x, s1.y / s0.x) : make_double2(0.0, 0.0);
+    {
+        double a = 0, b = 0, c = 0;
+        for (int i = threadIdx.x; i < nb; i += 256) {
+            a += orth[i].x;
+            b += orth[nb + i].x;
+            c += orth[nb + i].y;
+        }
+        double zero = 0;
+        block_sum2(a, zero, ws, 0, &s0);
+        block_sum2(b, c, ws, 1, &s1);
+        __syncthreads();
     }
-}
-
-// x += alpha z ; r -= alpha w ; partials of |r|^2
-__global__ __launch_bounds__(256) void k_zupdate(float2 *x, float2 *r, const float2 *z, const float2 *w, size_t n,
-                                                 const double2 *alpha, double2 *partials) {
-    const float ar = (float)alpha->x, ai = (float)alpha->y;
+    const double d0 = s0.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) nn[k] = d0;
+    const float ar = d0 > 0 ? (float)(s1.x / d0) : 0.f, ai = d0 > 0 ? (float)(s1.y / d0) : 0.f;
     double rr = 0;
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
         const float2 zv = z[e], wv = w[e];
@@ -169,9 +168,16 @@ __global__ __launch_bounds__(256) void k_zupdate(float2 *x, float2 *r, const flo
         r[e] = rv;
         rr += (double)(rv.x * rv.x + rv.y * rv.y);
     }
-    __shared__ double2 ws[4 * kZdotJ];
+    __syncthreads();
     double zero = 0;
-    block_sum2(rr, zero, ws, 0, &partials[blockIdx.x]);
+    double2 tot;
+    __shared__ double2 t2;
+    block_sum2(rr, zero, ws, 2, &t2);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        tot = t2;
+        rr_parts[blockIdx.x] = tot.x;
+    }
 }
 
 #define TRY(x)                           \
@@ -462,7 +468,8 @@ bsm_status bsm_fgcr_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U
     // the context's second scratch: the fall back CG uses the first
     const bool fast = net && prm->precond_layers == 0 && net_fast_supported(d);
     const size_t need = (2 * (size_t)m + 2) * f32 + 2 * f64 + (net && !fast ? (size_t)channels * f32 : 0) +
-                        (size_t)kGcrMax * nb * sizeof(double2) + 4 * kGcrMax * sizeof(double2) + 16 * 256;
+                        (size_t)kGcrMax * nb * sizeof(double2) + 4 * kGcrMax * sizeof(double2) +
+                        kZblocks * sizeof(double) + 17 * 256;
     void *work = nullptr;
     TRY(ctx_work_slot(ctx, 1, need, &work));
     char *w = (char *)work;
@@ -483,7 +490,10 @@ bsm_status bsm_fgcr_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U
     double2 *parts = (double2 *)take((size_t)kGcrMax * nb * sizeof(double2));
     double2 *coef = (double2 *)take(4 * kGcrMax * sizeof(double2));
     double *nn = (double *)(coef + kGcrMax);          // kGcrMax doubles
-    double2 *alpha = coef + 2 * kGcrMax, *rr = coef + 3 * kGcrMax;
+    double *rrp = (double *)take(kZblocks * sizeof(double));   // per-workgroup |rho|^2
+    // pinned: two slots of kZblocks partials, the upper half of the context's mirror
+    double *host_rr = ctx->host_scal + kScalars / 2;
+    static_assert(2 * kZblocks <= kScalars / 2, "host partial slots");
     hipEvent_t ev[2] = {nullptr, nullptr};
     BSM_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     BSM_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
@@ -518,14 +528,12 @@ bsm_status bsm_fgcr_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U
             k_zcols<<<k, 256, 0, st>>>(parts, nb, nn, coef, 0);
         }
         k_zorth<<<nb, 256, 0, st>>>(Wp, Zp, k, coef, (float2 *)Wv[k], (float2 *)Z[k], (const float2 *)rho, n, parts);
-        k_zalpha<<<1, 256, 0, st>>>(parts, nb, nn, k, alpha);
         k_zupdate<<<nb, 256, 0, st>>>((float2 *)e, (float2 *)rho, (const float2 *)Z[k], (const float2 *)Wv[k], n,
-                                      alpha, parts);
-        k_zcols<<<1, 256, 0, st>>>(parts, nb, nullptr, rr, 1);
+                                      parts, nb, nn, k, rrp);
         BSM_HIP(hipGetLastError());
-        // |rho|^2 to a pinned slot; the host reads it one step later, so the
-        // next step is already queued while this one finishes
-        BSM_HIP(hipMemcpyAsync(ctx->host_scal + S_TMP + (k & 1), rr, sizeof(double), hipMemcpyDeviceToHost, st));
+        // the workgroup partials of |rho|^2 to a pinned slot; the host sums
+        // them one step later, so the next step is already queued meanwhile
+        BSM_HIP(hipMemcpyAsync(host_rr + (k & 1) * kZblocks, rrp, nb * sizeof(double), hipMemcpyDeviceToHost, st));
         BSM_HIP(hipEventRecord(ev[k & 1], st));
         return BSM_OK;
     };
@@ -554,7 +562,8 @@ bsm_status bsm_fgcr_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U
             if (k > 0) {
                 // the previous step's residual (this step runs meanwhile and is kept)
                 if (hipEventSynchronize(ev[(k - 1) & 1]) != hipSuccess) { status = fail(BSM_ERR_HIP, "event"); break; }
-                const double rk = ctx->host_scal[S_TMP + ((k - 1) & 1)];
+                double rk = 0;
+                for (int i = 0; i < nb; i++) rk += host_rr[((k - 1) & 1) * kZblocks + i];
                 if (!std::isfinite(rk) || rk <= tol2) break;
             }
         }
