@@ -168,3 +168,30 @@ def test_fgcr_with_wilson_layer_as_preconditioner():
     _, it0, _ = ptc.fgcr(D, lambda r: r, b, tol=1e-10, m=16)
     _, it1, h1 = ptc.fgcr(D, Mneu, b, tol=1e-10, m=16)
     assert h1[-1] <= 1e-10 and it1 < it0
+
+
+def test_two_linear_layers_collapse_to_one_operator():
+    """Both layers are linear and a spin matrix commutes with a colour
+    transport, so the 1 -> C -> 1 net equals sum_p T_p sum_q C_pq T_q with
+    C_pq = sum_j W2_p^{0j} W1_q^{j0} (the form the collapsed GPU path uses),
+    built here from single-path layers of the oracle."""
+    lat = gen.Lattice(4, 2, 4, 2)
+    U = gen.gauge_links(lat, 3, "haar", 11)
+    C = 5
+    W1 = _rand_w((C, 1, 9, 4, 4), 12)
+    W2 = _rand_w((1, C, 9, 4, 4), 13)
+    v = gen.gaussian_spinor(lat, 3, 14)
+    sel = np.zeros((9, 1, 9, 4, 4), complex)    # channel q <- T_q v
+    tsum = np.zeros((1, 9, 9, 4, 4), complex)   # sum_p T_p (channel p)
+    for q in range(9):
+        sel[q, 0, q] = np.eye(4)
+        tsum[0, q, q] = np.eye(4)
+    Cm = np.einsum("jpac,jqcb->pqab", W2[0], W1[:, 0])
+    t = oracle.ptc_layer(lat, U, sel, v[None])           # [9][V][4][d]
+    G = np.einsum("pqab,qvbc->pvac", Cm, t)
+    collapsed = oracle.ptc_layer(lat, U, tsum, G)[0]
+    assert rel(collapsed, ptc.net_apply(lat, U, W1, W2, v)) < 1e-13
+    # a transposed product (W1 W2 instead of W2 W1) is not the net
+    Cw = np.einsum("jqac,jpcb->pqab", W1[:, 0], W2[0])
+    wrong = oracle.ptc_layer(lat, U, tsum, np.einsum("pqab,qvbc->pvac", Cw, t))[0]
+    assert rel(wrong, ptc.net_apply(lat, U, W1, W2, v)) > 1e-2
