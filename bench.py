@@ -172,7 +172,7 @@ def bench_cg_cfg2(ctx, lat, Uf_dev, psi_dev, kappa, bsm):
         prm = bsm.solver_params(kappa, 1e-10, schur=True, variant=variant)
         log(f"CG 32^3x64 SU(3) {name} ...")
         out = x64 if name == "plain_f64" else x
-        status, st = ctx.bsm_cg_solve(dl, Ul, U64, prm, b, out, check=False)
+        status, st = warm_solve(lambda: ctx.bsm_cg_solve(dl, Ul, U64, prm, b, out, check=False))
         cg[name] = solve_row(status, st, base)
         if name == "plain_f64":
             base = st["seconds"]
@@ -211,7 +211,8 @@ def bench_cfg3(bsm, gen):
             ctx.bsm_gauge_represent(dl, Uf, Ul)
         prm = bsm.solver_params(c["kappa"], 1e-10, schur=True, variant=variant)
         log(f"cfg3 {name} ...")
-        status, st = ctx.bsm_cg_solve(dl, Ul, U64, prm, b, x64 if base is None else x, check=False)
+        xo = x64 if base is None else x
+        status, st = warm_solve(lambda: ctx.bsm_cg_solve(dl, Ul, U64, prm, b, xo, check=False))
         out[name] = solve_row(status, st, base)
         if base is None:
             base = st["seconds"]
@@ -257,6 +258,8 @@ def bench_cfg4(bsm, gen):
     log(f"  {tb:.3f} s, iters {[s['iters'] for s in stats]}, block plan {plan}")
     tseq, its, worst = 0.0, [], 0.0
     log("cfg4 sequential plain FP64 ...")
+    # one untimed solve first (the context's plain-CG scratch is allocated there)
+    ctx.bsm_cg_solve(d64, U, U, bsm.solver_params(kappas[0], 1e-10, schur=True), b[0:fb], xs[0:fb], check=False)
     for r in range(n):
         p1 = bsm.solver_params(kappas[r], 1e-10, schur=True)
         sl = slice(r * fb, (r + 1) * fb)
@@ -321,13 +324,14 @@ def bench_cfg5(bsm, gen, train_steps=300, n_pairs=32, channels=8, large_dims=Tru
     x0 = ctx.new_spinor(d64)
     rows = {}
     log("cfg5 plain FP64 Schur CG ...")
-    s, st = ctx.bsm_cg_solve(d64, U64, U64, bsm.solver_params(kappa, 1e-10, schur=True), b, x0, check=False)
+    s, st = warm_solve(lambda: ctx.bsm_cg_solve(d64, U64, U64, bsm.solver_params(kappa, 1e-10, schur=True), b, x0,
+                                                check=False))
     base = st["seconds"]
     rows["plain_f64"] = solve_row(s, st)
     log(f"  {rows['plain_f64']}")
     log("cfg5 mixed FP32 CG ...")
-    s, st = ctx.bsm_cg_solve(d32, U32, U64, bsm.solver_params(kappa, 1e-10, schur=True, variant=bsm.SOLVER_MIXED),
-                             b, x, check=False)
+    s, st = warm_solve(lambda: ctx.bsm_cg_solve(
+        d32, U32, U64, bsm.solver_params(kappa, 1e-10, schur=True, variant=bsm.SOLVER_MIXED), b, x, check=False))
     rows["mixed_f32"] = solve_row(s, st, base)
     _fgcr_rows(bsm, ctx, d32, d64, U32, U64, kappa, channels, net, b, x, x0, base, rows, "cfg5")
     apply_us = _time_net_apply(bsm, ctx, d32, U32, channels, net, b)
@@ -366,12 +370,13 @@ def bench_cfg5_large(bsm, gen, net, channels, kappa):
     x, x0 = ctx.new_spinor(d64), ctx.new_spinor(d64)
     rows = {}
     log("cfg5 transfer: plain FP64 Schur CG ...")
-    s, st = ctx.bsm_cg_solve(d64, U64, U64, bsm.solver_params(kappa, 1e-10, schur=True), b, x0, check=False)
+    s, st = warm_solve(lambda: ctx.bsm_cg_solve(d64, U64, U64, bsm.solver_params(kappa, 1e-10, schur=True), b, x0,
+                                                check=False))
     base = st["seconds"]
     rows["plain_f64"] = solve_row(s, st)
     log(f"  {rows['plain_f64']}")
-    s, st = ctx.bsm_cg_solve(d32, U32, U64, bsm.solver_params(kappa, 1e-10, schur=True, variant=bsm.SOLVER_MIXED),
-                             b, x, check=False)
+    s, st = warm_solve(lambda: ctx.bsm_cg_solve(
+        d32, U32, U64, bsm.solver_params(kappa, 1e-10, schur=True, variant=bsm.SOLVER_MIXED), b, x, check=False))
     rows["mixed_f32"] = solve_row(s, st, base)
     log(f"  mixed_f32 {rows['mixed_f32']}")
     _fgcr_rows(bsm, ctx, d32, d64, U32, U64, kappa, channels, net, b, x, x0, base, rows, "cfg5 transfer")
@@ -382,6 +387,13 @@ def bench_cfg5_large(bsm, gen, net, channels, kappa):
             "solves": rows, "net_apply_us": apply_us}
 
 
+def warm_solve(fn):
+    """Run a solve twice and keep the second: the first call on a context
+    grows its scratch buffers (allocation, zero fill) and is not timed."""
+    fn()
+    return fn()
+
+
 def _fgcr_rows(bsm, ctx, d32, d64, U32, U64, kappa, channels, net, b, x, x0, base, rows, tag):
     """GCR(6) without the net, FGCR(6) with the collapsed FP16 net (the
     default) and with the FP32 layers."""
@@ -389,7 +401,8 @@ def _fgcr_rows(bsm, ctx, d32, d64, U32, U64, kappa, channels, net, b, x, x0, bas
                                   ("fgcr_net_layers_f32", True, 1)):
         log(f"{tag} {name} ...")
         prm = bsm.solver_params(kappa, 1e-10, max_iter=20000, restart=6, precond_layers=layers)
-        s, st = ctx.bsm_fgcr_solve(d32, U32, U64, prm, channels, net if use_net else None, b, x, check=False)
+        s, st = warm_solve(lambda: ctx.bsm_fgcr_solve(d32, U32, U64, prm, channels, net if use_net else None, b, x,
+                                                      check=False))
         rows[name] = solve_row(s, st, base)
         rows[name].update(fell_back=st["fell_back"], precond_applies=st["precond_applies"],
                           x_rel_diff_vs_plain=rel_diff(ctx, d64, x, x0))

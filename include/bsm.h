@@ -269,7 +269,9 @@ bsm_status bsm_precond_apply(bsm_ctx ctx, const bsm_field_desc *desc, const void
  * are kept in FP16 with that scale, so z agrees with bsm_precond_apply to a
  * relative O(1e-3) (norm-wise).  Non-finite components of r give non-finite
  * components of z.  d_R <= 3 (BSM_ERR_UNSUPPORTED otherwise); scratch from
- * the context.  Asynchronous on stream. */
+ * the context.  desc->link_prec may be BSM_F16S here (U_rep then holds FP16
+ * links, e.g. from bsm_gauge_represent with link_prec F16S), which FGCR uses
+ * for its network.  Asynchronous on stream. */
 bsm_status bsm_precond_apply_collapsed(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep,
                                        int32_t channels, const void *net, const void *r, void *z, void *stream);
 

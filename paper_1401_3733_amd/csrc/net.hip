@@ -227,12 +227,13 @@ static bsm_status net_apply(bsm_ctx ctx, const bsm_field_desc *desc, const void 
 }
 
 // the collapsed network: scratch in the network slot, C from the weights
-static bsm_status net_fast_prepare(bsm_ctx ctx, int d, int C, const void *net, const void *U, NetFastArgs &a,
-                                   hipStream_t st) {
+static bsm_status net_fast_prepare(bsm_ctx ctx, int d, int C, const void *net, const void *U, int link_prec,
+                                   NetFastArgs &a, hipStream_t st) {
     void *w = nullptr;
     TRY(ctx_work_slot(ctx, 2, net_fast_bytes(ctx->g, d), &w));
     a = NetFastArgs{};
     a.U = U;
+    a.link_prec = link_prec;
     net_fast_carve(ctx->g, d, w, a);
     return launch_net_collapse(net, C, a, st);
 }
@@ -305,14 +306,22 @@ bsm_status bsm_precond_apply(bsm_ctx ctx, const bsm_field_desc *desc, const void
 
 bsm_status bsm_precond_apply_collapsed(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep,
                                        int32_t channels, const void *net, const void *r, void *z, void *stream) {
-    TRY(check_net_desc(ctx, desc));
+    if (!desc) return fail(BSM_ERR_ARG, "null argument");
+    if (desc->link_prec == BSM_F16S) {
+        // FP16 links are accepted here: the same checks with F32 links
+        bsm_field_desc d32 = *desc;
+        d32.link_prec = BSM_F32;
+        TRY(check_net_desc(ctx, &d32));
+    } else {
+        TRY(check_net_desc(ctx, desc));
+    }
     if (!U_rep || !net || !r || !z) return fail(BSM_ERR_ARG, "null pointer");
     if (channels < 1 || channels > 64) return fail(BSM_ERR_ARG, "channels must be in [1, 64]");
     if (r == z) return fail(BSM_ERR_ARG, "r and z must differ");
     if (!net_fast_supported(desc->d_R)) return fail(BSM_ERR_UNSUPPORTED, "the collapsed network runs for d_R <= 3");
     hipStream_t st = (hipStream_t)stream;
     NetFastArgs a;
-    TRY(net_fast_prepare(ctx, desc->d_R, channels, net, U_rep, a, st));
+    TRY(net_fast_prepare(ctx, desc->d_R, channels, net, U_rep, desc->link_prec, a, st));
     a.in = r;
     a.out = z;
     return launch_net_fast(ctx->g, desc->d_R, a, st);
@@ -467,9 +476,11 @@ bsm_status bsm_fgcr_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U
     auto t0 = std::chrono::steady_clock::now();
     // the context's second scratch: the fall back CG uses the first
     const bool fast = net && prm->precond_layers == 0 && net_fast_supported(d);
-    const size_t need = (2 * (size_t)m + 2) * f32 + 2 * f64 + (net && !fast ? (size_t)channels * f32 : 0) +
+    // the collapsed network reads FP16 copies of the links (converted once per solve)
+    const size_t l16 = fast ? 8 * link_block_bytes(BSM_F16S, false, d, g.Vh_pad) : 0;
+    const size_t need = (2 * (size_t)m + 2) * f32 + 2 * f64 + (net && !fast ? (size_t)channels * f32 : 0) + l16 +
                         (size_t)kGcrMax * nb * sizeof(double2) + 4 * kGcrMax * sizeof(double2) +
-                        kZblocks * sizeof(double) + 17 * 256;
+                        kZblocks * sizeof(double) + 18 * 256;
     void *work = nullptr;
     TRY(ctx_work_slot(ctx, 1, need, &work));
     char *w = (char *)work;
@@ -485,7 +496,11 @@ bsm_status bsm_fgcr_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U
     char *rho = take(f32), *e = take(f32);
     char *h32 = net && !fast ? take((size_t)channels * f32) : nullptr;
     NetFastArgs fa{};
-    if (fast) TRY(net_fast_prepare(ctx, d, channels, net, U_rep, fa, st));
+    if (fast) {
+        char *U16 = take(l16);
+        TRY(launch_convert_links(g, d, false, BSM_F32, BSM_F16S, U_rep, U16, st));
+        TRY(net_fast_prepare(ctx, d, channels, net, U16, BSM_F16S, fa, st));
+    }
     char *r = take(f64), *t = take(f64);
     double2 *parts = (double2 *)take((size_t)kGcrMax * nb * sizeof(double2));
     double2 *coef = (double2 *)take(4 * kGcrMax * sizeof(double2));

@@ -31,7 +31,8 @@ bsm_status launch_ptc_adjoint_weights(const void *W, void *Wa, int cin, int cout
 // z = cs * sum_p T_p (S * G'_p), with G'_p, S and cs built as described in
 // ptc_fast.hip.  Scratch: net_fast_bytes(), carved by net_fast_carve().
 struct NetFastArgs {
-    const void *U;       // F32 links (complex), internal layout
+    const void *U;       // links (complex), internal layout, in link_prec
+    int link_prec;       // BSM_F32 or BSM_F16S
     const void *in;      // F32 full field v
     void *out;           // F32 full field z
     void *G;             // nine FP16 mixed fields (both parities)

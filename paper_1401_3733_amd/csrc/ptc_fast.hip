@@ -8,7 +8,8 @@
 // every site and colour, and a second transport sweep; the C channel fields
 // are never formed.
 //
-// Precision: the transports are FP32.  The mixing runs on FP16 matrix cores
+// Precision: the transports are FP32 (links FP32, or FP16 where the caller
+// passes FP16 links: a further relative 2^-11 on each link element).  The mixing runs on FP16 matrix cores
 // with FP32 accumulation: the transported fields are divided by a bound on
 // their largest |component| (per site and group of paths) before rounding to
 // FP16, C by its largest entry; the nine mixed fields are stored in FP16 with
@@ -105,8 +106,8 @@ __device__ inline void load_g16(const NetFastArgs &a, const Geom &g, int p, int 
         }
 }
 
-// t = w U s (forward path) or w U^dag s (backward path)
-template <int D>
+// t = w U s (forward path) or w U^dag s (backward path); links in LP
+template <int D, int LP>
 __device__ inline void link_apply(const Geom &g, const PathSite &ps, const cx<float> (&s)[4 * D],
                                   cx<float> (&t)[4 * D]) {
 #pragma unroll
@@ -115,7 +116,7 @@ __device__ inline void link_apply(const Geom &g, const PathSite &ps, const cx<fl
     for (int i = 0; i < D; i++)
 #pragma unroll
         for (int j = 0; j < D; j++) {
-            const cx<float> u = load_link<BSM_F32, false, float>(ps.blk, g.Vh_pad, i * D + j, ps.hl);
+            const cx<float> u = load_link<LP, false, float>(ps.blk, g.Vh_pad, i * D + j, ps.hl);
 #pragma unroll
             for (int a = 0; a < 4; a++) {
                 if (!ps.back) t[a * D + i] = cfma(u, s[a * D + j], t[a * D + i]);
@@ -177,7 +178,7 @@ __device__ inline float source_maxabs(const Geom &g, const char *v, size_t pblk,
     return maxabs<D>(s, m);
 }
 
-template <int D>
+template <int D, int LP>
 __device__ inline void stage_transport(const Geom &g, const char *v, size_t pblk, int px, uint32_t h,
                                        const PathSite &ps, int p, float inv, h4v *Bh, int site) {
     cx<float> s[4 * D];
@@ -187,7 +188,7 @@ __device__ inline void stage_transport(const Geom &g, const char *v, size_t pblk
     } else {
         load_spinor<BSM_F32, D, float>(v + (1 - px) * pblk, g.Vh_pad, ps.hn, s);
         cx<float> t[4 * D];
-        link_apply<D>(g, ps, s, t);
+        link_apply<D, LP>(g, ps, s, t);
         stage_path<D>(Bh, fast_path_slot(p), site, inv, t);
     }
 }
@@ -201,7 +202,7 @@ __device__ inline void stage_transport(const Geom &g, const char *v, size_t pblk
 // sites 16w..16w+15 of the block: each 16-deep K step is one thread's, so its product is
 // rescaled by that thread's bound before it is summed; S(y) is the largest
 // of the site's four bounds and G' = G / S is stored in FP16 (|G'| <= 72).
-template <int D>
+template <int D, int LP>
 __global__ __launch_bounds__(4 * kFastSites) void k_net_mix16(Geom g, NetFastArgs a, int nblk, int per_wg) {
     __shared__ h4v Bh[D * kFastSlotsKq * kFastSites];
     __shared__ h4v Afs[kFastTiles * kFastTiles * 64];
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(4 * kFastSites) void k_net_mix16(Geom g, NetFastArg
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane >> 4, sl = lane & 15;
     const int pg = tid / kFastSites, site = tid % kFastSites;
     const size_t pblk = spinor_block_bytes(BSM_F32, D, g.Vh_pad);
-    const size_t lblk = link_block_bytes(BSM_F32, false, D, g.Vh_pad);
+    const size_t lblk = link_block_bytes(LP, false, D, g.Vh_pad);
     const char *U = (const char *)a.U, *v = (const char *)a.in;
     for (int e = tid; e < kFastTiles * kFastTiles * 64; e += 4 * kFastSites) Afs[e] = ((const h4v *)a.Afrag)[e];
     // the zero slot (thread group 0 owns it)
@@ -243,9 +244,9 @@ __global__ __launch_bounds__(4 * kFastSites) void k_net_mix16(Geom g, NetFastArg
             }
             const float inv = bound > 0.f ? 1.f / bound : 0.f;
             if (live) {
-                stage_transport<D>(g, v, pblk, px, h, sA, pA, inv, Bh, site);
-                stage_transport<D>(g, v, pblk, px, h, sB, pB, inv, Bh, site);
-                if (pg == 0) stage_transport<D>(g, v, pblk, px, h, sC, 8, inv, Bh, site);
+                stage_transport<D, LP>(g, v, pblk, px, h, sA, pA, inv, Bh, site);
+                stage_transport<D, LP>(g, v, pblk, px, h, sB, pB, inv, Bh, site);
+                if (pg == 0) stage_transport<D, LP>(g, v, pblk, px, h, sC, 8, inv, Bh, site);
             } else {
                 cx<float> z[4 * D];
 #pragma unroll
@@ -302,7 +303,7 @@ __global__ __launch_bounds__(4 * kFastSites) void k_net_mix16(Geom g, NetFastArg
 // stay path) and the partial sums added in LDS in a fixed order: four times
 // the loads in flight of one thread per site (measured 9 % faster on
 // 16^3x32, 2 % on 32^3x64)
-template <int D>
+template <int D, int LP>
 __global__ __launch_bounds__(256) void k_net_tsum16(Geom g, NetFastArgs a, int nblk) {
     __shared__ float2 part[4][4 * D][64];
     const int s = threadIdx.x & 63, grp = threadIdx.x >> 6;
@@ -311,7 +312,7 @@ __global__ __launch_bounds__(256) void k_net_tsum16(Geom g, NetFastArgs a, int n
     const uint32_t h = (lb - px * nblk) * 64 + s;
     const bool live = h < (uint32_t)g.Vh;
     const size_t pblk = spinor_block_bytes(BSM_F32, D, g.Vh_pad);
-    const size_t lblk = link_block_bytes(BSM_F32, false, D, g.Vh_pad);
+    const size_t lblk = link_block_bytes(LP, false, D, g.Vh_pad);
     cx<float> acc[4 * D];
 #pragma unroll
     for (int e = 0; e < 4 * D; e++) acc[e] = mk<float>(0.f, 0.f);
@@ -324,7 +325,7 @@ __global__ __launch_bounds__(256) void k_net_tsum16(Geom g, NetFastArgs a, int n
             const PathSite ps = path_site(g, (const char *)a.U, lblk, px, h, c, p);
             cx<float> v[4 * D], t[4 * D];
             load_g16<D>(a, g, p, 1 - px, ps.hn, v);
-            link_apply<D>(g, ps, v, t);
+            link_apply<D, LP>(g, ps, v, t);
 #pragma unroll
             for (int e = 0; e < 4 * D; e++) acc[e] = acc[e] + t[e];
         }
@@ -383,9 +384,14 @@ struct NetFastByD {
             // up to 4096 workgroups (two fit a CU), each over a contiguous range of blocks
             const int per_wg = std::max(1, (2 * nbm + 4095) / 4096);
             const int grid = (2 * nbm + per_wg - 1) / per_wg;
-            k_net_mix16<D><<<grid, 4 * kFastSites, 0, st>>>(g, a, nbm, per_wg);
             const int nb64 = (g.Vh + 63) / 64;
-            k_net_tsum16<D><<<2 * nb64, 256, 0, st>>>(g, a, nb64);
+            if (a.link_prec == BSM_F16S) {
+                k_net_mix16<D, BSM_F16S><<<grid, 4 * kFastSites, 0, st>>>(g, a, nbm, per_wg);
+                k_net_tsum16<D, BSM_F16S><<<2 * nb64, 256, 0, st>>>(g, a, nb64);
+            } else {
+                k_net_mix16<D, BSM_F32><<<grid, 4 * kFastSites, 0, st>>>(g, a, nbm, per_wg);
+                k_net_tsum16<D, BSM_F32><<<2 * nb64, 256, 0, st>>>(g, a, nb64);
+            }
             BSM_HIP(hipGetLastError());
             return BSM_OK;
         }

@@ -413,3 +413,20 @@ def test_fgcr_collapsed_and_layered_nets_agree():
         res[layers] = stats["iters"]
     print("iters collapsed / layered", res)
     assert abs(res[0] - res[1]) <= max(2, res[1] // 10)
+
+
+def test_collapsed_net_with_fp16_links():
+    """FGCR's network reads FP16 copies of the links (a further relative
+    2^-11 per link element): still within the collapsed operator's bound."""
+    note("collapsed precond FP16 links")
+    S = NetSetup(3, "fund", 154)
+    S16 = Setup(LAT, 3, "fund", S.Uf, prec="f32", link_prec="f16s")
+    W1, W2 = _net_weights(24)
+    net = _net_dev(W1, W2)
+    r = _f32_exact(gen.gaussian_spinor(LAT, 3, 25))
+    z = S.out(1)
+    S16.ctx.bsm_precond_apply_collapsed(S16.desc, S16.U, 8, net, S.fields(r[None]), z)
+    got = S.get(z, 1)[0]
+    ref = ptc.net_apply(LAT, S.UR32, W1, W2, r)
+    print("collapsed fp16-link rel err", rel(got, ref))
+    assert rel(got, ref) < COLLAPSED_TOL
