@@ -79,10 +79,9 @@ __global__ __launch_bounds__(256) void k_zmultidot(ZPtrs W, int k, const float2 
     }
 }
 
-// one workgroup per column j: s = sum of nb partials (fixed order);
-// mode 0: coef[j] = s / nn[j] (0 when nn[j] is 0); mode 1: coef[j] = s
-__global__ __launch_bounds__(256) void k_zcols(const double2 *partials, int nb, const double *nn, double2 *coef,
-                                               int mode) {
+// one workgroup per column j: coef[j] = (sum of nb partials, fixed order) /
+// nn[j] (0 when nn[j] is 0)
+__global__ __launch_bounds__(256) void k_zcols(const double2 *partials, int nb, const double *nn, double2 *coef) {
     const int j = blockIdx.x;
     double re = 0, im = 0;
     for (int i = threadIdx.x; i < nb; i += 256) {
@@ -94,12 +93,8 @@ __global__ __launch_bounds__(256) void k_zcols(const double2 *partials, int nb, 
     block_sum2(re, im, ws, 0, &s);
     __syncthreads();
     if (threadIdx.x != 0) return;
-    if (mode == 0) {
-        const double d = nn[j];
-        coef[j] = d > 0 ? make_double2(s.x / d, s.y / d) : make_double2(0.0, 0.0);
-    } else {
-        coef[j] = s;
-    }
+    const double d = nn[j];
+    coef[j] = d > 0 ? make_double2(s.x / d, s.y / d) : make_double2(0.0, 0.0);
 }
 
 // w -= sum_j coef_j W_j ; z -= sum_j coef_j Z_j ; partials of |w|^2 and <w, r>
@@ -170,14 +165,9 @@ __global__ __launch_bounds__(256) void k_zupdate(float2 *x, float2 *r, const flo
     }
     __syncthreads();
     double zero = 0;
-    double2 tot;
     __shared__ double2 t2;
     block_sum2(rr, zero, ws, 2, &t2);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        tot = t2;
-        rr_parts[blockIdx.x] = tot.x;
-    }
+    if (threadIdx.x == 0) rr_parts[blockIdx.x] = t2.x;   // block_sum2's writer is thread 0
 }
 
 #define TRY(x)                           \
@@ -540,7 +530,7 @@ bsm_status bsm_fgcr_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U
         TRY(bsm_dslash_apply(ctx, desc, U_rep, prm->kappa, 0, Z[k], Wv[k], stream));
         if (k > 0) {
             k_zmultidot<<<dim3(nb, (k + kZdotJ - 1) / kZdotJ), 256, 0, st>>>(Wp, k, (const float2 *)Wv[k], n, parts);
-            k_zcols<<<k, 256, 0, st>>>(parts, nb, nn, coef, 0);
+            k_zcols<<<k, 256, 0, st>>>(parts, nb, nn, coef);
         }
         k_zorth<<<nb, 256, 0, st>>>(Wp, Zp, k, coef, (float2 *)Wv[k], (float2 *)Z[k], (const float2 *)rho, n, parts);
         k_zupdate<<<nb, 256, 0, st>>>((float2 *)e, (float2 *)rho, (const float2 *)Z[k], (const float2 *)Wv[k], n,

@@ -54,3 +54,26 @@ def test_conversions():
     S.ctx.bsm_vec_axpby(S.desc, 2, 1.0, X, 0.0, None, o16, prec_out="f16s")
     q, s = quant.quantise(x)
     assert np.array_equal(S.unpack(o16, desc=d16), quant.dequantise(q, s, 3))
+
+
+@pytest.mark.parametrize("nbytes", [1 << 20, (1 << 20) + 4096 * 16 + 48])
+@pytest.mark.parametrize("blocks", [1, 7, 2048])
+def test_stream_copy_and_read(nbytes, blocks):
+    """the bandwidth calibration kernels: the copy is exact, including a
+    ragged chunk per workgroup and a tail, and the read sweep's per-workgroup
+    sums add up to the buffer's sum"""
+    import torch
+    n = nbytes // 4
+    src = (torch.arange(n, dtype=torch.float32, device="cuda") % 7) - 3.0
+    dst = torch.zeros_like(src)
+    for nt in (0, 1):
+        dst.zero_()
+        bsm.bsm_stream_copy(src, dst, nontemporal=nt, blocks=blocks)
+        torch.cuda.synchronize()
+        assert torch.equal(dst, src)
+    part = torch.zeros(blocks, dtype=torch.float32, device="cuda")
+    bsm.bsm_stream_read(src, part, blocks=blocks)
+    torch.cuda.synchronize()
+    assert abs(part.double().sum().item() - src.double().sum().item()) <= 1e-3 * n ** 0.5
+    with pytest.raises(bsm.BsmError):
+        bsm.bsm_stream_read(src, part, nbytes=nbytes - 4, blocks=blocks)
