@@ -430,3 +430,28 @@ def test_collapsed_net_with_fp16_links():
     ref = ptc.net_apply(LAT, S.UR32, W1, W2, r)
     print("collapsed fp16-link rel err", rel(got, ref))
     assert rel(got, ref) < COLLAPSED_TOL
+
+
+def test_collapsed_net_full_size_16x16x16x32():
+    """The collapsed network at the size FGCR runs it in the benchmark (the
+    16^3 x 32 SU(3) workload, bench launch shapes: 1024 mixing workgroups,
+    2048 transport-sum workgroups), F32 and FP16 links, every site against
+    the oracle's layered net."""
+    lat = gen.config_lattice(5)
+    note("collapsed precond 16^3x32")
+    Uf = gen.config_links(5, lat)
+    S = Setup(lat, 3, "fund", Uf, prec="f32", link_prec="f32")
+    S16 = Setup(lat, 3, "fund", Uf, prec="f32", link_prec="f16s")
+    UR32 = _f32_exact(oracle.represent(Uf, "fund"))
+    W1, W2 = _net_weights(26)
+    net = _net_dev(W1, W2)
+    r = _f32_exact(gen.gaussian_spinor(lat, 3, 27))
+    ref = ptc.net_apply(lat, UR32, W1, W2, r)
+    rb = S.pack(r)
+    for T in (S, S16):
+        import torch
+        z = torch.zeros_like(rb)
+        T.ctx.bsm_precond_apply_collapsed(T.desc, T.U, 8, net, rb, z)
+        got = S.unpack(z)
+        print("full-size collapsed rel err", T.desc.link_prec, rel(got, ref))
+        assert rel(got, ref) < COLLAPSED_TOL
