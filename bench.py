@@ -164,7 +164,8 @@ def bench_cg_cfg2(ctx, lat, Uf_dev, psi_dev, kappa, bsm):
     base = None
     for name, prec, lprec, variant in (("plain_f64", "f64", "f64", bsm.SOLVER_PLAIN),
                                        ("mixed_f32", "f32", "f32", bsm.SOLVER_MIXED),
-                                       ("mixed_f16s", "f16s", "f32", bsm.SOLVER_MIXED)):
+                                       ("mixed_f16s", "f16s", "f32", bsm.SOLVER_MIXED),
+                                       ("mixed_f16s_f16links", "f16s", "f16s", bsm.SOLVER_MIXED)):
         dl = bsm.desc(3, "fund", prec, lprec)
         Ul = U64 if prec == "f64" else ctx.new_gauge(dl)
         if prec != "f64":
