@@ -544,8 +544,8 @@ def main():
                     help="also run N plain 1 GiB device copies (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: multi-GPU runs are not part of this build; "
-              "how the path would shard is described in the design notes", file=sys.stderr)
+        print("bench.py runs on exactly one GPU (--gpus 1); how the path would shard over several "
+              "GPUs is described in the design notes", file=sys.stderr)
         sys.exit(2)
     sections = set(s for s in args.sections.split(",") if s)
     if args.no_cg:

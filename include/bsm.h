@@ -302,7 +302,7 @@ bsm_status bsm_precond_pairs(bsm_ctx ctx, const bsm_field_desc *desc64, const vo
  * (net nullable: M = 1; params->precond_layers picks the collapsed FP16 or
  * the layered FP32 form of M).  Each restart cycle solves the correction equation
  * D e = r in FP32 (directions, D, Gram-Schmidt; sums in FP64), then
- * x += e in FP64 and r = b - D x is recomputed in FP64 (the judge).  A cycle
+ * x += e in FP64 and r = b - D x is recomputed in FP64 (the deciding residual).  A cycle
  * that reduces |r| by less than a factor 2, or meets a non-finite value,
  * hands over to plain FP64 Schur CG from the current x (from x = 0 after a
  * non-finite value).  desc/U_rep: F32 spinors and F32 links (the inner

@@ -58,3 +58,16 @@ def test_argument_validation_without_gpu():
     d = bsm.FieldDesc(3, 0, 3, 0, 0)
     assert L.bsm_dslash_apply(None, C.byref(d), None, 0.1, 0, None, None, None) == bsm.ERR_ARG
     assert L.bsm_gauge_bytes(None, C.byref(d)) == 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; --gpus N > 1 exits with status 2 and a
+    message, before touching a device"""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, cwd=root)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""

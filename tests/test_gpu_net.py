@@ -394,7 +394,7 @@ def test_collapsed_net_rejects_unsupported_shapes():
 
 def test_fgcr_collapsed_and_layered_nets_agree():
     """FGCR with the collapsed FP16 net and with the FP32 layers: both reach
-    the FP64 judge, and their iteration counts agree to within 10 %."""
+    the FP64 stopping test, and their iteration counts agree to within 10 %."""
     import torch
     T = Trainer()
     net, _ = _net_trained(T, steps=120)

@@ -258,7 +258,7 @@ def test_cg_error_norm_decreases_monotonically():
     assert all(errs[i + 1] < errs[i] for i in range(len(errs) - 1))
 
 
-def test_true_residual_judge_after_early_trigger():
+def test_true_residual_decides_after_early_trigger():
     # the normal-equation trigger alone can stop above the target; the solve
     # keeps going until the full-lattice residual is under it
     lat = gen.Lattice(4, 4, 2, 2)
