@@ -110,21 +110,6 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 // non-temporal (streaming) load.
 template <int LP, bool REAL, class T, bool NT = false>
 __device__ inline cx<T> load_link(const void *blk, int64_t stride, int e, uint32_t h) {
-#ifdef BSM_LINK_CPOL
-    // streaming link loads as buffer loads with an explicit cache policy
-    if constexpr (NT && !REAL && (LP == BSM_F32 || LP == BSM_F64)) {
-        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void *)blk, (short)0, 0x7fffffff, 0x00020000);
-        if constexpr (LP == BSM_F32) {
-            const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)((e * stride + h) * 8), 0, BSM_LINK_CPOL);
-            const float2 f = *reinterpret_cast<const float2 *>(&v);
-            return mk<T>((T)f.x, (T)f.y);
-        } else {
-            const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)((e * stride + h) * 16), 0, BSM_LINK_CPOL);
-            const double2 f = *reinterpret_cast<const double2 *>(&v);
-            return mk<T>((T)f.x, (T)f.y);
-        }
-    }
-#endif
     if constexpr (NT && !REAL && LP == BSM_F32) {
         f32x2 v = __builtin_nontemporal_load((const f32x2 *)blk + e * stride + h);
         return mk<T>((T)v.x, (T)v.y);
