@@ -19,9 +19,11 @@ against plain FP64 Schur CG on the same GPU for
   * 16^3 x 32 SU(3) fundamental, links exp(i 0.5 H), kappa 0.1335: FGCR with
     the trained parallel-transport network vs plain CG and vs GCR without
     the network (training time reported separately);
-and the FP64 CPU oracle's hop rate on the host cores.
+the paper's own benchmark (three tasks in its doubling timed loop, rated in
+flop/s, for its three theories on the headline lattice), and the FP64 CPU
+oracle's hop rate on the host cores.
 
-  python bench.py [--steps K] [--warmup W] [--sections hop,cg,cfg3,cfg4,cfg5,cpu]
+  python bench.py [--steps K] [--warmup W] [--sections hop,cg,cfg3,cfg4,cfg5,tasks,cpu]
 """
 from __future__ import annotations
 
@@ -39,7 +41,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-ALL_SECTIONS = ("hop", "cg", "cfg3", "cfg4", "cfg5", "cpu")
+ALL_SECTIONS = ("hop", "cg", "cfg3", "cfg4", "cfg5", "tasks", "cpu")
+# Section III's three theories (N, M): SU(2) stands in for its
+# communication-dominated case, whose M = 4 is not one of the supported
+# representations of SU(2); SU(3) and SU(6) fundamental are its balanced and
+# compute-dominated cases.
+TASK_THEORIES = ((2, "fund", "comms"), (3, "fund", "balance"), (6, "fund", "compute"))
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hop_f32_32x32x32x64_su3_traffic.md")
 
 
@@ -528,6 +535,50 @@ def cpu_cg_small():
             "workload": "16^3x32 SU(3) fund, exp(0.5iH) links, kappa 0.1335, plain FP64 Schur CG to 1e-10"}
 
 
+def bench_tasks(bsm, gen, lat, Uf3, min_seconds):
+    """The paper's benchmark (Section III): the vector, link x spinor and
+    Dphi tasks, each in the library's doubling timed loop (bsm_task_run), for
+    the three theories on the headline lattice, FP64 and FP32.  Random
+    fields: Haar links for SU(2) and SU(6) (gauge seed 1060 + N), the
+    headline exp(0.3iH) links for SU(3); Gaussian sources (seed 2060 + N)."""
+    import torch
+    rows = []
+    for N, rep, role in TASK_THEORIES:
+        t0 = time.time()
+        Uf = Uf3 if N == 3 else gen.gauge_links(lat, N, "haar", gen.SEED_GAUGE + 60 + N)
+        psi = gen.gaussian_spinor(lat, bsm.bsm_rep_dim(N, rep), gen.SEED_SOURCE + 60 + N)
+        log(f"tasks SU({N}) {rep}: fields {time.time() - t0:.1f} s")
+        ctx = bsm.Context(lat.dims, lat.bc)
+        Uf_dev = bsm.to_device_c128(Uf)
+        psi_dev = bsm.to_device_c128(psi)
+        del Uf, psi
+        for prec in ("f64", "f32"):
+            d = bsm.desc(N, rep, prec)
+            U = ctx.new_gauge(d)
+            ctx.bsm_gauge_represent(d, Uf_dev, U)
+            inp, out = ctx.new_spinor(d), ctx.new_spinor(d)
+            ctx.bsm_pack_spinor(d, psi_dev, inp)
+            ctx.bsm_autotune(d, U)          # Dphi runs on the tuned hop plan
+            for task in ("vector", "matvec", "dphi"):
+                ctx.bsm_task_run(d, task, U, 0.13, inp, out, 0.02)
+                it, sec = ctx.bsm_task_run(d, task, U, 0.13, inp, out, min_seconds)
+                flops, nbytes = bsm.bsm_task_cost(lat.dims, d, task, lat.bc)
+                gbs = nbytes * it / sec / 1e9
+                row = dict(theory=f"SU({N}) {rep}", role=role, d_R=d.d_R, prec=prec, task=task,
+                           iterations=it, seconds=round(sec, 4), us_per_iter=round(sec / it * 1e6, 2),
+                           gflops=round(flops * it / sec / 1e9, 1), gbs=round(gbs, 1),
+                           frac_hbm=round(gbs / PEAK_HBM_GBS, 4))
+                log(f"  {row}")
+                rows.append(row)
+            del U, inp, out
+        del Uf_dev, psi_dev
+        ctx.close()
+        torch.cuda.empty_cache()
+    return {"lattice": list(lat.dims), "min_seconds": min_seconds,
+            "flop_model": "per site: vector 24d; mat-vec 128d^2-8d; Dphi 128d^2+72d",
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -540,6 +591,8 @@ def main():
     ap.add_argument("--only-f32", action="store_true", help="skip the FP64 hop timing")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default hop plan (counter runs: every hop dispatch is the same kernel)")
+    ap.add_argument("--task-seconds", type=float, default=0.25,
+                    help="minimum timed period of each task of the paper's benchmark")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run N plain 1 GiB device copies (counter calibration)")
     args = ap.parse_args()
@@ -596,6 +649,7 @@ def main():
         forms["batched"] = bench_cfg4(bsm, gen)
     if "cfg5" in sections:
         forms["learned_preconditioner"] = bench_cfg5(bsm, gen)
+    tasks = bench_tasks(bsm, gen, lat, Uf, args.task_seconds) if "tasks" in sections else None
 
     cpu = None
     if "cpu" in sections:
@@ -635,6 +689,7 @@ def main():
             "frac": round(res["f64"]["gbs"] / PEAK_HBM_GBS, 4), "plan": res["f64"]["plan"]},
         "cg": cg,
         "forms": forms or None,
+        "paper_tasks": tasks,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

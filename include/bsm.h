@@ -365,6 +365,47 @@ bsm_status bsm_batched_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void
                              const bsm_solver_params *params, int32_t n_rhs, const double *kappas,
                              const void *b, void *x, bsm_solver_stats *stats, void *stream);
 
+/* -------------------------------------------------------- benchmark tasks
+ * Section III's benchmark: three tasks (an elementary vector operation, a
+ * matrix-vector operation, then the full Dirac operator) are each repeated
+ * on fixed random fields, the number of repetitions between two readings of
+ * the clock doubling after every reading, and rated as
+ * repetitions x flops per repetition / elapsed time.  The paper does not
+ * define the two elementary operations or the flop counts; here:
+ *   BSM_TASK_VECTOR  out = 0.5 in + 0.5 out                 (bsm_vec_axpby)
+ *   BSM_TASK_MATVEC  out = sum_mu U_mu(x) in(x), each spin  (bsm_link_matvec)
+ *   BSM_TASK_DPHI    out = D in with the given kappa        (bsm_dslash_apply)
+ * Fields are full internal fields (both parities). */
+typedef enum { BSM_TASK_VECTOR = 0, BSM_TASK_MATVEC = 1, BSM_TASK_DPHI = 2 } bsm_task;
+
+/* Link x spinor at every site, no neighbour access:
+ *   out(x)_s = sum_mu U_mu(x) in(x)_s   for spin s = 0..3,
+ * U_mu(x) the forward link of site x in the fermion representation.  in and
+ * out are full internal fields in desc->prec, U_rep in desc->link_prec
+ * (precision pairs as for bsm_dslash_apply); they must not overlap.
+ * Asynchronous. */
+bsm_status bsm_link_matvec(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, const void *in, void *out,
+                           void *stream);
+
+/* Flop count and algorithmic bytes of one repetition of task on the whole
+ * lattice (host only, no device access).  Flops per site: vector 24 d;
+ * mat-vec 128 d^2 - 8 d (real links 64 d^2 - 8 d); Dphi 128 d^2 + 72 d (real
+ * 64 d^2 + 72 d).  Bytes count every element touched once: vector 3 spinor
+ * fields, mat-vec and Dphi the 4 V links plus 2 spinor fields.
+ * BSM_ERR_ARG for odd or non-positive extents, a bad descriptor or task. */
+bsm_status bsm_task_cost(const bsm_lattice *lat, const bsm_field_desc *desc, int32_t task, double *flops,
+                         double *bytes);
+
+/* The timed loop: one untimed call (which validates the arguments), then
+ * rounds of 1, 2, 4, ... repetitions on `stream`, the elapsed time read with
+ * HIP events after each round, until it reaches min_seconds (0 <
+ * min_seconds <= 3600).  iterations (host) receives the total repetitions,
+ * seconds (host) the elapsed time.  kappa is used by BSM_TASK_DPHI only,
+ * U_rep is ignored by BSM_TASK_VECTOR.  Synchronous. */
+bsm_status bsm_task_run(bsm_ctx ctx, const bsm_field_desc *desc, int32_t task, const void *U_rep, double kappa,
+                        const void *in, void *out, double min_seconds, void *stream, int64_t *iterations,
+                        double *seconds);
+
 #ifdef __cplusplus
 }
 #endif

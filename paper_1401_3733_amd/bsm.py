@@ -21,6 +21,7 @@ REP = {"fund": 0, "adj": 1, "sym": 2, "asym": 3}
 F64, F32, F16S = 0, 1, 2
 PREC = {"f64": F64, "f32": F32, "f16s": F16S}
 SOLVER_PLAIN, SOLVER_MIXED = 0, 1
+TASK = {"vector": 0, "matvec": 1, "dphi": 2}
 
 
 class BsmError(RuntimeError):
@@ -113,6 +114,11 @@ _SIGS = {
                                  _vp, _vp, C.POINTER(SolverStats), _vp]),
     "bsm_cg_solve": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, _vp, C.POINTER(SolverParams), _vp, _vp,
                                C.POINTER(SolverStats), _vp]),
+    "bsm_link_matvec": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, _vp, _vp, _vp]),
+    "bsm_task_cost": (C.c_int, [C.POINTER(Lattice), C.POINTER(FieldDesc), C.c_int32, C.POINTER(C.c_double),
+                                C.POINTER(C.c_double)]),
+    "bsm_task_run": (C.c_int, [_vp, C.POINTER(FieldDesc), C.c_int32, _vp, C.c_double, _vp, _vp, C.c_double, _vp,
+                               C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
 }
 
 
@@ -378,6 +384,19 @@ class Context:
             _check(status, "bsm_fgcr_solve")
         return status, st.as_dict()
 
+    def bsm_link_matvec(self, d, U_rep, inp, out, stream=None):
+        _check(lib().bsm_link_matvec(self.handle, C.byref(d), _ptr(U_rep), _ptr(inp), _ptr(out),
+                                     _stream(stream)), "bsm_link_matvec")
+
+    def bsm_task_run(self, d, task, U_rep, kappa, inp, out, min_seconds, stream=None):
+        """(repetitions, seconds) of the timed doubling loop of one task"""
+        it, sec = C.c_int64(), C.c_double()
+        t = TASK[task] if isinstance(task, str) else int(task)
+        _check(lib().bsm_task_run(self.handle, C.byref(d), t, _ptr(U_rep), float(kappa), _ptr(inp), _ptr(out),
+                                  float(min_seconds), _stream(stream), C.byref(it), C.byref(sec)),
+               "bsm_task_run")
+        return it.value, sec.value
+
 
 def _darr(vals, n=None):
     if vals is None:
@@ -392,6 +411,15 @@ def solver_params(kappa, tol=1e-10, schur=True, variant=SOLVER_PLAIN, max_iter=1
                   check_every=8, restart=16, precond_layers=0) -> SolverParams:
     return SolverParams(variant, int(schur), float(kappa), float(tol), int(max_iter), float(delta),
                         int(check_every), int(restart), int(precond_layers))
+
+
+def bsm_task_cost(dims, d: FieldDesc, task, bc=(-1, 1, 1, 1)):
+    """(flops, algorithmic bytes) of one repetition of a benchmark task"""
+    lat = Lattice((C.c_int32 * 4)(*dims), (C.c_int32 * 4)(*bc))
+    f, b = C.c_double(), C.c_double()
+    t = TASK[task] if isinstance(task, str) else int(task)
+    _check(lib().bsm_task_cost(C.byref(lat), C.byref(d), t, C.byref(f), C.byref(b)), "bsm_task_cost")
+    return f.value, b.value
 
 
 def train_params(lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, batch=4, steps=100, seed=0, step0=0) -> TrainParams:
