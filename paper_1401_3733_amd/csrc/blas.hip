@@ -88,9 +88,14 @@ __device__ inline void store_f16s(const char *blk, int64_t S, uint32_t h, const 
     ((float *)(b + D * S))[h] = mx;
 }
 
+// Sites of nblk parity blocks: i < n maps to block i / S, plane index
+// i % S; plane indices at or above live (= Vh) are padding, which kernels
+// skip: no operator writes it, and scratch reused across precisions can hold
+// any bytes there.
 struct SiteIter {
     uint32_t n;       // nblk * Vh_pad
     int64_t S;
+    uint32_t live;
 };
 
 __device__ inline void site_of(uint32_t i, int64_t S, int &b, uint32_t &h) {
@@ -106,6 +111,7 @@ __global__ __launch_bounds__(256) void k_axpby(SiteIter it, void *out, const voi
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < it.n; i += gridDim.x * 256) {
         int b; uint32_t h;
         site_of(i, it.S, b, h);
+        if (h >= it.live) continue;
         Field<PA, D> fa; fa.open(A, b, h, it.S);
         Field<PB, D> fb;
         if constexpr (HASB) fb.open(B, b, h, it.S);
@@ -144,6 +150,7 @@ __global__ __launch_bounds__(256) void k_dot(SiteIter it, const void *A, const v
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < it.n; i += gridDim.x * 256) {
         int b; uint32_t h;
         site_of(i, it.S, b, h);
+        if (h >= it.live) continue;
         Field<PA, D> fa; fa.open(A, b, h, it.S);
         Field<PB, D> fb;
         if constexpr (DOT) fb.open(B, b, h, it.S);
@@ -170,6 +177,7 @@ __global__ __launch_bounds__(256) void k_cg_update(SiteIter it, void *x, const v
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < it.n; i += gridDim.x * 256) {
         int b; uint32_t h;
         site_of(i, it.S, b, h);
+        if (h >= it.live) continue;
         Field<PX, D> fx; fx.open(x, b, h, it.S);
         Field<PP, D> fp; fp.open(p, b, h, it.S);
         Field<PR, D> fr; fr.open(r, b, h, it.S);
@@ -206,6 +214,7 @@ __global__ __launch_bounds__(256) void k_cg_xpay(SiteIter it, void *p, const voi
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < it.n; i += gridDim.x * 256) {
         int b; uint32_t h;
         site_of(i, it.S, b, h);
+        if (h >= it.live) continue;
         Field<PP, D> fp; fp.open(p, b, h, it.S);
         Field<PR, D> fr; fr.open(r, b, h, it.S);
         float buf[PP == BSM_F16S ? 8 * D : 1];
@@ -237,6 +246,7 @@ static SiteIter iter_of(const Geom &g, int nblk) {
     SiteIter it;
     it.n = (uint32_t)((int64_t)nblk * g.Vh_pad);
     it.S = g.Vh_pad;
+    it.live = (uint32_t)g.Vh;
     return it;
 }
 

@@ -455,12 +455,21 @@ __device__ inline void block_rhs_sum(double v, double *partials) {
             (ws[0][threadIdx.x] + ws[1][threadIdx.x]) + (ws[2][threadIdx.x] + ws[3][threadIdx.x]);
 }
 
-__global__ __launch_bounds__(256) void k_block_update(size_t n, float2 *x, const float2 *p, float2 *r,
-                                                      const float2 *q, const double *alpha, double *partials) {
+// Element e of a block field of one or two parity blocks (per elements
+// each) lies on a live site when its offset in its block is below live;
+// padding sites are skipped (no operator writes them).
+__device__ inline bool block_live(size_t e, size_t per, size_t live) {
+    return (e >= per ? e - per : e) < live;
+}
+
+__global__ __launch_bounds__(256) void k_block_update(size_t n, size_t per, size_t live, float2 *x, const float2 *p,
+                                                      float2 *r, const float2 *q, const double *alpha,
+                                                      double *partials) {
     const double al = alpha[threadIdx.x % kNR];
     const float a = (float)al;
     double nrm = 0;
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+        if (!block_live(e, per, live)) continue;
         float2 xv = x[e], pv = p[e], rv = r[e], qv = q[e];
         xv.x = fmaf(a, pv.x, xv.x); xv.y = fmaf(a, pv.y, xv.y);
         rv.x = fmaf(-a, qv.x, rv.x); rv.y = fmaf(-a, qv.y, rv.y);
@@ -471,17 +480,21 @@ __global__ __launch_bounds__(256) void k_block_update(size_t n, float2 *x, const
     block_rhs_sum(nrm, partials);
 }
 
-__global__ __launch_bounds__(256) void k_block_xpay(size_t n, float2 *p, const float2 *r, const double *beta) {
+__global__ __launch_bounds__(256) void k_block_xpay(size_t n, size_t per, size_t live, float2 *p, const float2 *r,
+                                                    const double *beta) {
     const float b = (float)beta[threadIdx.x % kNR];
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+        if (!block_live(e, per, live)) continue;
         float2 pv = p[e], rv = r[e];
         p[e] = make_float2(fmaf(b, pv.x, rv.x), fmaf(b, pv.y, rv.y));
     }
 }
 
-__global__ __launch_bounds__(256) void k_block_norm(size_t n, const float2 *v, double *partials) {
+__global__ __launch_bounds__(256) void k_block_norm(size_t n, size_t per, size_t live, const float2 *v,
+                                                    double *partials) {
     double nrm = 0;
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+        if (!block_live(e, per, live)) continue;
         const float2 t = v[e];
         nrm += (double)t.x * t.x + (double)t.y * t.y;
     }
@@ -489,10 +502,14 @@ __global__ __launch_bounds__(256) void k_block_norm(size_t n, const float2 *v, d
 }
 
 static size_t block_elems(const Geom &g, int d, int nblk) { return (size_t)nblk * g.Vh_pad * d * 4 * kNR; }
+static size_t block_per(const Geom &g, int d) { return (size_t)g.Vh_pad * d * 4 * kNR; }
+static size_t block_live_elems(const Geom &g, int d) { return (size_t)g.Vh * d * 4 * kNR; }
 
 bsm_status block_update(const Geom &g, int d, int nblk, float2 *x, const float2 *p, float2 *r,
                         const float2 *q, const double *alpha, double *partials, hipStream_t st) {
-    k_block_update<<<block_blas_grid(g, d, nblk), 256, 0, st>>>(block_elems(g, d, nblk), x, p, r, q, alpha,
+    if (nblk < 1 || nblk > 2) return fail(BSM_ERR_ARG, "block fields hold one or two parity blocks");
+    k_block_update<<<block_blas_grid(g, d, nblk), 256, 0, st>>>(block_elems(g, d, nblk), block_per(g, d),
+                                                                 block_live_elems(g, d), x, p, r, q, alpha,
                                                                  partials);
     BSM_HIP(hipGetLastError());
     return BSM_OK;
@@ -500,13 +517,17 @@ bsm_status block_update(const Geom &g, int d, int nblk, float2 *x, const float2 
 
 bsm_status block_xpay(const Geom &g, int d, int nblk, float2 *p, const float2 *r, const double *beta,
                       hipStream_t st) {
-    k_block_xpay<<<block_blas_grid(g, d, nblk), 256, 0, st>>>(block_elems(g, d, nblk), p, r, beta);
+    if (nblk < 1 || nblk > 2) return fail(BSM_ERR_ARG, "block fields hold one or two parity blocks");
+    k_block_xpay<<<block_blas_grid(g, d, nblk), 256, 0, st>>>(block_elems(g, d, nblk), block_per(g, d),
+                                                               block_live_elems(g, d), p, r, beta);
     BSM_HIP(hipGetLastError());
     return BSM_OK;
 }
 
 bsm_status block_norm(const Geom &g, int d, int nblk, const float2 *v, double *partials, hipStream_t st) {
-    k_block_norm<<<block_blas_grid(g, d, nblk), 256, 0, st>>>(block_elems(g, d, nblk), v, partials);
+    if (nblk < 1 || nblk > 2) return fail(BSM_ERR_ARG, "block fields hold one or two parity blocks");
+    k_block_norm<<<block_blas_grid(g, d, nblk), 256, 0, st>>>(block_elems(g, d, nblk), block_per(g, d),
+                                                               block_live_elems(g, d), v, partials);
     BSM_HIP(hipGetLastError());
     return BSM_OK;
 }

@@ -40,6 +40,19 @@ constexpr int kZblocks = 1024;
 
 struct ZPtrs { const float2 *p[kGcrMax]; };
 
+// Plane geometry of the F32 full fields: complex number e belongs to plane
+// index (e / 2) % Vh_pad; indices at or above Vh are padding, which the
+// loops skip (no operator writes it, and reused scratch can hold any bytes
+// there).
+struct ZLive {
+    FastDiv pad;
+    uint32_t live;
+    __device__ inline bool operator()(size_t e) const {
+        const uint32_t q = (uint32_t)(e >> 1);
+        return q - pad.div(q) * pad.d < live;
+    }
+};
+
 __device__ inline void block_sum2(double &re, double &im, double2 *ws, int slot, double2 *dst) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -56,12 +69,13 @@ __device__ inline void block_sum2(double &re, double &im, double2 *ws, int slot,
 
 // partials[j][block] = sum conj(W_j) w over this workgroup's elements, for
 // j in [blockIdx.y * 8, min(k, +8))
-__global__ __launch_bounds__(256) void k_zmultidot(ZPtrs W, int k, const float2 *w, size_t n, double2 *partials) {
+__global__ __launch_bounds__(256) void k_zmultidot(ZPtrs W, int k, const float2 *w, size_t n, ZLive lv, double2 *partials) {
     const int j0 = blockIdx.y * kZdotJ;
     double re[kZdotJ], im[kZdotJ];
 #pragma unroll
     for (int q = 0; q < kZdotJ; q++) re[q] = im[q] = 0.0;
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+        if (!lv(e)) continue;
         const float2 y = w[e];
 #pragma unroll
         for (int q = 0; q < kZdotJ; q++) {
@@ -99,12 +113,13 @@ __global__ __launch_bounds__(256) void k_zcols(const double2 *partials, int nb, 
 
 // w -= sum_j coef_j W_j ; z -= sum_j coef_j Z_j ; partials of |w|^2 and <w, r>
 __global__ __launch_bounds__(256) void k_zorth(ZPtrs W, ZPtrs Z, int k, const double2 *coef, float2 *w, float2 *z,
-                                               const float2 *r, size_t n, double2 *partials) {
+                                               const float2 *r, size_t n, ZLive lv, double2 *partials) {
     __shared__ float2 cs[kGcrMax];
     if (threadIdx.x < k) cs[threadIdx.x] = make_float2((float)coef[threadIdx.x].x, (float)coef[threadIdx.x].y);
     __syncthreads();
     double nw = 0, dr = 0, di = 0;
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+        if (!lv(e)) continue;
         float2 wv = w[e], zv = z[e];
         for (int j = 0; j < k; j++) {
             const float2 c = cs[j], a = W.p[j][e], b = Z.p[j][e];
@@ -133,7 +148,7 @@ __global__ __launch_bounds__(256) void k_zorth(ZPtrs W, ZPtrs Z, int k, const do
 // no separate reduction launch is needed; workgroup 0 records nn[k] = |w|^2);
 // then x += alpha z ; r -= alpha w ; per-workgroup |r|^2 into rr_parts
 __global__ __launch_bounds__(256) void k_zupdate(float2 *x, float2 *r, const float2 *z, const float2 *w, size_t n,
-                                                 const double2 *orth, int nb, double *nn, int k, double *rr_parts) {
+                                                 ZLive lv, const double2 *orth, int nb, double *nn, int k, double *rr_parts) {
     __shared__ double2 ws[4 * kZdotJ];
     __shared__ double2 s0, s1;
     {
@@ -153,6 +168,7 @@ __global__ __launch_bounds__(256) void k_zupdate(float2 *x, float2 *r, const flo
     const float ar = d0 > 0 ? (float)(s1.x / d0) : 0.f, ai = d0 > 0 ? (float)(s1.y / d0) : 0.f;
     double rr = 0;
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+        if (!lv(e)) continue;
         const float2 zv = z[e], wv = w[e];
         float2 xv = x[e], rv = r[e];
         xv.x += ar * zv.x - ai * zv.y;
@@ -462,6 +478,7 @@ bsm_status bsm_fgcr_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U
     const size_t f64 = 2 * spinor_block_bytes(BSM_F64, d, g.Vh_pad);
     const size_t f32 = 2 * spinor_block_bytes(BSM_F32, d, g.Vh_pad);
     const size_t n = f32 / sizeof(float2);
+    const ZLive lv{FastDiv((uint32_t)g.Vh_pad), (uint32_t)g.Vh};
     const int nb = (int)std::min<size_t>((n + 255) / 256, kZblocks);
     auto t0 = std::chrono::steady_clock::now();
     // the context's second scratch: the fall back CG uses the first
@@ -529,11 +546,11 @@ bsm_status bsm_fgcr_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U
         }
         TRY(bsm_dslash_apply(ctx, desc, U_rep, prm->kappa, 0, Z[k], Wv[k], stream));
         if (k > 0) {
-            k_zmultidot<<<dim3(nb, (k + kZdotJ - 1) / kZdotJ), 256, 0, st>>>(Wp, k, (const float2 *)Wv[k], n, parts);
+            k_zmultidot<<<dim3(nb, (k + kZdotJ - 1) / kZdotJ), 256, 0, st>>>(Wp, k, (const float2 *)Wv[k], n, lv, parts);
             k_zcols<<<k, 256, 0, st>>>(parts, nb, nn, coef);
         }
-        k_zorth<<<nb, 256, 0, st>>>(Wp, Zp, k, coef, (float2 *)Wv[k], (float2 *)Z[k], (const float2 *)rho, n, parts);
-        k_zupdate<<<nb, 256, 0, st>>>((float2 *)e, (float2 *)rho, (const float2 *)Z[k], (const float2 *)Wv[k], n,
+        k_zorth<<<nb, 256, 0, st>>>(Wp, Zp, k, coef, (float2 *)Wv[k], (float2 *)Z[k], (const float2 *)rho, n, lv, parts);
+        k_zupdate<<<nb, 256, 0, st>>>((float2 *)e, (float2 *)rho, (const float2 *)Z[k], (const float2 *)Wv[k], n, lv,
                                       parts, nb, nn, k, rrp);
         BSM_HIP(hipGetLastError());
         // the workgroup partials of |rho|^2 to a pinned slot; the host sums
