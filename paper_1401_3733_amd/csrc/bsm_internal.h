@@ -4,8 +4,10 @@
 //   Sites of one parity are numbered by their half index h = lex / 2 with
 //   lex = ((t*LZ + z)*LY + y)*LX + x (LX even, so the two sites x = 2k, 2k+1
 //   of a row share h and have opposite parity).  Each parity block stores
-//   component planes of Vh_pad = round_up(V/2, 64) sites, so lane i of a
-//   wavefront touches site i of a plane and every load is coalesced.
+//   component planes of Vh_pad sites (V/2 rounded up to a multiple of 64,
+//   plus 256 when that is a multiple of 1024, so that planes do not start a
+//   large power of two apart), so lane i of a wavefront touches site i of a
+//   plane and every load is coalesced.  Sites h >= Vh of a plane are padding.
 //   Spinor (4 d complex per site, component c = spin*d + colour):
 //     F64  : 4d planes of double2 (one complex)           16 B per site-plane
 //     F32  : 2d planes of float4  (complex 2k, 2k+1)      16 B
