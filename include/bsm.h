@@ -93,6 +93,18 @@ typedef struct bsm_ctx_s *bsm_ctx;
 bsm_status bsm_ctx_create(const bsm_lattice *lat, bsm_ctx *out);
 void bsm_ctx_destroy(bsm_ctx ctx);
 
+/* FP64 reduction slots (one partial sum per workgroup) that a context for
+ * this lattice allocates: enough for every fused-norm launch of the solvers
+ * on it, whatever the representation, precision and traversal plan.  Host
+ * only, no device access; -1 for an invalid lattice. */
+int64_t bsm_reduction_slots(const bsm_lattice *lat);
+/* Workgroups of the largest fused-norm hop launch (both parities, any
+ * traversal plan) for this operator type on this lattice, i.e. the
+ * reduction slots such a launch writes.  A hop whose grid exceeds the
+ * context's slots is refused with BSM_ERR_ARG before any launch.  Host only;
+ * -1 for an invalid lattice or descriptor. */
+int64_t bsm_hop_norm_slots(const bsm_lattice *lat, const bsm_field_desc *desc);
+
 /* Message for the last non-OK status returned on this thread. */
 const char *bsm_last_error(void);
 
@@ -198,6 +210,8 @@ bsm_status bsm_vec_dot(bsm_ctx ctx, const bsm_field_desc *desc, int32_t nparity,
 typedef enum {
     BSM_SOLVER_PLAIN = 0,       /* CG in FP64 (full D^dag D, or Schur if schur=1) */
     BSM_SOLVER_MIXED = 1,       /* reliable-update CG, inner precision desc->prec */
+    BSM_SOLVER_BATCHED = 2,     /* n_rhs right-hand sides with their own kappas (bsm_batched_solve) */
+    BSM_SOLVER_FGCR_NET = 3,    /* flexible GCR with the network preconditioner (bsm_fgcr_solve) */
 } bsm_solver_variant;
 
 typedef struct {
@@ -212,6 +226,10 @@ typedef struct {
     int32_t precond_layers; /* FGCR: 0 applies the network as one collapsed operator
                                (bsm_precond_apply_collapsed) where d_R <= 3; 1 always
                                applies it layer by layer in FP32 (bsm_precond_apply) */
+    int32_t n_rhs;         /* BATCHED: number of right-hand sides */
+    const double *kappas;  /* BATCHED: host array of n_rhs kappas (kappa is then ignored) */
+    int32_t channels;      /* FGCR_NET: network channels */
+    const void *net;       /* FGCR_NET: network weights (device, bsm_net_bytes), NULL: M = 1 */
 } bsm_solver_params;
 
 typedef struct {
@@ -226,7 +244,11 @@ typedef struct {
 } bsm_solver_stats;
 
 /* Solve D x = b (Section II.B: the operator is inverted by conjugate
- * gradients; here CG on the normal equations).  b and x are full internal
+ * gradients; here CG on the normal equations).  params->variant BATCHED
+ * and FGCR_NET forward to bsm_batched_solve (n_rhs, kappas from params;
+ * stats an array of n_rhs) and bsm_fgcr_solve (channels, net from params),
+ * with the arguments and behaviour documented there; the rest of this
+ * comment is about PLAIN and MIXED.  b and x are full internal
  * fields in F64 (desc->prec is the inner precision for MIXED and must be F64
  * for PLAIN); U_rep holds links in desc->link_prec for the inner operator and
  * U_rep64 the FP64 links used for every true residual (may equal U_rep when
@@ -261,6 +283,20 @@ bsm_status bsm_ptc_weight_grad(bsm_ctx ctx, const bsm_field_desc *desc, const vo
 /* z = M(r) for F32 full fields r, z */
 bsm_status bsm_precond_apply(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, int32_t channels,
                              const void *net, const void *r, void *z, void *stream);
+/* Backward pass of z = M(r) = L2(L1(r)) for one field r, the gradients that
+ * training the network needs: with the output gradient
+ * dz = dL/dRe z + i dL/dIm z of a real loss L,
+ *   dr       = M^dag dz = L1^dag (L2^dag dz)        (skipped when dr is NULL),
+ *   dweights = [dW1, dW2] in the layout of net (bsm_net_bytes(channels)),
+ *              dW2_p^{0j} = sum_x dz(x) conj((T_p h_j)(x))^T with h = L1 r,
+ *              dW1_p^{j0} = sum_x (L2^dag dz)_j(x) conj((T_p r)(x))^T
+ * (each entry as in bsm_ptc_weight_grad: dL/dRe W + i dL/dIm W, FP64 sums).
+ * desc as for bsm_precond_apply; r, dz, dr: F32 full fields (dr must not
+ * overlap r or dz); dweights is overwritten.  Scratch from the context.
+ * Asynchronous on stream. */
+bsm_status bsm_precond_backward(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, int32_t channels,
+                                const void *net, const void *r, const void *dz, void *dr, void *dweights,
+                                void *stream);
 /* z = M(r) with the two layers collapsed into one operator, which both
  * layers being linear allows (spin matrices commute with the transports):
  *   z = sum_p T_p G_p,  G_p(y) = sum_q C_pq (T_q r)(y),  C_pq = sum_j W2_p^{0j} W1_q^{j0}.

@@ -13,14 +13,15 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# BSM_LIB selects another build of the same library (e.g. a tuning variant)
-LIB_PATH = os.environ.get("BSM_LIB") or os.path.join(_HERE, "libbsm.so")
+LIB_PATH = os.path.join(_HERE, "libbsm.so")
+if os.environ.get("BSM_LIB"):
+    raise RuntimeError("BSM_LIB is not supported: the binding loads only the in-tree libbsm.so")
 
 OK, ERR_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_NOMEM, ERR_NOT_CONVERGED, ERR_NONFINITE = range(7)
 REP = {"fund": 0, "adj": 1, "sym": 2, "asym": 3}
 F64, F32, F16S = 0, 1, 2
 PREC = {"f64": F64, "f32": F32, "f16s": F16S}
-SOLVER_PLAIN, SOLVER_MIXED = 0, 1
+SOLVER_PLAIN, SOLVER_MIXED, SOLVER_BATCHED, SOLVER_FGCR_NET = 0, 1, 2, 3
 TASK = {"vector": 0, "matvec": 1, "dphi": 2}
 
 
@@ -42,7 +43,9 @@ class FieldDesc(C.Structure):
 class SolverParams(C.Structure):
     _fields_ = [("variant", C.c_int32), ("schur", C.c_int32), ("kappa", C.c_double),
                 ("tol", C.c_double), ("max_iter", C.c_int32), ("delta", C.c_double),
-                ("check_every", C.c_int32), ("restart", C.c_int32), ("precond_layers", C.c_int32)]
+                ("check_every", C.c_int32), ("restart", C.c_int32), ("precond_layers", C.c_int32),
+                ("n_rhs", C.c_int32), ("kappas", C.POINTER(C.c_double)), ("channels", C.c_int32),
+                ("net", C.c_void_p)]
 
 
 class SolverStats(C.Structure):
@@ -68,6 +71,8 @@ _SIGS = {
     "bsm_ctx_destroy": (None, [_vp]),
     "bsm_last_error": (C.c_char_p, []),
     "bsm_rep_dim": (C.c_int32, [C.c_int32, C.c_int32]),
+    "bsm_reduction_slots": (C.c_int64, [C.POINTER(Lattice)]),
+    "bsm_hop_norm_slots": (C.c_int64, [C.POINTER(Lattice), C.POINTER(FieldDesc)]),
     "bsm_gauge_bytes": (C.c_size_t, [_vp, C.POINTER(FieldDesc)]),
     "bsm_spinor_bytes": (C.c_size_t, [_vp, C.POINTER(FieldDesc), C.c_int32, C.c_int32]),
     "bsm_pack_spinor": (C.c_int, [_vp, C.POINTER(FieldDesc), C.c_int32, _vp, _vp, _vp]),
@@ -105,6 +110,7 @@ _SIGS = {
                                         _vp]),
     "bsm_ptc_weight_grad": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp]),
     "bsm_precond_apply": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, _vp, _vp, _vp, _vp]),
+    "bsm_precond_backward": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "bsm_precond_apply_collapsed": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, _vp, _vp, _vp, _vp]),
     "bsm_precond_train": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, _vp, _vp, _vp, _vp, C.c_int32,
                                     C.POINTER(TrainParams), C.POINTER(C.c_float), _vp]),
@@ -329,12 +335,16 @@ class Context:
         return status, [s.as_dict() for s in st]
 
     def bsm_cg_solve(self, d, U_rep, U_rep64, params: SolverParams, b, x, stream=None, check=True):
-        st = SolverStats()
+        """stats: one dict, or a list of n_rhs dicts for the BATCHED variant"""
+        n = params.n_rhs if params.variant == SOLVER_BATCHED else 1
+        st = (SolverStats * max(1, n))()
         status = lib().bsm_cg_solve(self.handle, C.byref(d), _ptr(U_rep), _ptr(U_rep64), C.byref(params),
-                                    _ptr(b), _ptr(x), C.byref(st), _stream(stream))
+                                    _ptr(b), _ptr(x), st, _stream(stream))
         if check and status not in (OK,):
             _check(status, "bsm_cg_solve")
-        return status, st.as_dict()
+        if params.variant == SOLVER_BATCHED:
+            return status, [s.as_dict() for s in st]
+        return status, st[0].as_dict()
 
     # ------------------------------------------------ learned preconditioner
     def new_net(self, channels, device="cuda"):
@@ -356,6 +366,11 @@ class Context:
     def bsm_precond_apply(self, d, U_rep, channels, net, r, z, stream=None):
         _check(lib().bsm_precond_apply(self.handle, C.byref(d), _ptr(U_rep), int(channels), _ptr(net), _ptr(r),
                                        _ptr(z), _stream(stream)), "bsm_precond_apply")
+
+    def bsm_precond_backward(self, d, U_rep, channels, net, r, dz, dr, dweights, stream=None):
+        _check(lib().bsm_precond_backward(self.handle, C.byref(d), _ptr(U_rep), int(channels), _ptr(net), _ptr(r),
+                                          _ptr(dz), _ptr(dr) if dr is not None else None, _ptr(dweights),
+                                          _stream(stream)), "bsm_precond_backward")
 
     def bsm_precond_apply_collapsed(self, d, U_rep, channels, net, r, z, stream=None):
         _check(lib().bsm_precond_apply_collapsed(self.handle, C.byref(d), _ptr(U_rep), int(channels), _ptr(net),
@@ -408,9 +423,17 @@ def _darr(vals, n=None):
 
 
 def solver_params(kappa, tol=1e-10, schur=True, variant=SOLVER_PLAIN, max_iter=100000, delta=0.1,
-                  check_every=8, restart=16, precond_layers=0) -> SolverParams:
-    return SolverParams(variant, int(schur), float(kappa), float(tol), int(max_iter), float(delta),
-                        int(check_every), int(restart), int(precond_layers))
+                  check_every=8, restart=16, precond_layers=0, kappas=None, channels=0,
+                  net=None) -> SolverParams:
+    """kappas (BATCHED) and net (FGCR_NET, a device tensor) are kept alive on
+    the returned structure."""
+    ka = _darr(kappas)
+    p = SolverParams(variant, int(schur), float(kappa), float(tol), int(max_iter), float(delta),
+                     int(check_every), int(restart), int(precond_layers), len(kappas) if kappas is not None else 1,
+                     C.cast(ka, C.POINTER(C.c_double)) if ka is not None else None, int(channels),
+                     net.data_ptr() if net is not None else None)
+    p._keep = (ka, net)
+    return p
 
 
 def bsm_task_cost(dims, d: FieldDesc, task, bc=(-1, 1, 1, 1)):

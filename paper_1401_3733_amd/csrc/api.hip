@@ -1,6 +1,7 @@
 // C ABI: context, validation, sizes, layout conversion, representation and
 // the Wilson-Dirac operator.  Every entry point validates its arguments
 // before launching anything.
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -49,6 +50,25 @@ bsm_status ctx_work_slot(bsm_ctx ctx, int slot, size_t bytes, void **out) {
 }
 
 bsm_status ctx_work(bsm_ctx ctx, size_t bytes, void **out) { return ctx_work_slot(ctx, 0, bytes, out); }
+
+bsm_status ctx_pinned(bsm_ctx ctx, size_t bytes, void **out) {
+    if (bytes > ctx->pinned_bytes) {
+        if (ctx->pinned) BSM_HIP(hipHostFree(ctx->pinned));
+        ctx->pinned = nullptr;
+        ctx->pinned_bytes = 0;
+        if (hipHostMalloc(&ctx->pinned, bytes, hipHostMallocDefault) != hipSuccess)
+            return fail(BSM_ERR_NOMEM, "pinned host scratch");
+        ctx->pinned_bytes = bytes;
+    }
+    *out = ctx->pinned;
+    return BSM_OK;
+}
+
+bsm_status ctx_solver_stream(bsm_ctx ctx, hipStream_t *out) {
+    if (!ctx->solver_stream) BSM_HIP(hipStreamCreateWithFlags(&ctx->solver_stream, hipStreamNonBlocking));
+    *out = ctx->solver_stream;
+    return BSM_OK;
+}
 
 int hop_blocks(const Geom &g) { return (g.Vh + 255) / 256; }
 
@@ -144,8 +164,8 @@ int32_t bsm_rep_dim(int32_t N, int32_t rep) {
     return -1;
 }
 
-bsm_status bsm_ctx_create(const bsm_lattice *lat, bsm_ctx *out) {
-    if (!lat || !out) return fail(BSM_ERR_ARG, "null argument");
+static bsm_status geom_of(const bsm_lattice *lat, Geom &g) {
+    if (!lat) return fail(BSM_ERR_ARG, "null lattice");
     int64_t V = 1;
     for (int mu = 0; mu < 4; mu++) {
         if (lat->L[mu] <= 0 || (lat->L[mu] & 1))
@@ -155,9 +175,7 @@ bsm_status bsm_ctx_create(const bsm_lattice *lat, bsm_ctx *out) {
         V *= lat->L[mu];
     }
     if (V / 2 > (1 << 30)) return fail(BSM_ERR_ARG, "lattice too large");
-    bsm_ctx c = new bsm_ctx_s();   // value-initialised: zeros, then the plans' defaults
-    c->lat = *lat;
-    Geom &g = c->g;
+    g = Geom{};
     for (int mu = 0; mu < 4; mu++) g.L[mu] = lat->L[mu];
     g.LXh = lat->L[1] / 2;
     g.Vh = (int32_t)(V / 2);
@@ -174,8 +192,20 @@ bsm_status bsm_ctx_create(const bsm_lattice *lat, bsm_ctx *out) {
     g.div_xh = FastDiv(g.LXh);
     g.div_y = FastDiv(g.L[2]);
     g.div_z = FastDiv(g.L[3]);
+    return BSM_OK;
+}
+
+bsm_status bsm_ctx_create(const bsm_lattice *lat, bsm_ctx *out) {
+    if (!lat || !out) return fail(BSM_ERR_ARG, "null argument");
+    Geom g0;
+    CHECK(geom_of(lat, g0));
+    bsm_ctx c = new bsm_ctx_s();   // value-initialised: zeros, then the plans' defaults
+    c->lat = *lat;
+    Geom &g = c->g;
+    g = g0;
+    c->n_partials = reduction_slots(g.Vh);
     hipError_t e = hipGetDevice(&c->device);
-    if (e == hipSuccess) e = hipMalloc(&c->partials, sizeof(double) * kMaxPartials);
+    if (e == hipSuccess) e = hipMalloc(&c->partials, sizeof(double) * c->n_partials);
     if (e == hipSuccess) e = hipMalloc(&c->scal, sizeof(double) * kScalars);
     if (e == hipSuccess) e = hipMemset(c->scal, 0, sizeof(double) * kScalars);
     if (e == hipSuccess) e = hipHostMalloc(&c->host_scal, sizeof(double) * kScalars, hipHostMallocDefault);
@@ -187,11 +217,36 @@ bsm_status bsm_ctx_create(const bsm_lattice *lat, bsm_ctx *out) {
     return BSM_OK;
 }
 
+int64_t bsm_reduction_slots(const bsm_lattice *lat) {
+    Geom g;
+    if (geom_of(lat, g) != BSM_OK) return -1;
+    return reduction_slots(g.Vh);
+}
+
+int64_t bsm_hop_norm_slots(const bsm_lattice *lat, const bsm_field_desc *desc) {
+    Geom g;
+    if (geom_of(lat, g) != BSM_OK || check_desc(desc) != BSM_OK) return -1;
+    HopArgs a{};
+    a.np = 2;
+    a.wide = hop_wide_of(desc->d_R, desc->prec);
+    int64_t most = 0;
+    // every traversal plan a context may pick for this operator
+    for (int order = 0; order <= 4; order++) {
+        a.order = order;
+        a.tchunk = 1;
+        if (order == 3 && (g.Vh / g.L[0]) % 256 != 0) continue;
+        most = std::max<int64_t>(most, hop_grid(g, a));
+    }
+    return most;
+}
+
 void bsm_ctx_destroy(bsm_ctx c) {
     if (!c) return;
     if (c->partials) (void)hipFree(c->partials);
     if (c->scal) (void)hipFree(c->scal);
     if (c->host_scal) (void)hipHostFree(c->host_scal);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->solver_stream) (void)hipStreamDestroy(c->solver_stream);
     for (void *w : c->work)
         if (w) (void)hipFree(w);
     delete c;

@@ -171,13 +171,20 @@ struct bsm_ctx_s {
     bsm_lattice lat;
     int device;
     // reduction scratch
-    double *partials;       // device, kMaxPartials doubles
+    double *partials;       // device, n_partials doubles
+    int64_t n_partials;     // reduction_slots(Vh): room for every fused-norm launch
     double *scal;           // device scalars for solvers (kScalars)
     double *host_scal;      // pinned host mirror
     // scratch buffers (lazily grown, zero-filled when allocated):
     //   0: solvers, 1: FGCR (its fall back CG uses 0), 2: network layers
     void *work[3];
     size_t work_bytes[3];
+    // pinned host scratch (lazily grown) and the batched solver's private
+    // stream (created on first use, default priority), kept for the
+    // context's lifetime so a solve allocates nothing after warm-up
+    void *pinned;
+    size_t pinned_bytes;
+    hipStream_t solver_stream;
     bsm::HopPlan plans[16][2][3][3];   // [d_R][real][spinor prec][link prec]
     bsm::BlockPlan block_plans[16];     // [d_R]
 };
@@ -185,8 +192,20 @@ struct bsm_ctx_s {
 namespace bsm {
 constexpr int kMaxPartials = 1 << 16;
 constexpr int kScalars = 4096;
+// FP64 reduction slots of a context for Vh sites per parity: the vector
+// kernels cap their grids at kMaxPartials workgroups, a fused-norm hop writes
+// one partial per workgroup of both parities, and its smallest workgroups
+// (the FP64 colour split with four threads per site) cover 64 sites
+inline int64_t reduction_slots(int64_t Vh) {
+    const int64_t hop = 2 * ((Vh + 63) / 64);
+    return hop > kMaxPartials ? hop : kMaxPartials;
+}
 // scratch that persists across calls, zero-filled when (re)allocated; slot 0
 // is the solvers' buffer, slot 1 FGCR's, slot 2 the network layers
 bsm_status ctx_work(bsm_ctx ctx, size_t bytes, void **out);
 bsm_status ctx_work_slot(bsm_ctx ctx, int slot, size_t bytes, void **out);
+// pinned host scratch of at least bytes (contents undefined after growth)
+bsm_status ctx_pinned(bsm_ctx ctx, size_t bytes, void **out);
+// the context's non-blocking solver stream
+bsm_status ctx_solver_stream(bsm_ctx ctx, hipStream_t *out);
 }

@@ -64,6 +64,7 @@ bsm_status op_apply(const Op &o, int dagger, const void *x, void *y, bool norm, 
         b.in[0] = o.tmp; b.x[0] = x; b.out[0] = y;
         b.a = 1.0; b.b = -o.kappa * o.kappa;
         b.norm_partials = norm ? o.partials : nullptr;
+        b.norm_cap = o.ctx->n_partials;
         apply_plan(o.ctx, o.d, o.real, o.sprec, o.lprec, b);
         if (np) *np = hop_grid(o.g, b);
         return launch_hop(o.g, o.d, o.real, o.sprec, o.lprec, b, st);
@@ -77,6 +78,7 @@ bsm_status op_apply(const Op &o, int dagger, const void *x, void *y, bool norm, 
     a.out[0] = yp; a.out[1] = yp + bb;
     a.a = 1.0; a.b = -o.kappa;
     a.norm_partials = norm ? o.partials : nullptr;
+    a.norm_cap = o.ctx->n_partials;
     apply_plan(o.ctx, o.d, o.real, o.sprec, o.lprec, a);
     if (np) *np = hop_grid(o.g, a);
     return launch_hop(o.g, o.d, o.real, o.sprec, o.lprec, a, st);
@@ -407,6 +409,10 @@ using namespace bsm;
 extern "C" bsm_status bsm_cg_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep,
                                    const void *U_rep64, const bsm_solver_params *prm, const void *b,
                                    void *x, bsm_solver_stats *stats, void *stream) {
+    if (prm && prm->variant == BSM_SOLVER_BATCHED)
+        return bsm_batched_solve(ctx, desc, U_rep64, prm, prm->n_rhs, prm->kappas, b, x, stats, stream);
+    if (prm && prm->variant == BSM_SOLVER_FGCR_NET)
+        return bsm_fgcr_solve(ctx, desc, U_rep, U_rep64, prm, prm->channels, prm->net, b, x, stats, stream);
     if (!ctx || !desc || !prm || !b || !x || !stats || !U_rep || !U_rep64)
         return fail(BSM_ERR_ARG, "null argument");
     if (bsm_rep_dim(desc->N, desc->rep) != desc->d_R || desc->d_R < 2 || desc->d_R > 15)
@@ -702,18 +708,12 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
     TRY(refresh(all));
     BSM_HIP(hipMemsetAsync(B.xlo, 0, B.bbB, st));
     BSM_HIP(hipMemsetAsync(B.p, 0, B.bbB, st));
-    // pinned host mirrors of the device scalars and mask
-    double *hs = nullptr;
-    int *hmask = nullptr;
-    BSM_HIP(hipHostMalloc((void **)&hs, block_scal_doubles() * 8, hipHostMallocDefault));
-    if (hipHostMalloc((void **)&hmask, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
-        (void)hipHostFree(hs);
-        return fail(BSM_ERR_NOMEM, "pinned host scalars");
-    }
-    struct PinnedGuard {
-        double *a; int *b;
-        ~PinnedGuard() { (void)hipHostFree(a); (void)hipHostFree(b); }
-    } guard{hs, hmask};
+    // pinned host mirrors of the device scalars and mask (context scratch)
+    void *pin = nullptr;
+    const size_t hs_bytes = (block_scal_doubles() * 8 + 255) / 256 * 256;
+    TRY(ctx_pinned(B.ctx, hs_bytes + 64 * sizeof(int), &pin));
+    double *hs = (double *)pin;
+    int *hmask = (int *)((char *)pin + hs_bytes);
     for (size_t i = 0; i < block_scal_doubles(); i++) hs[i] = 0.0;
     for (int i = 0; i < 64; i++) hmask[i] = 0;
     for (int r = 0; r < n; r++) {
@@ -727,15 +727,23 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
     BSM_HIP(hipStreamSynchronize(st));
     // ---- capture K iterations once
     B.K = std::max(1, std::min(B.prm->check_every > 0 ? B.prm->check_every : 8, kBlockHist));
-    hipGraph_t graph;
+    hipGraph_t graph = nullptr;
     BSM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     bsm_status cap = BSM_OK;
     for (int k = 0; k < B.K && cap == BSM_OK; k++) cap = block_iteration(B, k);
     hipError_t ce = hipStreamEndCapture(st, &graph);
+    struct GraphGuard {
+        hipGraph_t g;
+        hipGraphExec_t *e;
+        ~GraphGuard() {
+            if (g) (void)hipGraphDestroy(g);
+            if (*e) (void)hipGraphExecDestroy(*e);
+            *e = nullptr;
+        }
+    } graph_guard{graph, &B.graph};
     if (cap != BSM_OK) return cap;
     BSM_HIP(ce);
     BSM_HIP(hipGraphInstantiate(&B.graph, graph, nullptr, nullptr, 0));
-    (void)hipGraphDestroy(graph);
 
     const double delta2 = B.prm->delta > 0 ? B.prm->delta * B.prm->delta : 0.01;
     int it = 0, active = n;
@@ -827,7 +835,6 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
             if (hmask[r]) left |= 1u << r;
         TRY(true_residuals(left));
     }
-    (void)hipGraphExecDestroy(B.graph);
     bsm_status worst = BSM_OK;
     for (int r = 0; r < n; r++) {
         stats[r].iters = iters[r];
@@ -868,9 +875,8 @@ extern "C" bsm_status bsm_batched_solve(bsm_ctx ctx, const bsm_field_desc *desc,
         if (desc->prec != BSM_F64) {
             if (desc->link_prec == BSM_F64) return fail(BSM_ERR_ARG, "mixed inner solve needs F32 or F16 links");
             const size_t lb = 8 * link_block_bytes(desc->link_prec, false, d, g.Vh_pad);
-            BSM_HIP(hipMalloc(&Ulo, lb));
-            bsm_status cs = launch_convert_links(g, d, false, BSM_F64, desc->link_prec, U_rep64, Ulo, user);
-            if (cs != BSM_OK) { (void)hipFree(Ulo); return cs; }
+            TRY(ctx_work_slot(ctx, 1, lb, &Ulo));
+            TRY(launch_convert_links(g, d, false, BSM_F64, desc->link_prec, U_rep64, Ulo, user));
         }
         bsm_field_desc d64 = *desc;
         d64.prec = BSM_F64;
@@ -885,11 +891,10 @@ extern "C" bsm_status bsm_batched_solve(bsm_ctx ctx, const bsm_field_desc *desc,
                                         stream);
             if (s != BSM_OK && worst == BSM_OK) worst = s;
         }
-        if (Ulo) (void)hipFree(Ulo);
         return worst;
     }
     hipStream_t st;
-    BSM_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    TRY(ctx_solver_stream(ctx, &st));
     for (int r0 = 0; r0 < n_rhs; r0 += kNR) {
         BlockSolve B{};
         B.ctx = ctx;
@@ -915,7 +920,6 @@ extern "C" bsm_status bsm_batched_solve(bsm_ctx ctx, const bsm_field_desc *desc,
         if (s != BSM_OK && s != BSM_ERR_NOT_CONVERGED && s != BSM_ERR_NONFINITE) break;
     }
     (void)hipStreamSynchronize(st);
-    (void)hipStreamDestroy(st);
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     for (int r = 0; r < n_rhs; r++) stats[r].seconds = secs;
     if (worst == BSM_ERR_NOT_CONVERGED) fail(worst, "max_iter reached before every RHS met tol");

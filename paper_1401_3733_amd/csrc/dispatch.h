@@ -60,6 +60,7 @@ struct HopArgs {
     int dagger;
     int p0, np;                 // first output parity, number of parities (1 or 2)
     double *norm_partials;
+    int64_t norm_cap;           // slots at norm_partials (checked against the grid)
     // traversal plan (set by launch_hop from the context's tuning):
     //   order 0: workgroup w covers half indices [256 w, 256 w + 256)
     //   order 1: the half lattice is [t][s] with s < S3 = Vh / T split into

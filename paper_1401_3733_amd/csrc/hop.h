@@ -528,6 +528,9 @@ template <int SP, int LP, int D>
 bsm_status hop_run(const Geom &g, bool real, const HopArgs &a, hipStream_t st) {
     const int grid = hop_grid(g, a);
     const int nblk = grid / a.np;
+    if (a.norm_partials && (int64_t)grid > a.norm_cap)
+        return fail(BSM_ERR_ARG, "fused-norm hop needs " + std::to_string(grid) + " reduction slots, " +
+                                     std::to_string(a.norm_cap) + " available");
     if (real && !(D == 3 || D == 8 || D == 15))
         return fail(BSM_ERR_UNSUPPORTED, "real links only for adjoint d_R 3, 8, 15");
     if (a.wide > 0) {

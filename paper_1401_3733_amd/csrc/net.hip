@@ -310,6 +310,55 @@ bsm_status bsm_precond_apply(bsm_ctx ctx, const bsm_field_desc *desc, const void
     return net_apply(ctx, desc, U_rep, channels, net, r, h, z, (hipStream_t)stream);
 }
 
+bsm_status bsm_precond_backward(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep, int32_t channels,
+                                const void *net, const void *r, const void *dz, void *dr, void *dweights,
+                                void *stream) {
+    TRY(check_net_desc(ctx, desc));
+    if (!U_rep || !net || !r || !dz || !dweights) return fail(BSM_ERR_ARG, "null pointer");
+    if (channels < 1 || channels > 64) return fail(BSM_ERR_ARG, "channels must be in [1, 64]");
+    if (dr && (dr == r || dr == dz)) return fail(BSM_ERR_ARG, "dr must differ from r and dz");
+    hipStream_t st = (hipStream_t)stream;
+    const Geom &g = ctx->g;
+    const int d = desc->d_R, C = channels;
+    const size_t f32 = 2 * spinor_block_bytes(BSM_F32, d, g.Vh_pad);
+    const size_t nw1 = layer_weights(1, C), nw2 = layer_weights(C, 1);
+    const size_t parts_bytes = (size_t)ptc_wgrad_blocks(g) * std::max(nw1, nw2) * sizeof(double2);
+    // scratch: h = L1 r (C fields), Gh = L2^dag dz (C fields), both adjoint
+    // weight sets, the weight-gradient partials
+    const size_t need = 2 * C * f32 + (nw1 + nw2) * sizeof(float2) + parts_bytes + 6 * 256;
+    TRY(reserve_net(ctx, d, C));
+    void *work = nullptr;
+    TRY(ctx_work(ctx, need, &work));
+    char *w = (char *)work;
+    auto take = [&](size_t bytes) { char *q = w; w += (bytes + 255) / 256 * 256; return q; };
+    char *h = take(C * f32), *Gh = take(C * f32);
+    float2 *W1a = (float2 *)take(nw1 * sizeof(float2)), *W2a = (float2 *)take(nw2 * sizeof(float2));
+    double2 *parts = (double2 *)take(parts_bytes);
+    const float2 *W1 = (const float2 *)net, *W2 = W1 + nw1;
+    float2 *dW1 = (float2 *)dweights, *dW2 = dW1 + nw1;
+    PtcArgs a{};
+    a.U = U_rep;
+    // h = L1 r
+    a.W = W1; a.in = r; a.out = h; a.cin = 1; a.cout = C;
+    TRY(layer(ctx, d, a, st));
+    // dW2 = sum_x dz conj(T_p h_j)
+    PtcArgs gw{};
+    gw.U = U_rep; gw.in = h; gw.G = dz; gw.cin = C; gw.cout = 1;
+    TRY(launch_ptc_wgrad(g, d, gw, parts, dW2, 1.0, false, st));
+    // Gh = L2^dag dz
+    TRY(launch_ptc_adjoint_weights(W2, W2a, C, 1, st));
+    a.W = W2a; a.in = dz; a.out = Gh; a.cin = 1; a.cout = C;
+    TRY(layer(ctx, d, a, st));
+    // dW1 = sum_x Gh_j conj(T_p r)
+    gw.in = r; gw.G = Gh; gw.cin = 1; gw.cout = C;
+    TRY(launch_ptc_wgrad(g, d, gw, parts, dW1, 1.0, false, st));
+    if (!dr) return BSM_OK;
+    // dr = L1^dag Gh
+    TRY(launch_ptc_adjoint_weights(W1, W1a, 1, C, st));
+    a.W = W1a; a.in = Gh; a.out = dr; a.cin = C; a.cout = 1;
+    return layer(ctx, d, a, st);
+}
+
 bsm_status bsm_precond_apply_collapsed(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep,
                                        int32_t channels, const void *net, const void *r, void *z, void *stream) {
     if (!desc) return fail(BSM_ERR_ARG, "null argument");
@@ -415,8 +464,9 @@ bsm_status bsm_precond_pairs(bsm_ctx ctx, const bsm_field_desc *desc64, const vo
     const size_t f64 = 2 * spinor_block_bytes(BSM_F64, d, g.Vh_pad);
     const size_t f32 = 2 * spinor_block_bytes(BSM_F32, d, g.Vh_pad);
     void *bx = nullptr;
-    // b, x_k and e in FP64 (own allocation: the solver below uses the context scratch)
-    BSM_HIP(hipMalloc(&bx, 3 * f64));
+    // b, x_k and e in FP64, in the FGCR scratch slot (the CG solves below use
+    // the solvers' slot)
+    TRY(ctx_work_slot(ctx, 1, 3 * f64, &bx));
     char *b = (char *)bx, *xk = b + f64, *e = xk + f64;
     bsm_status status = BSM_OK;
     for (int s = 0; s < n_solves && status == BSM_OK; s++) {
@@ -449,7 +499,6 @@ bsm_status bsm_precond_pairs(bsm_ctx ctx, const bsm_field_desc *desc64, const vo
         }
     }
     (void)hipStreamSynchronize(st);
-    (void)hipFree(bx);
     return status;
 }
 

@@ -10,6 +10,10 @@ from tests.gpu_util import Setup, c128, note, rel
 
 pytestmark = pytest.mark.gpu
 
+# FP32 operator against the FP64 oracle on the same FP64 fields (inputs
+# rounded to FP32 on the GPU)
+FP32_TOL = 1e-6
+
 
 def _block_setup(lat, N, seed):
     Uf = gen.gauge_links(lat, N, "haar", seed)
@@ -47,6 +51,7 @@ def test_block_hop_matches_oracle_per_rhs(N, n_rhs):
     par = oracle.parity_mask(lat)
     a = np.linspace(0.5, 1.5, 16)
     b = -np.linspace(0.01, 0.02, 16)
+    worst = 0.0
     for p in (0, 1):
         for dag in (0, 1):
             out = S.ctx.new_block(S.desc)
@@ -56,8 +61,10 @@ def test_block_hop_matches_oracle_per_rhs(N, n_rhs):
             for r in range(n_rhs):
                 ref = a[r] * xs[r] + b[r] * oracle.hop(lat, UR, psi[r], dagger=bool(dag), parity=p)
                 m = par == p
-                assert rel(got[r][m], ref[m]) < 2e-6, (p, dag, r, rel(got[r][m], ref[m]))
+                worst = max(worst, rel(got[r][m], ref[m]))
+                assert rel(got[r][m], ref[m]) < FP32_TOL, (p, dag, r, rel(got[r][m], ref[m]))
                 assert np.all(got[r][~m] == 0)
+    print(f"block hop N={N} n_rhs={n_rhs}: max rel err {worst:.2e}", flush=True)
 
 
 def test_block_hop_without_x():
@@ -73,7 +80,9 @@ def test_block_hop_without_x():
     par = oracle.parity_mask(lat)
     for r in (0, 7, 15):
         ref = oracle.hop(lat, UR, psi[r], parity=0)
-        assert rel(got[r][par == 0], ref[par == 0]) < 2e-6
+        err = rel(got[r][par == 0], ref[par == 0])
+        print(f"block hop without x, rhs {r}: rel err {err:.2e}", flush=True)
+        assert err < FP32_TOL
 
 
 @pytest.mark.parametrize("n_rhs", [16, 7, 3])
@@ -150,7 +159,9 @@ def test_block_hop_full_size_sampled():
         sample = np.concatenate([sites[:64], sites[-64:], rng.choice(sites, 256, replace=False)])
         for r in range(n_rhs):
             ref = oracle.dslash_sites(lat, UR, 1.0, psi[r], sample)
-            assert rel(got[r][sample], ref) < 2e-6, (p, r, rel(got[r][sample], ref))
+            err = rel(got[r][sample], ref)
+            print(f"full-size block hop p={p} rhs {r}: rel err {err:.2e}", flush=True)
+            assert err < FP32_TOL, (p, r, err)
 
 
 PLANS = [(s, w) for s in (1, 2) for w in (1, 2, 4)]
@@ -182,7 +193,7 @@ def test_every_block_plan_gives_the_same_operator(N, spw, wpb, tiled):
         for r in (0, 9, 15):
             ref = psi[r] - 0.1 * oracle.hop(lat, UR, psi[r], dagger=True, parity=p)
             m = par == p
-            assert rel(got[r][m], ref[m]) < 2e-6
+            assert rel(got[r][m], ref[m]) < FP32_TOL, (p, r, rel(got[r][m], ref[m]))
 
 
 @pytest.mark.parametrize("tiled", [0, 1])
@@ -221,3 +232,53 @@ def test_block_autotune_picks_a_plan():
         S.ctx.bsm_set_block_plan(S.desc, 3, 4)
     with pytest.raises(bsm.BsmError):
         S.ctx.bsm_set_block_plan(S.desc, 1, 8)
+
+
+def test_batched_solve_two_stage_reduction_and_staggered_padding():
+    """16 RHS on 16 x 16 x 8 x 8 SU(2) adjoint: V/2 = 8192 sites per parity, so
+    the planes get 256 staggering sites (four whole 64-site tiles of padding)
+    and the block vector kernels run 6336 workgroups, beyond the 4096 partials
+    summed in one stage: the per-RHS sums take the two-stage reduction.  Every
+    RHS against the oracle's FP64 solve to 1e-13."""
+    import torch
+    note("batched solve 16x16x8x8 SU(2) adj, 16 RHS (two-stage per-RHS sums)")
+    lat = gen.Lattice(16, 16, 8, 8)
+    Uf = gen.gauge_links(lat, 2, "haar", 790)
+    S = Setup(lat, 2, "adj", Uf, prec="f64")
+    UR = oracle.represent(Uf, "adj").real.astype(np.complex128)
+    kappas = list(np.linspace(0.10, 0.125, 16))
+    b = gen.gaussian_spinor(lat, 3, 791, n_rhs=16)
+    bb = S.pack(b, n_rhs=16)
+    x = torch.zeros_like(bb)
+    status, stats = S.ctx.bsm_batched_solve(S.desc, S.U, bsm.solver_params(0.1, 1e-10), kappas, bb, x)
+    assert status == 0
+    xs = S.unpack(x, n_rhs=16)
+    worst = 0.0
+    for r in range(16):
+        assert stats[r]["converged"]
+        tr = oracle.true_residual(lat, UR, kappas[r], b[r], xs[r])
+        assert tr <= 1e-10, (r, tr)
+        xo, _ = oracle.solve(lat, UR, kappas[r], b[r], tol=1e-13, schur=True)
+        worst = max(worst, rel(xs[r], xo))
+        assert rel(xs[r], xo) <= 1e-9, (r, rel(xs[r], xo))
+    print(f"two-stage batched: iters {[s['iters'] for s in stats]}, max |x - x_oracle| / |x_oracle| {worst:.2e}",
+          flush=True)
+
+
+def test_cg_solve_batched_variant_forwards():
+    """bsm_cg_solve with the BATCHED variant gives bsm_batched_solve's result"""
+    import torch
+    note("cg_solve BATCHED variant")
+    lat = gen.Lattice(4, 4, 4, 6)
+    Uf = gen.gauge_links(lat, 3, "haar", 792)
+    S = Setup(lat, 3, "adj", Uf, prec="f64")
+    kappas = [0.11, 0.125, 0.1]
+    b = gen.gaussian_spinor(lat, 8, 793, n_rhs=3)
+    bb = S.pack(b, n_rhs=3)
+    x1, x2 = torch.zeros_like(bb), torch.zeros_like(bb)
+    st1, s1 = S.ctx.bsm_batched_solve(S.desc, S.U, bsm.solver_params(0.1, 1e-10), kappas, bb, x1)
+    prm = bsm.solver_params(0.1, 1e-10, variant=bsm.SOLVER_BATCHED, kappas=kappas)
+    st2, s2 = S.ctx.bsm_cg_solve(S.desc, S.U, S.U, prm, bb, x2)
+    assert st1 == st2 == 0 and len(s2) == 3
+    assert [a["iters"] for a in s1] == [a["iters"] for a in s2]
+    assert torch.equal(x1, x2)

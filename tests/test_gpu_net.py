@@ -118,6 +118,42 @@ def test_precond_apply_matches_net():
         S.ctx.bsm_precond_apply(S.desc, S.U, 0, net, S.fields(r[None]), z)
 
 
+def test_precond_backward_matches_oracle_gradients():
+    """bsm_precond_backward with dz = dL/dz of the training loss of one pair
+    gives the oracle's backpropagated weight gradients (loss_and_grad), and
+    dr = M^dag dz matches the oracle's adjoint layers."""
+    import torch
+    note("precond backward N=3 fund C=8")
+    S = NetSetup(3, "fund", 131)
+    C = 8
+    W1, W2 = ptc.init_weights(C, gen.SEED_NET)
+    W1, W2 = _f32_exact(W1 + _rand_w(W1.shape, 17, 0.05)), _f32_exact(W2 + _rand_w(W2.shape, 18, 0.05))
+    net = torch.cat([_w_dev(W1).reshape(-1), _w_dev(W2).reshape(-1)])
+    r = _f32_exact(gen.gaussian_spinor(LAT, 3, 19))
+    e = _f32_exact(gen.gaussian_spinor(LAT, 3, 20))
+    L, g1, g2 = ptc.loss_and_grad(LAT, S.UR32, W1, W2, [r], [e])
+    # the loss gradient with respect to z = M(r) for this pair (batch of one)
+    dz = _f32_exact(2.0 * (ptc.net_apply(LAT, S.UR32, W1, W2, r) - e) / np.vdot(e, e).real)
+    dW = torch.zeros(net.numel(), dtype=torch.complex64, device="cuda")
+    dr = S.out(1)
+    S.ctx.bsm_precond_backward(S.desc, S.U, C, net, S.fields(r[None]), S.fields(dz[None]), dr, dW)
+    torch.cuda.synchronize()
+    got = host(dW).astype(np.complex128)
+    n1 = W1.size
+    e1, e2 = rel(got[:n1].reshape(W1.shape), g1), rel(got[n1:].reshape(W2.shape), g2)
+    dr_ref = oracle.ptc_layer_adjoint(LAT, S.UR32, W1, oracle.ptc_layer_adjoint(LAT, S.UR32, W2, dz[None]))[0]
+    e3 = rel(S.get(dr, 1)[0], dr_ref)
+    print(f"backward rel err: dW1 {e1:.2e} dW2 {e2:.2e} dr {e3:.2e}", flush=True)
+    assert e1 < 4e-6 and e2 < 4e-6 and e3 < 4e-6
+    # dr is optional; null pointers are refused
+    dW2 = torch.zeros_like(dW)
+    S.ctx.bsm_precond_backward(S.desc, S.U, C, net, S.fields(r[None]), S.fields(dz[None]), None, dW2)
+    torch.cuda.synchronize()
+    assert torch.equal(dW2, dW)
+    with pytest.raises(bsm.BsmError):
+        S.ctx.bsm_precond_backward(S.desc, S.U, C, net, None, S.fields(dz[None]), dr, dW)
+
+
 # ------------------------------------------------------------ training
 def _splitmix64(x):
     """Vigna's splitmix64 output function on the counter x"""
@@ -201,6 +237,50 @@ def test_one_adam_step_matches_oracle():
         assert np.all(np.abs(part(got - w0)) <= lr * (1 + 1e-3))
 
 
+def test_several_adam_steps_match_oracle():
+    """Four training steps on the GPU against the oracle's loss, gradients and
+    Adam (beta1 = 0.9, beta2 = 0.999) replayed step by step in FP64 with the
+    same batches: from step 2 on the update depends on the moment decay."""
+    import torch
+    T = Trainer(n_solves=2, iters=(0, 3))
+    S = T.S
+    C = 4
+    W1, W2 = ptc.init_weights(C, gen.SEED_NET + 1)
+    W1 = _f32_exact(W1 + _rand_w(W1.shape, 15, 0.05))
+    W2 = _f32_exact(W2 + _rand_w(W2.shape, 16, 0.05))
+    net = torch.cat([_w_dev(W1).reshape(-1), _w_dev(W2).reshape(-1)])
+    adam = torch.zeros(4 * net.numel(), dtype=torch.float32, device="cuda")
+    lr, batch, seed, steps = 1e-3, 2, 91, 4
+    prm = bsm.train_params(lr=lr, beta1=0.9, beta2=0.999, batch=batch, steps=steps, seed=seed)
+    note(f"precond train {steps} steps C={C}")
+    losses = S.ctx.bsm_precond_train(S.desc, S.U, C, net, adam, T.r_pairs, T.e_pairs, T.n, prm)
+    torch.cuda.synchronize()
+    o1, o2 = ptc.Adam(lr=lr, b1=0.9, b2=0.999), ptc.Adam(lr=lr, b1=0.9, b2=0.999)
+    w1, w2 = W1.copy(), W2.copy()
+    gsteps = []
+    for k in range(steps):
+        pick = [_splitmix64(seed + k * batch + b) % T.n for b in range(batch)]
+        L, g1, g2 = ptc.loss_and_grad(LAT, S.UR32, w1, w2, [T.r[i] for i in pick], [T.e[i] for i in pick])
+        print(f"step {k}: loss gpu {losses[k]:.9e} oracle {L:.9e}", flush=True)
+        assert abs(losses[k] - L) <= 2e-6 * L
+        gsteps.append(np.concatenate([g1.ravel(), g2.ravel()]))
+        w1, w2 = o1.step(w1, g1), o2.step(w2, g2)
+    ref = np.concatenate([w1.ravel(), w2.ravel()])
+    got = host(net).view(np.complex64).astype(np.complex128)
+    G = np.stack(gsteps)
+    worst = 0.0
+    for part in (np.real, np.imag):
+        # coordinates whose gradient is well above FP32 noise at every step;
+        # near-zero gradients make Adam's normalised step sign-sensitive
+        gmax = np.abs(part(G)).max()
+        ok = np.all(np.abs(part(G)) > 1e-2 * gmax, axis=0)
+        assert ok.sum() > 100
+        err = np.abs(part(got - ref))[ok]
+        worst = max(worst, float(err.max()))
+        assert np.all(err <= 2e-6)
+    print(f"max |w_gpu - w_oracle| after {steps} steps: {worst:.2e} (lr {lr})", flush=True)
+
+
 def _net_trained(T, C=8, steps=200, lr=5e-3):
     import torch
     W1, W2 = ptc.init_weights(C, gen.SEED_NET)
@@ -238,6 +318,28 @@ def test_fgcr_without_net_is_gcr():
         D = lambda v: oracle.dslash(LAT, T.UR, KAPPA, v)
         _, it_or, _ = ptc.fgcr(D, lambda r: r, b, tol=1e-10, m=16)
         assert abs(stats["iters"] - it_or) <= max(2, it_or // 10)
+
+
+def test_cg_solve_fgcr_net_variant_forwards():
+    """bsm_cg_solve with the FGCR_NET variant gives bsm_fgcr_solve's result"""
+    import torch
+    T = Trainer(n_solves=1, iters=(0,))
+    S, S64 = T.S, T.S64
+    C = 8
+    W1, W2 = ptc.init_weights(C, gen.SEED_NET)
+    net = torch.cat([_w_dev(_f32_exact(W1)).reshape(-1), _w_dev(_f32_exact(W2)).reshape(-1)])
+    b = gen.gaussian_spinor(LAT, 3, 98)
+    bb = S64.pack(b)
+    x1, x2 = torch.zeros_like(bb), torch.zeros_like(bb)
+    note("cg_solve FGCR_NET variant")
+    prm1 = bsm.solver_params(KAPPA, 1e-10, max_iter=5000, restart=8)
+    st1, s1 = S.ctx.bsm_fgcr_solve(S.desc, S.U, S64.U, prm1, C, net, bb, x1)
+    prm2 = bsm.solver_params(KAPPA, 1e-10, max_iter=5000, restart=8, variant=bsm.SOLVER_FGCR_NET, channels=C,
+                             net=net)
+    st2, s2 = S.ctx.bsm_cg_solve(S.desc, S.U, S64.U, prm2, bb, x2)
+    assert st1 == st2 == 0 and s1["iters"] == s2["iters"]
+    assert torch.equal(x1, x2)
+    assert oracle.true_residual(LAT, T.UR, KAPPA, b, S64.unpack(x2)) <= 1e-10
 
 
 def test_training_reduces_loss_and_fgcr_iterations():

@@ -130,6 +130,39 @@ def test_adam_first_steps_closed_form():
     assert np.allclose(w2 - w1, step, atol=1e-8)
 
 
+def test_adam_moment_decay_with_varying_gradient():
+    """Kingma & Ba (2014), Algorithm 1, with beta1 = 0.9, beta2 = 0.999 and a
+    gradient that changes sign and size from step to step, worked out by hand:
+      step 1, g = 1:    m = 0.1,    v = 0.001,      mhat = 1,            vhat = 1
+      step 2, g = -2:   m = -0.11,  v = 0.004999,   mhat = -0.11/0.19,   vhat = 0.004999/0.001999
+      step 3, g = 0.5:  m = -0.049, v = 0.005244001, mhat = -0.049/0.271, vhat = 0.005244001/0.002997001
+    Each real coordinate moves by -lr mhat / (sqrt(vhat) + eps).  A swapped or
+    mistyped beta, a missing bias correction or a moment that is not carried
+    over changes steps 2 and 3 (the constant-gradient test cannot see those)."""
+    lr, eps = 1e-2, 1e-8
+    opt = ptc.Adam(lr=lr, b1=0.9, b2=0.999, eps=eps)
+    # real part carries the sequence; the imaginary part gets -3 g (same
+    # moments up to the factor, so the same steps with the opposite sign)
+    gs = [1.0, -2.0, 0.5]
+    mhat = [1.0, -0.11 / 0.19, -0.049 / 0.271]
+    vhat = [1.0, 0.004999 / 0.001999, 0.005244001 / 0.002997001]
+    w = np.array([0.25 - 1.5j])
+    for k, gk in enumerate(gs):
+        w_new = opt.step(w, np.array([gk - 3j * gk]))
+        d_re = -lr * mhat[k] / (np.sqrt(vhat[k]) + eps)
+        d_im = -lr * (-3 * mhat[k]) / (np.sqrt(9 * vhat[k]) + eps)
+        assert abs((w_new - w)[0].real - d_re) <= 1e-12, (k, (w_new - w)[0].real, d_re)
+        assert abs((w_new - w)[0].imag - d_im) <= 1e-12, (k, (w_new - w)[0].imag, d_im)
+        w = w_new
+    # the hand values are not those of the swapped betas (0.999, 0.9)
+    swapped = ptc.Adam(lr=lr, b1=0.999, b2=0.9, eps=eps)
+    w = np.array([0.25 - 1.5j])
+    for gk in gs:
+        w = swapped.step(w, np.array([gk - 3j * gk]))
+    ref = 0.25 - lr * sum(m / (np.sqrt(v) + eps) for m, v in zip(mhat, vhat))
+    assert abs(w[0].real - ref) > 1e-4
+
+
 @pytest.mark.parametrize("m", [4, 64])
 def test_fgcr_identity_preconditioner_matches_lu(m):
     lat = gen.Lattice(4, 2, 2, 2)
