@@ -311,6 +311,24 @@ bsm_status bsm_precond_backward(bsm_ctx ctx, const bsm_field_desc *desc, const v
 bsm_status bsm_precond_apply_collapsed(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep,
                                        int32_t channels, const void *net, const void *r, void *z, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation, arguments and result as bsm_precond_apply_collapsed, but its
+ * scratch (the nine FP16 mixed fields, their per-site scales and the
+ * collapsed mixing matrix: 144 d_R + 4 bytes per lattice site plus
+ * 13 KB) lives in a static device array of 64 MiB that the library holds on
+ * every device it runs on until the process ends, never in memory it
+ * allocates.  The call itself allocates nothing; the context (created
+ * beforehand) must belong to the current device.  BSM_ERR_ARG, before any
+ * launch, when the lattice needs more than 64 MiB of scratch (d_R = 3: up to
+ * about 77 000 sites per parity, e.g. 16^3 x 32).  Every call on a device
+ * shares that device's array and leaves its contents behind: calls that
+ * overlap on one device (other streams, other threads) race and must be
+ * ordered by the caller.  Asynchronous on stream. */
+bsm_status bsm_precond_apply_collapsed_noalloc(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep,
+                                               int32_t channels, const void *net, const void *r, void *z,
+                                               void *stream);
+
 typedef struct {
     float lr, beta1, beta2, eps;   /* Adam (e.g. 1e-3, 0.9, 0.999, 1e-8) */
     int32_t batch;                 /* pairs per step */

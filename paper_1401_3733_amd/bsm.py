@@ -111,6 +111,8 @@ _SIGS = {
     "bsm_ptc_weight_grad": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp]),
     "bsm_precond_apply": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, _vp, _vp, _vp, _vp]),
     "bsm_precond_backward": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "bsm_precond_apply_collapsed_noalloc": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, _vp, _vp, _vp,
+                                                      _vp]),
     "bsm_precond_apply_collapsed": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, _vp, _vp, _vp, _vp]),
     "bsm_precond_train": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, _vp, _vp, _vp, _vp, C.c_int32,
                                     C.POINTER(TrainParams), C.POINTER(C.c_float), _vp]),
@@ -375,6 +377,11 @@ class Context:
     def bsm_precond_apply_collapsed(self, d, U_rep, channels, net, r, z, stream=None):
         _check(lib().bsm_precond_apply_collapsed(self.handle, C.byref(d), _ptr(U_rep), int(channels), _ptr(net),
                                                  _ptr(r), _ptr(z), _stream(stream)), "bsm_precond_apply_collapsed")
+
+    def bsm_precond_apply_collapsed_noalloc(self, d, U_rep, channels, net, r, z, stream=None):
+        _check(lib().bsm_precond_apply_collapsed_noalloc(self.handle, C.byref(d), _ptr(U_rep), int(channels),
+                                                         _ptr(net), _ptr(r), _ptr(z), _stream(stream)),
+               "bsm_precond_apply_collapsed_noalloc")
 
     def bsm_precond_train(self, d, U_rep, channels, net, adam_state, r_pairs, e_pairs, n_pairs,
                           params: TrainParams, stream=None):

@@ -213,6 +213,11 @@ bsm_status bsm_ctx_create(const bsm_lattice *lat, bsm_ctx *out) {
         bsm_ctx_destroy(c);
         return hip_check(e, "bsm_ctx_create");
     }
+    bsm_status ns = noalloc_scratch_init(c->device);
+    if (ns != BSM_OK) {
+        bsm_ctx_destroy(c);
+        return ns;
+    }
     *out = c;
     return BSM_OK;
 }

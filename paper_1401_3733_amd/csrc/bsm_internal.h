@@ -208,4 +208,7 @@ bsm_status ctx_work_slot(bsm_ctx ctx, int slot, size_t bytes, void **out);
 bsm_status ctx_pinned(bsm_ctx ctx, size_t bytes, void **out);
 // the context's non-blocking solver stream
 bsm_status ctx_solver_stream(bsm_ctx ctx, hipStream_t *out);
+// device address of the allocation-free network's static scratch on this
+// device (the device must be current); once per device, at context creation
+bsm_status noalloc_scratch_init(int device);
 }

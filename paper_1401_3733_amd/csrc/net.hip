@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 #include <vector>
 
 #include "ptc.h"
@@ -251,6 +252,41 @@ static uint64_t splitmix64(uint64_t x) {
     return x ^ (x >> 31);
 }
 
+// ------------------------------------------------ allocation-free network
+// Scratch of bsm_precond_apply_collapsed_noalloc: the nine FP16 mixed fields,
+// their per-site scales and the collapsed mixing matrix, in a static device
+// array (every device the library runs on holds its own copy until the
+// process ends).  Host code never passes `scratch` itself to a kernel: its
+// device address comes from hipGetSymbolAddress, taken once per device at
+// context creation and kept in noalloc_ptr.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+constexpr int kNoallocDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+static std::mutex noalloc_mu;
+static void *noalloc_ptr[kNoallocDevices];
+
+bsm_status noalloc_scratch_init(int device) {
+    if (device < 0 || device >= kNoallocDevices) return fail(BSM_ERR_UNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (noalloc_ptr[device]) return BSM_OK;
+    int cur = -1;
+    BSM_HIP(hipGetDevice(&cur));
+    if (cur != device) return fail(BSM_ERR_ARG, "static scratch set up with another device current");
+    void *ptr = nullptr;
+    BSM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(BSM_ERR_HIP, "hipGetSymbolAddress(scratch) returned null");
+    noalloc_ptr[device] = ptr;
+    return BSM_OK;
+}
+
+static bsm_status noalloc_scratch(int device, void **out) {
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (device < 0 || device >= kNoallocDevices || !noalloc_ptr[device])
+        return fail(BSM_ERR_HIP, "static scratch was not set up for this device");
+    *out = noalloc_ptr[device];
+    return BSM_OK;
+}
+
 }  // namespace bsm
 
 using namespace bsm;
@@ -377,6 +413,37 @@ bsm_status bsm_precond_apply_collapsed(bsm_ctx ctx, const bsm_field_desc *desc, 
     hipStream_t st = (hipStream_t)stream;
     NetFastArgs a;
     TRY(net_fast_prepare(ctx, desc->d_R, channels, net, U_rep, desc->link_prec, a, st));
+    a.in = r;
+    a.out = z;
+    return launch_net_fast(ctx->g, desc->d_R, a, st);
+}
+
+bsm_status bsm_precond_apply_collapsed_noalloc(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep,
+                                               int32_t channels, const void *net, const void *r, void *z,
+                                               void *stream) {
+    if (!desc) return fail(BSM_ERR_ARG, "null argument");
+    bsm_field_desc d32 = *desc;
+    if (d32.link_prec == BSM_F16S) d32.link_prec = BSM_F32;   // FP16 links accepted, as in the allocating form
+    TRY(check_net_desc(ctx, &d32));
+    if (!U_rep || !net || !r || !z) return fail(BSM_ERR_ARG, "null pointer");
+    if (channels < 1 || channels > 64) return fail(BSM_ERR_ARG, "channels must be in [1, 64]");
+    if (r == z) return fail(BSM_ERR_ARG, "r and z must differ");
+    if (!net_fast_supported(desc->d_R)) return fail(BSM_ERR_UNSUPPORTED, "the collapsed network runs for d_R <= 3");
+    const size_t need = net_fast_bytes(ctx->g, desc->d_R);
+    if (need > kNoallocScratchBytes)
+        return fail(BSM_ERR_ARG, "lattice needs " + std::to_string(need) + " bytes of network scratch, more than the " +
+                                     std::to_string(kNoallocScratchBytes) + " of the static array");
+    int cur = -1;
+    BSM_HIP(hipGetDevice(&cur));
+    if (cur != ctx->device) return fail(BSM_ERR_ARG, "the context belongs to another device");
+    void *ptr = nullptr;
+    TRY(noalloc_scratch(ctx->device, &ptr));
+    hipStream_t st = (hipStream_t)stream;
+    NetFastArgs a{};
+    a.U = U_rep;
+    a.link_prec = desc->link_prec;
+    net_fast_carve(ctx->g, desc->d_R, ptr, a);
+    TRY(launch_net_collapse(net, channels, a, st));
     a.in = r;
     a.out = z;
     return launch_net_fast(ctx->g, desc->d_R, a, st);
