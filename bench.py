@@ -41,7 +41,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-ALL_SECTIONS = ("hop", "cg", "cfg3", "cfg4", "cfg5", "tasks", "cpu")
+ALL_SECTIONS = ("hop", "cg", "cfg1", "cfg3", "cfg4", "cfg5", "tasks", "cpu")
 # Section III's three theories (N, M): SU(2) stands in for its
 # communication-dominated case, whose M = 4 is not one of the supported
 # representations of SU(2); SU(3) and SU(6) fundamental are its balanced and
@@ -131,6 +131,137 @@ def rel_diff(ctx, d64, x, y):
     return float(np.sqrt(ctx.bsm_vec_dot(d64, 2, t) / ctx.bsm_vec_dot(d64, 2, y)))
 
 
+# ------------------------------------------------------------- conditioning
+def mean_link_and_plaquette(Uf, dims):
+    """<Re Tr U>/N over all links and <Re Tr P_munu>/N over all plaquettes
+    (mu < nu) of canonical links Uf [V][4][N][N] (lattice axes t, z, y, x;
+    direction mu = 0 is t, 1..3 are x, y, z)."""
+    T, X, Y, Z = dims
+    N = Uf.shape[-1]
+    U = Uf.reshape(T, Z, Y, X, 4, N, N)
+    axis = {0: 0, 1: 3, 2: 2, 3: 1}
+    mean_link = float(np.trace(U, axis1=-2, axis2=-1).real.mean() / N)
+    plaq, count = 0.0, 0
+    for mu in range(4):
+        for nu in range(mu + 1, 4):
+            Umu, Unu = U[..., mu, :, :], U[..., nu, :, :]
+            Unu_xmu = np.roll(Unu, -1, axis=axis[mu])
+            Umu_xnu = np.roll(Umu, -1, axis=axis[nu])
+            P = Umu @ Unu_xmu @ np.conj(np.swapaxes(Umu_xnu, -1, -2)) @ np.conj(np.swapaxes(Unu, -1, -2))
+            plaq += float(np.trace(P, axis1=-2, axis2=-1).real.sum())
+            count += P.size // (N * N)
+            del P, Unu_xmu, Umu_xnu
+    return mean_link, plaq / count / N
+
+
+def cg_lanczos(ctx, d64, U64, kappa, b, schur=True, tol=1e-10, max_iter=3000):
+    """Extreme eigenvalues of A = M^dag M (M the even-odd Schur operator
+    Dhat = 1 - kappa^2 H_eo H_oe on even sites, or D on the full lattice)
+    from the coefficients of plain CG on A x = M^dag bhat, run with the
+    library's FP64 operator and vector calls: the CG tridiagonal has
+    T_kk = 1/alpha_k + beta_(k-1)/alpha_(k-1), T_k,k+1 = sqrt(beta_k)/alpha_k
+    (Lanczos connection), and its extreme eigenvalues converge to those of A
+    long before CG reaches tol.  cond(M) = sqrt(lambda_max / lambda_min)."""
+    import torch
+    nb = ctx.spinor_bytes(d64, 1, 1)
+    npar = 1 if schur else 2
+
+    def blk(t, p):
+        return t[p * nb:(p + 1) * nb]
+
+    if schur:
+        tmp = ctx.new_spinor(d64, 1)
+
+        def M(x, y, dag):
+            ctx.bsm_dslash_eo(d64, U64, 1, dag, 0.0, None, 1.0, x, tmp)
+            ctx.bsm_dslash_eo(d64, U64, 0, dag, 1.0, x, -kappa * kappa, tmp, y)
+
+        bh = ctx.new_spinor(d64, 1)
+        ctx.bsm_dslash_eo(d64, U64, 0, 0, 1.0, blk(b, 0), kappa, blk(b, 1), bh)
+        new = lambda: ctx.new_spinor(d64, 1)
+    else:
+        def M(x, y, dag):
+            ctx.bsm_dslash_apply(d64, U64, kappa, dag, x, y)
+
+        bh = b
+        new = lambda: ctx.new_spinor(d64, 2)
+    r, p, t, Ap = new(), new(), new(), new()
+    M(bh, r, 1)
+    ctx.bsm_vec_axpby(d64, npar, 1.0, r, 0.0, None, p)
+    rr = ctx.bsm_vec_dot(d64, npar, r)
+    rr0 = rr
+    alphas, betas = [], []
+    t0 = time.perf_counter()
+    while len(alphas) < max_iter and rr > tol * tol * rr0:
+        M(p, t, 0)
+        M(t, Ap, 1)
+        alpha = rr / ctx.bsm_vec_dot(d64, npar, p, Ap)
+        ctx.bsm_vec_axpby(d64, npar, 1.0, r, -alpha, Ap, r)
+        rr_new = ctx.bsm_vec_dot(d64, npar, r)
+        beta = rr_new / rr
+        rr = rr_new
+        ctx.bsm_vec_axpby(d64, npar, 1.0, r, beta, p, p)
+        alphas.append(alpha)
+        betas.append(beta)
+    torch.cuda.synchronize()
+    k = len(alphas)
+    diag = np.array([1.0 / alphas[i] + (betas[i - 1] / alphas[i - 1] if i else 0.0) for i in range(k)])
+    off = np.array([np.sqrt(betas[i]) / alphas[i] for i in range(k - 1)])
+    ev = np.linalg.eigvalsh(np.diag(diag) + np.diag(off, 1) + np.diag(off, -1))
+    lo, hi = float(ev[0]), float(ev[-1])
+    del r, p, t, Ap
+    return {"operator": "Dhat^dag Dhat (even-odd Schur)" if schur else "D^dag D (full lattice)",
+            "lambda_min": lo, "lambda_max": hi, "cond_normal": hi / lo, "cond_D": float(np.sqrt(hi / lo)),
+            "cg_iters": k, "seconds": round(time.perf_counter() - t0, 3),
+            "method": "extreme Ritz values of the CG-Lanczos tridiagonal (FP64 CG to a 1e-10 normal residual); "
+                      "lambda_min is an upper estimate of the smallest eigenvalue"}
+
+
+def conditioning(ctx, d64, U64, kappa, b, Uf_host, dims, schur=True):
+    ml, pl = mean_link_and_plaquette(Uf_host, dims)
+    out = {"mean_link": ml, "plaquette": pl}
+    out.update(cg_lanczos(ctx, d64, U64, kappa, b, schur=schur))
+    log(f"  conditioning: {out}")
+    return out
+
+
+def time_block_hops(ctx, d, Ub, A, B, steps):
+    """Mean duration of one 16-RHS even-odd block hop (alternating parity),
+    HIP events on the stream the library launches on."""
+    import torch
+    nb = ctx.block_bytes(d) // 2
+    ones = np.ones(16)
+
+    def step(i):
+        p = i & 1
+        ctx.bsm_dslash_eo_block(d, Ub, p, 0, None, None, ones, A[(1 - p) * nb:(2 - p) * nb], B[p * nb:(p + 1) * nb])
+
+    for i in range(4):
+        step(i)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for i in range(steps):
+        step(i)
+    e1.record(st)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def hop_row(ctx, d, U, A, B, n_out, real, steps, warmup, autotune=True):
+    """Autotuned even-odd hop timing with its algorithmic bytes and flops."""
+    if autotune:
+        ctx.bsm_autotune(d, U)
+    ms = time_hops(ctx, d, U, A, B, steps, warmup)
+    inv = {0: "f64", 1: "f32", 2: "f16s"}
+    nbytes = hop_bytes(d.d_R, real, inv[d.prec], inv[d.link_prec], n_out)
+    return {"us": round(ms * 1e3, 2), "gbs": round(nbytes / ms / 1e6, 1),
+            "frac": round(nbytes / ms / 1e6 / PEAK_HBM_GBS, 4),
+            "tflops": round(hop_flops(d.d_R, real, n_out) / ms / 1e9, 2), "bytes": nbytes,
+            "plan": ctx.bsm_get_hop_plan(d)}
+
+
 # --------------------------------------------------------------- sections
 def bench_hop(ctx, lat, Uf_dev, psi_dev, args, bsm):
     import torch
@@ -158,7 +289,18 @@ def bench_hop(ctx, lat, Uf_dev, psi_dev, args, bsm):
     return res
 
 
-def bench_cg_cfg2(ctx, lat, Uf_dev, psi_dev, kappa, bsm):
+def _to_host(ctx, bsm, d64, x, V, d):
+    import torch
+    c = torch.zeros((V, 4, d), dtype=torch.complex128, device="cuda")
+    ctx.bsm_unpack_spinor(d64, x, c)
+    h = c.cpu().numpy()
+    del c
+    return h
+
+
+def bench_cg_cfg2(ctx, lat, Uf_dev, psi_dev, kappa, bsm, Uf_host=None, keep=None):
+    """keep (dict or None): receives the host copy of each form's solution
+    for the oracle comparison of the CPU leg"""
     import torch
     cg = {}
     d64 = bsm.desc(3, "fund", "f64")
@@ -168,6 +310,7 @@ def bench_cg_cfg2(ctx, lat, Uf_dev, psi_dev, kappa, bsm):
     ctx.bsm_pack_spinor(d64, psi_dev, b)
     x64 = ctx.new_spinor(d64)
     x = ctx.new_spinor(d64)
+    x11 = ctx.new_spinor(d64) if keep is not None else None
     base = None
     for name, prec, lprec, variant in (("plain_f64", "f64", "f64", bsm.SOLVER_PLAIN),
                                        ("mixed_f32", "f32", "f32", bsm.SOLVER_MIXED),
@@ -186,10 +329,51 @@ def bench_cg_cfg2(ctx, lat, Uf_dev, psi_dev, kappa, bsm):
             base = st["seconds"]
         else:
             cg[name]["x_rel_diff_vs_plain"] = rel_diff(ctx, d64, x, x64)
+        if keep is not None:
+            keep[name] = _to_host(ctx, bsm, d64, out, lat.V, 3)
+            # the error against the oracle is bounded by cond(D) x the true
+            # residual: the same solve to 1e-11 shows the bound at work
+            prm11 = bsm.solver_params(kappa, 1e-11, schur=True, variant=variant)
+            s11, st11 = ctx.bsm_cg_solve(dl, Ul, U64, prm11, b, x11, check=False)
+            cg[name]["tol_1e-11"] = dict(status=s11, iters=st11["iters"], true_rel_res=st11["true_rel_res"],
+                                         seconds=round(st11["seconds"], 4))
+            keep[name + "_tol_1e-11"] = _to_host(ctx, bsm, d64, x11, lat.V, 3)
         log(f"  {cg[name]}")
-    del U64, b, x, x64
+    if Uf_host is not None:
+        log("cfg2 conditioning ...")
+        cg["conditioning"] = conditioning(ctx, d64, U64, kappa, b, Uf_host, lat.dims)
+    del U64, b, x, x64, x11
     torch.cuda.empty_cache()
     return cg
+
+
+def bench_cfg1(bsm, gen, keep=None):
+    """Plain FP64 CG on the full D^dag D, 4^4 SU(2) fundamental, Haar links,
+    kappa 0.12 (latency bound: a correctness and time-to-solution case)."""
+    import torch
+    c = gen.CONFIGS[1]
+    lat = gen.config_lattice(1)
+    Uf_host = gen.config_links(1, lat)
+    Uf = bsm.to_device_c128(Uf_host)
+    ctx = bsm.Context(lat.dims, lat.bc)
+    d64 = bsm.desc(2, "fund", "f64")
+    U64 = ctx.new_gauge(d64)
+    ctx.bsm_gauge_represent(d64, Uf, U64)
+    b = ctx.new_spinor(d64)
+    ctx.bsm_pack_spinor(d64, bsm.to_device_c128(gen.config_source(1, 2, lat)), b)
+    x = ctx.new_spinor(d64)
+    log("cfg1 plain FP64 CG on D^dag D ...")
+    prm = bsm.solver_params(c["kappa"], 1e-10, schur=False)
+    status, st = warm_solve(lambda: ctx.bsm_cg_solve(d64, U64, U64, prm, b, x, check=False))
+    out = {"workload": "4^4 SU(2) fund, Haar links, kappa 0.12, CG on the full D^dag D to 1e-10",
+           "plain_f64": solve_row(status, st)}
+    if keep is not None:
+        keep["cfg1"] = _to_host(ctx, bsm, d64, x, lat.V, 2)
+    log(f"  {out['plain_f64']}")
+    out["conditioning"] = conditioning(ctx, d64, U64, c["kappa"], b, Uf_host, lat.dims, schur=False)
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_cfg3(bsm, gen):
@@ -198,7 +382,8 @@ def bench_cfg3(bsm, gen):
     c = gen.CONFIGS[3]
     lat = gen.config_lattice(3)
     log("cfg3: generating 32^3x64 SU(3) links and source ...")
-    Uf = bsm.to_device_c128(gen.config_links(3, lat))
+    Uf_host = gen.config_links(3, lat)
+    Uf = bsm.to_device_c128(Uf_host)
     ctx = bsm.Context(lat.dims, lat.bc)
     d64 = bsm.desc(3, "sym", "f64")
     src = bsm.to_device_c128(gen.config_source(3, d64.d_R, lat))
@@ -229,6 +414,78 @@ def bench_cfg3(bsm, gen):
         log(f"  {out[name]}")
         if prec != "f64":
             del Ul
+    x64_keep = x64
+    del x
+    # the single operator of each precision form, autotuned and timed like the headline hop
+    hops = {}
+    Vh = lat.V // 2
+    for name, prec, lprec in (("f64", "f64", "f64"), ("f32", "f32", "f32"), ("f16s_f32links", "f16s", "f32"),
+                              ("f16s_f16links", "f16s", "f16s")):
+        dl = bsm.desc(3, "sym", prec, lprec)
+        Ul = U64 if prec == "f64" else ctx.new_gauge(dl)
+        if prec != "f64":
+            ctx.bsm_gauge_represent(dl, Uf, Ul)
+        A, B = ctx.new_spinor(dl), ctx.new_spinor(dl)
+        canon = torch.zeros((lat.V, 4, 6), dtype=torch.complex128, device="cuda")
+        ctx.bsm_unpack_spinor(d64, b, canon)
+        ctx.bsm_pack_spinor(dl, canon, A)
+        del canon
+        log(f"cfg3 hop {name} ...")
+        hops[name] = hop_row(ctx, dl, Ul, A, B, Vh, False, 100 if prec != "f64" else 40, 10)
+        log(f"  {hops[name]}")
+        del A, B
+        if prec != "f64":
+            del Ul
+    out["hop"] = hops
+    # fundamental links, the representation formed inside the hop: 8 N x N
+    # complex links per output site instead of 8 d x d
+    hops_otf = {}
+    bl = {"f64": 8, "f32": 4, "f16s": 2}
+    for name, prec, lprec in (("f64", "f64", "f64"), ("f32", "f32", "f32"), ("f16s_f32links", "f16s", "f32"),
+                              ("f16s_f16links", "f16s", "f16s")):
+        dl = bsm.desc(3, "sym", prec, lprec, fundamental_links=True)
+        Ul = ctx.new_gauge(dl)
+        ctx.bsm_gauge_represent(dl, Uf, Ul)
+        A, B = ctx.new_spinor(dl), ctx.new_spinor(dl)
+        canon = torch.zeros((lat.V, 4, 6), dtype=torch.complex128, device="cuda")
+        ctx.bsm_unpack_spinor(d64, b, canon)
+        ctx.bsm_pack_spinor(dl, canon, A)
+        del canon
+        log(f"cfg3 hop with fundamental links {name} ...")
+        ctx.bsm_autotune(dl, Ul)
+        ms = time_hops(ctx, dl, Ul, A, B, 100 if prec != "f64" else 40, 10)
+        nbytes = (8 * 2 * 9 * bl[lprec] + 2 * (8 * 6 * bl[prec] + (4 if prec == "f16s" else 0))) * Vh
+        hops_otf[name] = {"us": round(ms * 1e3, 2), "gbs": round(nbytes / ms / 1e6, 1),
+                          "frac": round(nbytes / ms / 1e6 / PEAK_HBM_GBS, 4), "bytes": nbytes,
+                          "speedup_vs_stored_links": round(hops[name]["us"] / (ms * 1e3), 3),
+                          "plan": ctx.bsm_get_hop_plan(dl)}
+        log(f"  {hops_otf[name]}")
+        del A, B, Ul
+    out["hop_otf"] = hops_otf
+    # the solves with fundamental links (FP64 fundamental links for the true
+    # residuals and reliable updates too)
+    d64o = bsm.desc(3, "sym", "f64", fundamental_links=True)
+    U64o = ctx.new_gauge(d64o)
+    ctx.bsm_gauge_represent(d64o, Uf, U64o)
+    x64o = ctx.new_spinor(d64)
+    for name, prec, lprec, variant in (("plain_f64_otf", "f64", "f64", bsm.SOLVER_PLAIN),
+                                       ("mixed_f16s_otf", "f16s", "f32", bsm.SOLVER_MIXED),
+                                       ("mixed_f16s_f16links_otf", "f16s", "f16s", bsm.SOLVER_MIXED)):
+        dl = bsm.desc(3, "sym", prec, lprec, fundamental_links=True)
+        Ul = U64o if prec == "f64" else ctx.new_gauge(dl)
+        if prec != "f64":
+            ctx.bsm_gauge_represent(dl, Uf, Ul)
+        prm = bsm.solver_params(c["kappa"], 1e-10, schur=True, variant=variant)
+        log(f"cfg3 {name} ...")
+        status, st = warm_solve(lambda: ctx.bsm_cg_solve(dl, Ul, U64o, prm, b, x64o, check=False))
+        out[name] = solve_row(status, st, base)
+        out[name]["x_rel_diff_vs_plain"] = rel_diff(ctx, d64, x64o, x64_keep)
+        log(f"  {out[name]}")
+        if prec != "f64":
+            del Ul
+    del U64o, x64o, x64_keep
+    log("cfg3 conditioning ...")
+    out["conditioning"] = conditioning(ctx, d64, U64, c["kappa"], b, Uf_host, lat.dims)
     ctx.close()
     torch.cuda.empty_cache()
     return out
@@ -240,7 +497,8 @@ def bench_cfg4(bsm, gen):
     c = gen.CONFIGS[4]
     lat = gen.config_lattice(4)
     log("cfg4: generating 24^3x48 SU(4) links and 16 sources ...")
-    Uf = bsm.to_device_c128(gen.config_links(4, lat))
+    Uf_host = gen.config_links(4, lat)
+    Uf = bsm.to_device_c128(Uf_host)
     ctx = bsm.Context(lat.dims, lat.bc)
     d64 = bsm.desc(4, "adj", "f64")
     U = ctx.new_gauge(d64)
@@ -276,6 +534,59 @@ def bench_cfg4(bsm, gen):
         its.append(st1["iters"])
         worst = max(worst, rel_diff(ctx, d64, xb[sl], xs[sl]))
     log(f"  {tseq:.3f} s, iters {its}")
+    # the 16-RHS block hop on its own, under the plan the batched solve tuned,
+    # on block fields holding the 16 sources
+    d32 = bsm.desc(4, "adj", "f32")
+    Ub = ctx.new_block_gauge(d32)
+    ctx.bsm_gauge_to_block(d32, U, Ub)
+    canon = torch.zeros((n, lat.V, 4, 15), dtype=torch.complex128, device="cuda")
+    for r in range(n):
+        ctx.bsm_unpack_spinor(d64, b[r * fb:(r + 1) * fb], canon[r])
+    A, B = ctx.new_block(d32), ctx.new_block(d32)
+    ctx.bsm_pack_block(d32, canon, A, n)
+    del canon
+    torch.cuda.synchronize()
+    log("cfg4 block hop timing ...")
+    ms = time_block_hops(ctx, d32, Ub, A, B, 40)
+    Vh = lat.V // 2
+    nbytes = (8 * 15 * 15 * 4 + 16 * 2 * 8 * 15 * 4) * Vh
+    flops = 16 * (64 * 15 * 15 + 56 * 15) * Vh
+    block_hop = {"us": round(ms * 1e3, 2), "gbs": round(nbytes / ms / 1e6, 1),
+                 "frac": round(nbytes / ms / 1e6 / PEAK_HBM_GBS, 4), "tflops": round(flops / ms / 1e9, 2),
+                 "bytes": nbytes, "plan": ctx.bsm_get_block_plan(d32),
+                 "bytes_model": "8 real FP32 d x d links + 16 x (input + output) FP32 spinors per output site"}
+    log(f"  {block_hop}")
+    del A, B, Ub
+    # the shifted family: one source (the first RHS), all 16 kappas in one
+    # Krylov space, against 16 sequential plain FP64 solves of that source
+    log("cfg4 shifted family (one source, 16 kappas; warm-up call first) ...")
+    prm_s = bsm.solver_params(kappas[0], 1e-10, max_iter=5000)
+    ctx.bsm_shifted_solve(d64, U, prm_s, kappas, b[0:fb], xb, check=False)
+    s_st, s_stats = ctx.bsm_shifted_solve(d64, U, prm_s, kappas, b[0:fb], xb, check=False)
+    t_shift = s_stats[0]["seconds"]
+    log(f"  {t_shift:.3f} s, iters {[s['iters'] for s in s_stats]}, fell back {[s['fell_back'] for s in s_stats]}")
+    tseq1, its1, worst1 = 0.0, [], 0.0
+    for r in range(n):
+        sl = slice(r * fb, (r + 1) * fb)
+        s1, st1 = ctx.bsm_cg_solve(d64, U, U, bsm.solver_params(kappas[r], 1e-10, schur=True), b[0:fb], xs[sl],
+                                   check=False)
+        tseq1 += st1["seconds"]
+        its1.append(st1["iters"])
+        worst1 = max(worst1, rel_diff(ctx, d64, xb[sl], xs[sl]))
+    log(f"  sequential plain FP64 on the same source: {tseq1:.3f} s")
+    shifted = {"workload": "24^3x48 SU(4) adjoint, Haar links, one Gaussian source, kappa linspace(0.10, 0.125, 16)",
+               "method": "BiCG with the gamma5 shadow sequence on sigma - H, all kappas as shifts of the largest; "
+                         "FP64; members retire at a 0.3e-10 residual estimate, FP64 true residual decides",
+               "status": s_st, "seconds": round(t_shift, 4), "iters": [s["iters"] for s in s_stats],
+               "fell_back": [s["fell_back"] for s in s_stats],
+               "max_true_rel_res": max(s["true_rel_res"] for s in s_stats),
+               "sequential_plain_f64": dict(seconds=round(tseq1, 4), iters=its1),
+               "speedup_vs_plain_f64": round(tseq1 / t_shift, 3) if t_shift > 0 else None,
+               "max_x_rel_diff_vs_plain": worst1}
+    cond = {}
+    for kk in (kappas[-1], kappas[0]):
+        log(f"cfg4 conditioning kappa {kk:.4f} ...")
+        cond[f"kappa_{kk:.4f}"] = conditioning(ctx, d64, U, kk, b[0:fb], Uf_host, lat.dims)
     out = {"workload": "24^3x48 SU(4) adjoint (d_R=15, real links), Haar links, 16 RHS, "
                        "kappa linspace(0.10, 0.125, 16), Schur CG to 1e-10 each",
            "kappas": kappas,
@@ -284,7 +595,10 @@ def bench_cfg4(bsm, gen):
                            reliable_updates=[s["reliable_updates"] for s in stats]),
            "sequential_plain_f64": dict(seconds=round(tseq, 4), iters=its),
            "speedup_vs_plain_f64": round(tseq / tb, 3) if tb > 0 else None,
-           "max_x_rel_diff_vs_plain": worst}
+           "max_x_rel_diff_vs_plain": worst,
+           "block_hop": block_hop,
+           "shifted_family": shifted,
+           "conditioning": cond}
     ctx.close()
     torch.cuda.empty_cache()
     return out
@@ -297,7 +611,8 @@ def bench_cfg5(bsm, gen, train_steps=300, n_pairs=32, channels=8, large_dims=Tru
     lat = gen.config_lattice(5)
     kappa = c["kappa"]
     log("cfg5: generating 16^3x32 SU(3) links, sources and training solutions ...")
-    Uf = bsm.to_device_c128(gen.config_links(5, lat))
+    Uf_host = gen.config_links(5, lat)
+    Uf = bsm.to_device_c128(Uf_host)
     ctx = bsm.Context(lat.dims, lat.bc)
     d64 = bsm.desc(3, "fund", "f64")
     d32 = bsm.desc(3, "fund", "f32")
@@ -344,6 +659,10 @@ def bench_cfg5(bsm, gen, train_steps=300, n_pairs=32, channels=8, large_dims=Tru
     _fgcr_rows(bsm, ctx, d32, d64, U32, U64, kappa, channels, net, b, x, x0, base, rows, "cfg5")
     apply_us = _time_net_apply(bsm, ctx, d32, U32, channels, net, b)
     gain = base - rows["fgcr_net"]["seconds"]
+    snap = _cfg5_snapshot_training(bsm, gen, ctx, lat, d32, d64, U32, U64, kappa, channels, b, x, x0, base,
+                                   train_steps)
+    log("cfg5 conditioning ...")
+    cond = conditioning(ctx, d64, U64, kappa, b, Uf_host, lat.dims)
     ctx.close()
     torch.cuda.empty_cache()
     large = bench_cfg5_large(bsm, gen, net, channels, kappa) if large_dims else None
@@ -355,8 +674,73 @@ def bench_cfg5(bsm, gen, train_steps=300, n_pairs=32, channels=8, large_dims=Tru
            "solves": rows,
            "net_apply_us": apply_us,
            "break_even_solves": (round(t_train / gain, 1) if gain > 0 else None),
+           "trained_on_cg_snapshots": snap,
+           "conditioning": cond,
            "same_net_on_32x32x32x64": large}
     return out
+
+
+def _val_loss(ctx, d32, U32, channels, net, r_pairs, e_pairs, idx):
+    """mean |M(r) - e|^2 / |e|^2 over the pairs idx (library calls)"""
+    import torch
+    f32 = ctx.spinor_bytes(d32, 2, 1) // 4
+    z = torch.zeros(f32, dtype=torch.float32, device="cuda")
+    tot = 0.0
+    for k in idx:
+        r, e = r_pairs[k * f32:(k + 1) * f32], e_pairs[k * f32:(k + 1) * f32]
+        ctx.bsm_precond_apply(d32, U32, channels, net, r, z)
+        ctx.bsm_vec_axpby(d32, 2, 1.0, z, -1.0, e, z)
+        tot += ctx.bsm_vec_dot(d32, 2, z) / ctx.bsm_vec_dot(d32, 2, e)
+    return tot / len(idx)
+
+
+def _cfg5_snapshot_training(bsm, gen, ctx, lat, d32, d64, U32, U64, kappa, channels, b, x, x0, base, train_steps,
+                            n_solves=100, snaps=tuple(range(0, 80, 4))):
+    """The training set as the workload states it: 2000 residual/error pairs
+    from the library's own plain FP64 CG solves (100 solutions x*, 20
+    snapshots k = 0, 4, ..., 76 each: e = x* - x_k, r = D e), 1800 for
+    training and the last 200 (10 fresh solutions) for validation; the same
+    Adam schedule as the 32-pair net; then FGCR(6) with this net."""
+    import torch
+    n = n_solves * len(snaps)
+    f32 = ctx.spinor_bytes(d32, 2, 1)
+    log(f"cfg5 snapshot training: {n} pairs from {n_solves} CG solves x {len(snaps)} snapshots ...")
+    xs = ctx.new_spinor(d64, 2, n_solves)
+    xs_c = np.stack([gen.gaussian_spinor(lat, 3, gen.SEED_TRAIN + 5 + 1000 * (100 + s)) for s in range(n_solves)])
+    ctx.bsm_pack_spinor(d64, bsm.to_device_c128(xs_c), xs, n_solves)
+    del xs_c
+    r_pairs = torch.zeros(n * f32 // 4, dtype=torch.float32, device="cuda")
+    e_pairs = torch.zeros_like(r_pairs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.bsm_precond_pairs(d64, U64, kappa, n_solves, xs, list(snaps), r_pairs, e_pairs)
+    t_pairs = time.perf_counter() - t0
+    del xs
+    W1, W2 = _init_weights(channels, gen.SEED_NET + 5)
+    net = torch.cat([torch.from_numpy(W1.astype(np.complex64).ravel()),
+                     torch.from_numpy(W2.astype(np.complex64).ravel())]).cuda()
+    adam = torch.zeros(4 * net.numel(), dtype=torch.float32, device="cuda")
+    n_train = n - 200
+    t0 = time.perf_counter()
+    losses = ctx.bsm_precond_train(d32, U32, channels, net, adam, r_pairs, e_pairs, n_train,
+                                   bsm.train_params(lr=5e-3, batch=4, steps=train_steps, seed=gen.SEED_TRAIN + 6))
+    t_train = time.perf_counter() - t0
+    val = _val_loss(ctx, d32, U32, channels, net, r_pairs, e_pairs, range(n_train, n))
+    log(f"  pairs {t_pairs:.2f} s, training {t_train:.2f} s, loss {losses[0]:.4f} -> "
+        f"{np.mean(losses[-20:]):.4f}, validation {val:.4f}")
+    rows = {}
+    prm = bsm.solver_params(kappa, 1e-10, max_iter=20000, restart=6)
+    s, st = warm_solve(lambda: ctx.bsm_fgcr_solve(d32, U32, U64, prm, channels, net, b, x, check=False))
+    rows["fgcr_net"] = solve_row(s, st, base)
+    rows["fgcr_net"].update(fell_back=st["fell_back"], precond_applies=st["precond_applies"],
+                            x_rel_diff_vs_plain=rel_diff(ctx, d64, x, x0))
+    log(f"  {rows['fgcr_net']}")
+    del r_pairs, e_pairs
+    torch.cuda.empty_cache()
+    return {"pairs": n, "train_pairs": n_train, "validation_pairs": 200, "snapshot_iters": list(snaps),
+            "solves": n_solves, "pairs_seconds": round(t_pairs, 3), "training_seconds": round(t_train, 3),
+            "steps": train_steps, "loss_first": losses[0], "loss_last20": float(np.mean(losses[-20:])),
+            "validation_loss": val, "fgcr": rows}
 
 
 def bench_cfg5_large(bsm, gen, net, channels, kappa):
@@ -519,6 +903,98 @@ def cpu_baseline(lat, Uf, psi, bytes_per_hop, min_seconds=10.0):
                       f"algorithmic bytes per hop as the GPU FP32 figure, so the ratio is a ratio of hop rates"}
 
 
+def _oracle_cfg2_job(path, threads):
+    """Child process of the CPU leg: the oracle's FP64 Schur CG on the
+    headline workload (32^3 x 64 SU(3), kappa 0.13) to a 1e-10 true residual,
+    timed, then continued from that iterate to a true residual <= 1e-13 (the
+    reference every GPU solution of that workload is compared with).  Writes
+    the solution and a JSON summary next to path."""
+    import json as _json
+    import oracle
+    from paper_1401_3733_amd import inputs as gen
+    oracle.set_num_threads(threads)
+    lat = gen.config_lattice(2)
+    kappa = gen.CONFIGS[2]["kappa"]
+    U = oracle.represent(gen.config_links(2, lat), "fund")
+    b = gen.config_source(2, 3, lat)
+    t0 = time.perf_counter()
+    x, info = oracle.solve(lat, U, kappa, b, tol=1e-10, schur=True)
+    t10 = time.perf_counter() - t0
+    # continue the Schur recurrence from the even part of x: bhat_e = b_e +
+    # kappa H_eo b_o, then rebuild x_o = b_o + kappa H_oe x_e
+    odd = oracle.parity_mask(lat).astype(bool)
+    bh = b + kappa * oracle.hop(lat, U, b, parity=0)
+    bh[odd] = 0
+    xe = x.copy()
+    xe[odd] = 0
+    res, extra, trig = info["true_res"], 0, 1e-13
+    t1 = time.perf_counter()
+    while res > 1e-13 and extra < 4000 and trig > 1e-17:
+        xe, it, _ = oracle.cgnr_raw(lat, U, kappa, bh, x0=xe, tol=trig, schur=True)
+        extra += it
+        x = xe.copy()
+        x[odd] = (b + kappa * oracle.hop(lat, U, xe, parity=1))[odd]
+        res = oracle.true_residual(lat, U, kappa, b, x)
+        trig *= 0.3
+    np.save(path, x)
+    with open(path + ".json", "w") as f:
+        _json.dump({"tts_1e-10_seconds": round(t10, 3), "iters_1e-10": info["iters"],
+                    "true_rel_res_1e-10": info["true_res"], "reference_true_rel_res": res,
+                    "reference_extra_iters": extra, "reference_extra_seconds": round(time.perf_counter() - t1, 3),
+                    "threads": oracle.num_threads()}, f)
+
+
+def start_oracle_reference(threads):
+    """Start the oracle's headline-workload solve in a child process (it runs
+    while the GPU sections run in this one); returns (process, path)."""
+    import multiprocessing as mp
+    import tempfile
+    path = os.path.join(tempfile.mkdtemp(prefix="bsm_oracle_"), "x_ref.npy")
+    proc = mp.get_context("spawn").Process(target=_oracle_cfg2_job, args=(path, threads), daemon=True)
+    proc.start()
+    return proc, path
+
+
+def finish_oracle_reference(proc, path, solutions, threads):
+    """Wait for the child, then compare each kept GPU solution of the headline
+    workload with the oracle's reference solution."""
+    import shutil
+    proc.join()
+    if proc.exitcode != 0 or not os.path.exists(path + ".json"):
+        return {"error": f"oracle reference job failed (exit code {proc.exitcode})"}
+    with open(path + ".json") as f:
+        out = json.load(f)
+    xr = np.load(path)
+    nr = np.linalg.norm(xr)
+    out["x_rel_err_vs_oracle"] = {k: float(np.linalg.norm(v - xr) / nr) for k, v in solutions.items()}
+    out["workload"] = ("32^3x64 SU(3) fund, exp(0.3iH) links, kappa 0.13, oracle FP64 Schur CG; timed on "
+                       f"{threads} host threads while the GPU sections ran in the parent process")
+    shutil.rmtree(os.path.dirname(path), ignore_errors=True)
+    return out
+
+
+def cpu_cfg1(solution):
+    """The oracle's FP64 CG on the full D^dag D for the 4^4 SU(2) workload:
+    time-to-solution at 1e-10 and the GPU solution against the oracle's
+    solution continued to 1e-13."""
+    import oracle
+    from paper_1401_3733_amd import inputs as gen
+    lat = gen.config_lattice(1)
+    U = oracle.represent(gen.config_links(1, lat), "fund")
+    b = gen.config_source(1, 2, lat)
+    k = gen.CONFIGS[1]["kappa"]
+    t0 = time.perf_counter()
+    _, info = oracle.solve(lat, U, k, b, tol=1e-10, schur=False)
+    t = time.perf_counter() - t0
+    xr, info13 = oracle.solve(lat, U, k, b, tol=1e-13, schur=False)
+    out = {"seconds": round(t, 5), "iters": info["iters"], "true_rel_res": info["true_res"],
+           "reference_true_rel_res": info13["true_res"], "cores": oracle.num_threads(),
+           "workload": "4^4 SU(2) fund, Haar links, kappa 0.12, oracle FP64 CG on D^dag D to 1e-10"}
+    if solution is not None:
+        out["x_rel_err_vs_oracle"] = float(np.linalg.norm(solution - xr) / np.linalg.norm(xr))
+    return out
+
+
 def cpu_cg_small():
     """The oracle's FP64 Schur CG to a 1e-10 true residual on the 16^3 x 32
     SU(3) workload (kappa 0.1335, the same links and source as the GPU solves
@@ -602,10 +1078,20 @@ def main():
         sys.exit(2)
     sections = set(s for s in args.sections.split(",") if s)
     if args.no_cg:
-        sections -= {"cg", "cfg3", "cfg4", "cfg5"}
+        sections -= {"cg", "cfg1", "cfg3", "cfg4", "cfg5"}
     if args.no_cpu:
         sections.discard("cpu")
     sections.add("hop")
+
+    cores = len(os.sched_getaffinity(0))
+    # CPU leg, first part: the oracle's solve of the headline workload runs in
+    # a child process on all but two host cores while the GPU sections run
+    # (started before this process touches the GPU)
+    oracle_job = None
+    if "cpu" in sections and "cg" in sections:
+        oracle_job = start_oracle_reference(max(1, cores - 2))
+        log(f"oracle reference solve of the headline workload started on {max(1, cores - 2)} threads")
+    keep = {} if oracle_job is not None else None
 
     import torch
     from paper_1401_3733_amd import bsm
@@ -636,13 +1122,15 @@ def main():
         log(f"calibration: {args.copy_calib} copies of 1 GiB")
         del src, dst
     res = bench_hop(ctx, lat, Uf_dev, psi_dev, args, bsm)
-    cg = bench_cg_cfg2(ctx, lat, Uf_dev, psi_dev, kappa, bsm) if "cg" in sections else None
+    cg = bench_cg_cfg2(ctx, lat, Uf_dev, psi_dev, kappa, bsm, Uf, keep) if "cg" in sections else None
     del Uf_dev, psi_dev
     ctx.close()
     torch.cuda.empty_cache()
     copy_gbs, read_gbs = measure_copy(bsm)
     log(f"achievable: copy {copy_gbs:.0f} GB/s (1 GiB read + 1 GiB written), read {read_gbs:.0f} GB/s")
     forms = {}
+    keep1 = {}
+    cfg1 = bench_cfg1(bsm, gen, keep1) if "cfg1" in sections else None
     if "cfg3" in sections:
         forms["mixed_precision"] = bench_cfg3(bsm, gen)
     if "cfg4" in sections:
@@ -652,6 +1140,13 @@ def main():
     tasks = bench_tasks(bsm, gen, lat, Uf, args.task_seconds) if "tasks" in sections else None
 
     cpu = None
+    ref = None
+    if oracle_job is not None:
+        # the rest of the CPU leg times the oracle on every core: wait first
+        log("waiting for the oracle reference solve of the headline workload ...")
+        ref = finish_oracle_reference(*oracle_job, keep, max(1, cores - 2))
+        log(f"  {ref}")
+        keep = None
     if "cpu" in sections:
         log("CPU oracle baseline ...")
         cpu = cpu_baseline(lat, Uf, psi, res["f32"]["bytes"])
@@ -659,6 +1154,11 @@ def main():
         log("CPU oracle CG on 16^3x32 ...")
         cpu["cg_tts_16x16x16x32"] = cpu_cg_small()
         log(f"  {cpu['cg_tts_16x16x16x32']}")
+        log("CPU oracle CG on 4^4 ...")
+        cpu["cg_tts_4x4x4x4"] = cpu_cfg1(keep1.get("cfg1"))
+        log(f"  {cpu['cg_tts_4x4x4x4']}")
+        if ref is not None:
+            cpu["cg_32x32x32x64"] = ref
 
     r32 = res["f32"]
     traffic, traffic_note = measured_traffic()
@@ -688,6 +1188,7 @@ def main():
             "gbs": round(res["f64"]["gbs"], 1), "us": round(res["f64"]["ms"] * 1e3, 2),
             "frac": round(res["f64"]["gbs"] / PEAK_HBM_GBS, 4), "plan": res["f64"]["plan"]},
         "cg": cg,
+        "cfg1": cfg1,
         "forms": forms or None,
         "paper_tasks": tasks,
         "cpu_baseline": cpu,

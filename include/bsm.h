@@ -70,6 +70,23 @@ typedef enum { BSM_REP_FUND = 0, BSM_REP_ADJ = 1, BSM_REP_SYM = 2, BSM_REP_ASYM 
  * binary16 (entries of a unitary matrix are bounded by 1, no scale). */
 typedef enum { BSM_F64 = 0, BSM_F32 = 1, BSM_F16S = 2 } bsm_prec;
 
+/* Flag ORed into bsm_field_desc.link_prec: the gauge field holds the
+ * fundamental N x N links U (the field content of Section II.A, 2 N^2 reals
+ * per link) instead of R(U), and every operator forms the representation on
+ * the fly inside the hop, applying R(U) (or R(U)^dag) to the projected half
+ * spinor without building the d_R x d_R matrix: two-index S -> V S V^T, adjoint
+ * X -> V X V^dag (V = U or U^dag).  bsm_gauge_represent then stores U itself
+ * (in the precision of the low bits), bsm_gauge_bytes sizes it and
+ * bsm_unpack_gauge returns [V][4][N][N].  Operators with these links:
+ * sym N = 2, 3, 4; asym N = 3, 4; adj N = 2, 3, 4 with F32 spinors and F32
+ * links or F16S spinors and F32 or F16S links; F64 spinors and F64 links for
+ * d_R <= 6 (BSM_ERR_UNSUPPORTED otherwise).  Accepted by bsm_dslash_apply,
+ * bsm_dslash_eo, the plan and autotune calls and bsm_cg_solve (PLAIN and
+ * MIXED; U_rep64 then holds F64 fundamental links too); refused
+ * (BSM_ERR_ARG) by the block, network, batched and benchmark-task calls.
+ * For fundamental fermions the flag changes nothing. */
+#define BSM_LINKS_FUNDAMENTAL 16
+
 typedef struct {
     int32_t L[4];
     int32_t bc[4];
@@ -212,6 +229,7 @@ typedef enum {
     BSM_SOLVER_MIXED = 1,       /* reliable-update CG, inner precision desc->prec */
     BSM_SOLVER_BATCHED = 2,     /* n_rhs right-hand sides with their own kappas (bsm_batched_solve) */
     BSM_SOLVER_FGCR_NET = 3,    /* flexible GCR with the network preconditioner (bsm_fgcr_solve) */
+    BSM_SOLVER_SHIFTED = 4,     /* one source, n_rhs kappas in one Krylov space (bsm_shifted_solve) */
 } bsm_solver_variant;
 
 typedef struct {
@@ -226,8 +244,8 @@ typedef struct {
     int32_t precond_layers; /* FGCR: 0 applies the network as one collapsed operator
                                (bsm_precond_apply_collapsed) where d_R <= 3; 1 always
                                applies it layer by layer in FP32 (bsm_precond_apply) */
-    int32_t n_rhs;         /* BATCHED: number of right-hand sides */
-    const double *kappas;  /* BATCHED: host array of n_rhs kappas (kappa is then ignored) */
+    int32_t n_rhs;         /* BATCHED, SHIFTED: number of right-hand sides / kappas */
+    const double *kappas;  /* BATCHED, SHIFTED: host array of n_rhs kappas (kappa is then ignored) */
     int32_t channels;      /* FGCR_NET: network channels */
     const void *net;       /* FGCR_NET: network weights (device, bsm_net_bytes), NULL: M = 1 */
 } bsm_solver_params;
@@ -244,11 +262,11 @@ typedef struct {
 } bsm_solver_stats;
 
 /* Solve D x = b (Section II.B: the operator is inverted by conjugate
- * gradients; here CG on the normal equations).  params->variant BATCHED
- * and FGCR_NET forward to bsm_batched_solve (n_rhs, kappas from params;
- * stats an array of n_rhs) and bsm_fgcr_solve (channels, net from params),
- * with the arguments and behaviour documented there; the rest of this
- * comment is about PLAIN and MIXED.  b and x are full internal
+ * gradients; here CG on the normal equations).  params->variant BATCHED,
+ * SHIFTED and FGCR_NET forward to bsm_batched_solve and bsm_shifted_solve
+ * (n_rhs, kappas from params; stats an array of n_rhs) and bsm_fgcr_solve
+ * (channels, net from params), with the arguments and behaviour documented
+ * there; the rest of this comment is about PLAIN and MIXED.  b and x are full internal
  * fields in F64 (desc->prec is the inner precision for MIXED and must be F64
  * for PLAIN); U_rep holds links in desc->link_prec for the inner operator and
  * U_rep64 the FP64 links used for every true residual (may equal U_rep when
@@ -417,6 +435,25 @@ bsm_status bsm_get_block_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t *
  * Synchronous. */
 bsm_status bsm_batched_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep64,
                              const bsm_solver_params *params, int32_t n_rhs, const double *kappas,
+                             const void *b, void *x, bsm_solver_stats *stats, void *stream);
+
+/* Solve D(kappa_i) x_i = b for n_kappa (1 ... 32) kappas and ONE source b
+ * (Section II.B's inversion for a family of masses) in one Krylov space:
+ * D(kappa) = kappa (1/kappa - H), so the systems differ by multiples of the
+ * identity.  The seed is the largest kappa; BiCG with the gamma5 shadow
+ * sequence (valid since D^dag = gamma5 D gamma5; one operator application
+ * per iteration, real coefficients) carries every shifted member along with
+ * colinear residuals; a member retires when its residual estimate is below
+ * params->delta * tol (delta <= 0: 0.3), then its FP64 full-lattice true
+ * residual decides, and a member that misses tol (or a breakdown) is
+ * finished by plain FP64 Schur CG (stats.fell_back; max_iter bounds the
+ * shared iteration and each fallback solve).  desc: F64 spinors, F64 links (stored, or fundamental
+ * with BSM_LINKS_FUNDAMENTAL); b: full FP64 field; x: n_kappa consecutive
+ * full FP64 fields, overwritten; stats: host array of n_kappa (iters =
+ * shared iterations until the member retired, plus fallback iterations).
+ * Scratch: the context's, (3 + n_kappa) full FP64 fields.  Synchronous. */
+bsm_status bsm_shifted_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep64,
+                             const bsm_solver_params *params, int32_t n_kappa, const double *kappas,
                              const void *b, void *x, bsm_solver_stats *stats, void *stream);
 
 /* -------------------------------------------------------- benchmark tasks

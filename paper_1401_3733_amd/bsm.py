@@ -21,7 +21,7 @@ OK, ERR_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_NOMEM, ERR_NOT_CONVERGED, ERR_NONFINI
 REP = {"fund": 0, "adj": 1, "sym": 2, "asym": 3}
 F64, F32, F16S = 0, 1, 2
 PREC = {"f64": F64, "f32": F32, "f16s": F16S}
-SOLVER_PLAIN, SOLVER_MIXED, SOLVER_BATCHED, SOLVER_FGCR_NET = 0, 1, 2, 3
+SOLVER_PLAIN, SOLVER_MIXED, SOLVER_BATCHED, SOLVER_FGCR_NET, SOLVER_SHIFTED = 0, 1, 2, 3, 4
 TASK = {"vector": 0, "matvec": 1, "dphi": 2}
 
 
@@ -120,6 +120,8 @@ _SIGS = {
                                     C.POINTER(C.c_int32), _vp, _vp, _vp]),
     "bsm_fgcr_solve": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, _vp, C.POINTER(SolverParams), C.c_int32, _vp,
                                  _vp, _vp, C.POINTER(SolverStats), _vp]),
+    "bsm_shifted_solve": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.POINTER(SolverParams), C.c_int32,
+                                    C.POINTER(C.c_double), _vp, _vp, C.POINTER(SolverStats), _vp]),
     "bsm_cg_solve": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, _vp, C.POINTER(SolverParams), _vp, _vp,
                                C.POINTER(SolverStats), _vp]),
     "bsm_link_matvec": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, _vp, _vp, _vp]),
@@ -170,12 +172,19 @@ def _stream(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
-def desc(N: int, rep: str, prec="f64", link_prec=None) -> FieldDesc:
+LINKS_FUNDAMENTAL = 16
+
+
+def desc(N: int, rep: str, prec="f64", link_prec=None, fundamental_links=False) -> FieldDesc:
+    """fundamental_links: the gauge field holds U and the operators form the
+    representation on the fly (BSM_LINKS_FUNDAMENTAL)"""
     r = REP[rep] if isinstance(rep, str) else int(rep)
     p = PREC[prec] if isinstance(prec, str) else int(prec)
     lp = p if link_prec is None else (PREC[link_prec] if isinstance(link_prec, str) else int(link_prec))
     if link_prec is None and p == F16S:
         lp = F32
+    if fundamental_links:
+        lp |= LINKS_FUNDAMENTAL
     return FieldDesc(N, r, bsm_rep_dim(N, r), p, lp)
 
 
@@ -336,15 +345,24 @@ class Context:
             _check(status, "bsm_batched_solve")
         return status, [s.as_dict() for s in st]
 
+    def bsm_shifted_solve(self, d, U_rep64, params: SolverParams, kappas, b, x, stream=None, check=True):
+        n = len(kappas)
+        st = (SolverStats * n)()
+        status = lib().bsm_shifted_solve(self.handle, C.byref(d), _ptr(U_rep64), C.byref(params), n,
+                                         _darr(kappas), _ptr(b), _ptr(x), st, _stream(stream))
+        if check and status != OK:
+            _check(status, "bsm_shifted_solve")
+        return status, [s.as_dict() for s in st]
+
     def bsm_cg_solve(self, d, U_rep, U_rep64, params: SolverParams, b, x, stream=None, check=True):
-        """stats: one dict, or a list of n_rhs dicts for the BATCHED variant"""
-        n = params.n_rhs if params.variant == SOLVER_BATCHED else 1
+        """stats: one dict, or a list of n_rhs dicts for the BATCHED and SHIFTED variants"""
+        n = params.n_rhs if params.variant in (SOLVER_BATCHED, SOLVER_SHIFTED) else 1
         st = (SolverStats * max(1, n))()
         status = lib().bsm_cg_solve(self.handle, C.byref(d), _ptr(U_rep), _ptr(U_rep64), C.byref(params),
                                     _ptr(b), _ptr(x), st, _stream(stream))
         if check and status not in (OK,):
             _check(status, "bsm_cg_solve")
-        if params.variant == SOLVER_BATCHED:
+        if params.variant in (SOLVER_BATCHED, SOLVER_SHIFTED):
             return status, [s.as_dict() for s in st]
         return status, st[0].as_dict()
 

@@ -72,20 +72,55 @@ bsm_status ctx_solver_stream(bsm_ctx ctx, hipStream_t *out) {
 
 int hop_blocks(const Geom &g) { return (g.Vh + 255) / 256; }
 
-static bool plan_fits(const Geom &g, const HopPlan &p, int d) {
+static bool plan_fits(const Geom &g, const HopPlan &p, int d, bool otf = false) {
     if (p.order == 0 || p.order == 2) return true;
-    if (p.order == 3 && d > kColMaxD) return false;
+    if (p.order == 3 && (d > kColMaxD || otf)) return false;
     int64_t S3 = (int64_t)g.Vh / g.L[0];
     if (p.order == 4) return S3 % (256 * kXcds) == 0;
     return p.tchunk >= 1 && S3 % 256 == 0 && g.L[0] % p.tchunk == 0;
 }
 
+static int plan_lp(int link_prec) { return link_base(link_prec) % 3 + (link_is_otf(link_prec) ? 3 : 0); }
+
+static HopPlan &plan_slot(bsm_ctx ctx, int d, bool real, int prec, int link_prec) {
+    const bool adj = real || (link_rn(link_prec) >> 4) == BSM_REP_ADJ;
+    return ctx->plans[d & 15][adj ? 1 : 0][prec % 3][plan_lp(link_prec)];
+}
+
 void apply_plan(bsm_ctx ctx, int d, bool real, int prec, int link_prec, HopArgs &a) {
-    HopPlan p = ctx->plans[d & 15][real ? 1 : 0][prec % 3][link_prec % 3];
-    if (!plan_fits(ctx->g, p, d)) p = HopPlan{};
+    const bool otf = link_is_otf(link_prec);
+    HopPlan p = plan_slot(ctx, d, real, prec, link_prec);
+    if (!plan_fits(ctx->g, p, d, otf)) p = HopPlan{};
     a.order = p.order;
     a.tchunk = p.tchunk;
-    a.wide = hop_wide_of(d, prec);
+    a.wide = otf ? 0 : hop_wide_of(d, prec);
+}
+
+// on-the-fly instances (hop_otf.hip)
+static bsm_status launch_hop_otf(const Geom &g, int rn, int prec, int lp, const HopArgs &a, hipStream_t st) {
+#define BSM_OTF_CASE(SP, LP, REP, N)                                              \
+    if (prec == SP && lp == LP && rn == otf_rn(REP, N))                            \
+        return hop_run_otf<SP, LP, otf_rn(REP, N)>(g, a, st);
+#define BSM_OTF_CASES_LOWP(REP, N)             \
+    BSM_OTF_CASE(BSM_F32, BSM_F32, REP, N)      \
+    BSM_OTF_CASE(BSM_F16S, BSM_F32, REP, N)     \
+    BSM_OTF_CASE(BSM_F16S, BSM_F16S, REP, N)
+    BSM_OTF_CASES_LOWP(BSM_REP_SYM, 2)
+    BSM_OTF_CASES_LOWP(BSM_REP_SYM, 3)
+    BSM_OTF_CASES_LOWP(BSM_REP_SYM, 4)
+    BSM_OTF_CASES_LOWP(BSM_REP_ASYM, 3)
+    BSM_OTF_CASES_LOWP(BSM_REP_ASYM, 4)
+    BSM_OTF_CASES_LOWP(BSM_REP_ADJ, 2)
+    BSM_OTF_CASES_LOWP(BSM_REP_ADJ, 3)
+    BSM_OTF_CASES_LOWP(BSM_REP_ADJ, 4)
+    BSM_OTF_CASE(BSM_F64, BSM_F64, BSM_REP_SYM, 2)
+    BSM_OTF_CASE(BSM_F64, BSM_F64, BSM_REP_SYM, 3)
+    BSM_OTF_CASE(BSM_F64, BSM_F64, BSM_REP_ASYM, 3)
+    BSM_OTF_CASE(BSM_F64, BSM_F64, BSM_REP_ASYM, 4)
+    BSM_OTF_CASE(BSM_F64, BSM_F64, BSM_REP_ADJ, 2)
+#undef BSM_OTF_CASES_LOWP
+#undef BSM_OTF_CASE
+    return fail(BSM_ERR_UNSUPPORTED, "no on-the-fly operator for this representation, N and precision pair");
 }
 
 template <int SP, int LP>
@@ -104,6 +139,10 @@ bsm_status launch_hop(const Geom &g, int d, bool real, int prec, int link_prec, 
     // colour split is used wherever it applies; with norms the caller sized
     // the partials for a.wide (apply_plan and hop_grid) and that is kept.
     HopArgs a = a_in;
+    if (link_is_otf(link_prec)) {
+        a.wide = 0;
+        return launch_hop_otf(g, link_rn(link_prec), prec, link_base(link_prec), a, st);
+    }
     if (!a.norm_partials) a.wide = hop_wide_of(d, prec);
     if (prec == BSM_F64 && link_prec == BSM_F64)
         return dispatch_d<HopSel<BSM_F64, BSM_F64>::ByD>(d, g, real, a, st);
@@ -139,7 +178,15 @@ static bsm_status check_desc(const bsm_field_desc *d) {
                                      std::to_string(d->N) + ", rep) = " + std::to_string(dim));
     if (d->d_R < 2 || d->d_R > 15) return fail(BSM_ERR_ARG, "d_R must be in [2, 15]");
     if (d->prec < 0 || d->prec > 2) return fail(BSM_ERR_ARG, "bad spinor precision");
-    if (d->link_prec < 0 || d->link_prec > 2) return fail(BSM_ERR_ARG, "bad link precision");
+    const int lb = d->link_prec & ~BSM_LINKS_FUNDAMENTAL;
+    if (lb < 0 || lb > 2) return fail(BSM_ERR_ARG, "bad link precision");
+    return BSM_OK;
+}
+
+// calls that need links stored in the representation
+static bsm_status check_stored_links(const bsm_field_desc *d) {
+    if (link_is_otf(link_code(d)))
+        return fail(BSM_ERR_ARG, "this call needs links stored in the representation (no BSM_LINKS_FUNDAMENTAL)");
     return BSM_OK;
 }
 
@@ -259,8 +306,7 @@ void bsm_ctx_destroy(bsm_ctx c) {
 
 size_t bsm_gauge_bytes(bsm_ctx ctx, const bsm_field_desc *desc) {
     if (check_ctx(ctx) != BSM_OK || check_desc(desc) != BSM_OK) return 0;
-    bool real = desc->rep == BSM_REP_ADJ;
-    return 8 * link_block_bytes(desc->link_prec, real, desc->d_R, ctx->g.Vh_pad);
+    return 8 * link_block_bytes(link_base(desc->link_prec), link_real(desc), link_dim(desc), ctx->g.Vh_pad);
 }
 
 size_t bsm_spinor_bytes(bsm_ctx ctx, const bsm_field_desc *desc, int32_t nparity, int32_t n_rhs) {
@@ -301,7 +347,10 @@ bsm_status bsm_gauge_represent(bsm_ctx ctx, const bsm_field_desc *desc, const vo
     if (!aligned16(U_fund) || !aligned16(U_rep)) return fail(BSM_ERR_ARG, "fields must be 16-byte aligned");
     if (desc->rep != BSM_REP_FUND && desc->N > 6)
         return fail(BSM_ERR_ARG, "two-index and adjoint representations need N <= 6 for d_R <= 15");
-    return launch_represent(ctx->g, desc->N, desc->rep, desc->d_R, desc->link_prec, U_fund, U_rep,
+    if (link_is_otf(link_code(desc)))   // fundamental storage: U itself
+        return launch_represent(ctx->g, desc->N, BSM_REP_FUND, desc->N, link_base(desc->link_prec), U_fund,
+                                U_rep, (hipStream_t)stream);
+    return launch_represent(ctx->g, desc->N, desc->rep, desc->d_R, link_base(desc->link_prec), U_fund, U_rep,
                             (hipStream_t)stream);
 }
 
@@ -310,7 +359,7 @@ bsm_status bsm_unpack_gauge(bsm_ctx ctx, const bsm_field_desc *desc, const void 
     CHECK(check_ctx(ctx));
     CHECK(check_desc(desc));
     if (!U_rep || !canon) return fail(BSM_ERR_ARG, "null field pointer");
-    return launch_unpack_gauge(ctx->g, desc->d_R, desc->rep == BSM_REP_ADJ, desc->link_prec, U_rep,
+    return launch_unpack_gauge(ctx->g, link_dim(desc), link_real(desc), link_base(desc->link_prec), U_rep,
                                canon, (hipStream_t)stream);
 }
 
@@ -340,8 +389,8 @@ bsm_status bsm_dslash_apply(bsm_ctx ctx, const bsm_field_desc *desc, const void 
     a.p0 = 0;
     a.np = 2;
     a.norm_partials = nullptr;
-    apply_plan(ctx, desc->d_R, desc->rep == BSM_REP_ADJ, desc->prec, desc->link_prec, a);
-    return launch_hop(ctx->g, desc->d_R, desc->rep == BSM_REP_ADJ, desc->prec, desc->link_prec, a,
+    apply_plan(ctx, desc->d_R, link_real(desc), desc->prec, link_code(desc), a);
+    return launch_hop(ctx->g, desc->d_R, link_real(desc), desc->prec, link_code(desc), a,
                       (hipStream_t)stream);
 }
 
@@ -369,8 +418,8 @@ bsm_status bsm_dslash_eo(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_
     h.p0 = out_parity;
     h.np = 1;
     h.norm_partials = nullptr;
-    apply_plan(ctx, desc->d_R, desc->rep == BSM_REP_ADJ, desc->prec, desc->link_prec, h);
-    return launch_hop(ctx->g, desc->d_R, desc->rep == BSM_REP_ADJ, desc->prec, desc->link_prec, h,
+    apply_plan(ctx, desc->d_R, link_real(desc), desc->prec, link_code(desc), h);
+    return launch_hop(ctx->g, desc->d_R, link_real(desc), desc->prec, link_code(desc), h,
                       (hipStream_t)stream);
 }
 
@@ -408,6 +457,7 @@ bsm_status bsm_vec_dot(bsm_ctx ctx, const bsm_field_desc *desc, int32_t nparity,
 static bsm_status check_block(bsm_ctx ctx, const bsm_field_desc *desc) {
     CHECK(check_ctx(ctx));
     CHECK(check_desc(desc));
+    CHECK(check_stored_links(desc));
     if (desc->rep != BSM_REP_ADJ) return fail(BSM_ERR_UNSUPPORTED, "block fields need real (adjoint) links");
     return BSM_OK;
 }
@@ -523,8 +573,9 @@ bsm_status bsm_set_hop_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t ord
     p.order = order;
     p.tchunk = tchunk;
     if (order < 0 || order > 4) return fail(BSM_ERR_ARG, "order must be 0 ... 4");
-    if (!plan_fits(ctx->g, p, desc->d_R)) return fail(BSM_ERR_ARG, "plan does not tile this lattice");
-    ctx->plans[desc->d_R][desc->rep == BSM_REP_ADJ][desc->prec][desc->link_prec] = p;
+    if (!plan_fits(ctx->g, p, desc->d_R, link_is_otf(link_code(desc))))
+        return fail(BSM_ERR_ARG, "plan does not tile this lattice (or needs links stored in the representation)");
+    plan_slot(ctx, desc->d_R, link_real(desc), desc->prec, link_code(desc)) = p;
     return BSM_OK;
 }
 
@@ -534,7 +585,9 @@ bsm_status bsm_autotune(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_r
     if (!U_rep) return fail(BSM_ERR_ARG, "null gauge field");
     hipStream_t st = (hipStream_t)stream;
     const Geom &g = ctx->g;
-    const bool real = desc->rep == BSM_REP_ADJ;
+    const bool real = link_real(desc);
+    const int lc = link_code(desc);
+    const bool otf = link_is_otf(lc);
     size_t bb = spinor_block_bytes(desc->prec, desc->d_R, g.Vh_pad);
     void *work = nullptr;
     CHECK(ctx_work(ctx, 2 * bb, &work));
@@ -545,12 +598,12 @@ bsm_status bsm_autotune(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_r
         cand.push_back(p);
         p.order = 4;
         p.tchunk = 1;
-        if (plan_fits(g, p, desc->d_R)) cand.push_back(p);
+        if (plan_fits(g, p, desc->d_R, otf)) cand.push_back(p);
         for (int order : {1, 3})
             for (int tc : {2, 4, 8, 16, 32}) {
                 p.order = order;
                 p.tchunk = tc;
-                if (plan_fits(g, p, desc->d_R)) cand.push_back(p);
+                if (plan_fits(g, p, desc->d_R, otf)) cand.push_back(p);
             }
     }
     hipEvent_t e0, e1;
@@ -574,7 +627,7 @@ bsm_status bsm_autotune(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_r
             a.in[par] = (char *)work + (1 - par) * bb;
             a.out[par] = (char *)work + par * bb;
             if (rep == 0) BSM_HIP(hipEventRecord(e0, st));
-            CHECK(launch_hop(g, desc->d_R, real, desc->prec, desc->link_prec, a, st));
+            CHECK(launch_hop(g, desc->d_R, real, desc->prec, lc, a, st));
         }
         BSM_HIP(hipEventRecord(e1, st));
         BSM_HIP(hipEventSynchronize(e1));
@@ -588,7 +641,7 @@ bsm_status bsm_autotune(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_r
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     best.us = best_us;
-    ctx->plans[desc->d_R][real][desc->prec][desc->link_prec] = best;
+    plan_slot(ctx, desc->d_R, real, desc->prec, lc) = best;
     return BSM_OK;
 }
 
@@ -596,7 +649,7 @@ bsm_status bsm_get_hop_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t *or
                             float *us) {
     CHECK(check_ctx(ctx));
     CHECK(check_desc(desc));
-    const HopPlan &p = ctx->plans[desc->d_R][desc->rep == BSM_REP_ADJ][desc->prec][desc->link_prec];
+    const HopPlan &p = plan_slot(ctx, desc->d_R, link_real(desc), desc->prec, link_code(desc));
     if (order) *order = p.order;
     if (tchunk) *tchunk = p.tchunk;
     if (us) *us = p.us;

@@ -150,6 +150,27 @@ __device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nblk) {
     return (b % kXcds) * per + b / kXcds;
 }
 
+// ------------------------------------------------------------ link storage
+// Internal link code of a descriptor: the link precision (bits 0-1), and for
+// fundamental storage of a higher representation (BSM_LINKS_FUNDAMENTAL) the
+// flag kLinkOtf with (rep, N) in bits 8-11 and 12-15; the operator then forms
+// R(U) from U inside the hop.  Fundamental fermions with the flag are the
+// plain stored case.
+constexpr int kLinkOtf = BSM_LINKS_FUNDAMENTAL;
+__host__ __device__ inline int link_base(int lc) { return lc & 3; }
+__host__ __device__ inline bool link_is_otf(int lc) { return (lc & kLinkOtf) != 0; }
+// (rep, N) of an on-the-fly code as rep * 16 + N, 0 for stored links
+__host__ __device__ inline int link_rn(int lc) { return link_is_otf(lc) ? ((lc >> 8) & 15) * 16 + ((lc >> 12) & 15) : 0; }
+inline int link_code(const bsm_field_desc *d) {
+    const int base = d->link_prec & 3;
+    if (!(d->link_prec & kLinkOtf) || d->rep == BSM_REP_FUND) return base;
+    return base | kLinkOtf | (d->rep << 8) | (d->N << 12);
+}
+// dimension of the stored link matrices (N for on-the-fly codes)
+inline int link_dim(const bsm_field_desc *d) { return link_is_otf(link_code(d)) ? d->N : d->d_R; }
+// real stored links (adjoint representation stored as R(U))
+inline bool link_real(const bsm_field_desc *d) { return d->rep == BSM_REP_ADJ && !link_is_otf(link_code(d)); }
+
 // hop traversal plan, chosen per (d_R, link type, precisions) by bsm_autotune
 struct HopPlan {
     int order = 0, tchunk = 1;
@@ -185,7 +206,7 @@ struct bsm_ctx_s {
     void *pinned;
     size_t pinned_bytes;
     hipStream_t solver_stream;
-    bsm::HopPlan plans[16][2][3][3];   // [d_R][real][spinor prec][link prec]
+    bsm::HopPlan plans[16][2][3][6];   // [d_R][adjoint][spinor prec][link prec (+3: on the fly)]
     bsm::BlockPlan block_plans[16];     // [d_R]
 };
 

@@ -119,14 +119,14 @@ bsm_status true_residual_full(const Op &o, const char *b, char *x, char *tfull, 
         a.U = o.U; a.dagger = 0; a.p0 = 1; a.np = 1;
         a.in[1] = x; a.x[1] = b + bb64; a.out[1] = x + bb64;
         a.a = 1.0; a.b = o.kappa;
-        TRY(launch_hop(g, o.d, o.real, BSM_F64, BSM_F64, a, st));
+        TRY(launch_hop(g, o.d, o.real, BSM_F64, o.lprec, a, st));
     }
     HopArgs a{};
     a.U = o.U; a.dagger = 0; a.p0 = 0; a.np = 2;
     a.in[0] = x + bb64; a.in[1] = x; a.x[0] = x; a.x[1] = x + bb64;
     a.out[0] = tfull; a.out[1] = tfull + bb64;
     a.a = 1.0; a.b = -o.kappa;
-    TRY(launch_hop(g, o.d, o.real, BSM_F64, BSM_F64, a, st));
+    TRY(launch_hop(g, o.d, o.real, BSM_F64, o.lprec, a, st));
     Vec TF{tfull, BSM_F64}, B{(void *)b, BSM_F64};
     TRY(blas_axpby(g, o.d, 2, TF, -1.0, TF, 1.0, B, o.ctx->partials, st));
     const double rn = reduce_to_host(o.ctx, o.ctx->partials, blas_blocks(g, 2), st);
@@ -175,7 +175,7 @@ struct Solver {
             a.U = op64.U; a.dagger = 0; a.p0 = 0; a.np = 1;
             a.in[0] = b + bb64; a.x[0] = b; a.out[0] = bh;
             a.a = 1.0; a.b = kappa;
-            TRY(launch_hop(g, d, real, BSM_F64, BSM_F64, a, st));
+            TRY(launch_hop(g, d, real, BSM_F64, op64.lprec, a, st));
         } else {
             BSM_HIP(hipMemcpyAsync(bh, b, vec64, hipMemcpyDeviceToDevice, st));
         }
@@ -411,6 +411,8 @@ extern "C" bsm_status bsm_cg_solve(bsm_ctx ctx, const bsm_field_desc *desc, cons
                                    void *x, bsm_solver_stats *stats, void *stream) {
     if (prm && prm->variant == BSM_SOLVER_BATCHED)
         return bsm_batched_solve(ctx, desc, U_rep64, prm, prm->n_rhs, prm->kappas, b, x, stats, stream);
+    if (prm && prm->variant == BSM_SOLVER_SHIFTED)
+        return bsm_shifted_solve(ctx, desc, U_rep64, prm, prm->n_rhs, prm->kappas, b, x, stats, stream);
     if (prm && prm->variant == BSM_SOLVER_FGCR_NET)
         return bsm_fgcr_solve(ctx, desc, U_rep, U_rep64, prm, prm->channels, prm->net, b, x, stats, stream);
     if (!ctx || !desc || !prm || !b || !x || !stats || !U_rep || !U_rep64)
@@ -421,7 +423,9 @@ extern "C" bsm_status bsm_cg_solve(bsm_ctx ctx, const bsm_field_desc *desc, cons
     if (!(prm->tol > 0)) return fail(BSM_ERR_ARG, "tol must be > 0");
     if (prm->max_iter < 1) return fail(BSM_ERR_ARG, "max_iter must be >= 1");
     if (b == x) return fail(BSM_ERR_ARG, "b and x must differ");
-    if (prm->variant == BSM_SOLVER_PLAIN && (desc->prec != BSM_F64 || desc->link_prec != BSM_F64))
+    if ((desc->link_prec & ~BSM_LINKS_FUNDAMENTAL) < 0 || (desc->link_prec & ~BSM_LINKS_FUNDAMENTAL) > 2)
+        return fail(BSM_ERR_ARG, "bad link precision");
+    if (prm->variant == BSM_SOLVER_PLAIN && (desc->prec != BSM_F64 || link_base(desc->link_prec) != BSM_F64))
         return fail(BSM_ERR_ARG, "plain CG runs in FP64: desc prec and link_prec must be F64");
     if (prm->variant == BSM_SOLVER_MIXED && desc->prec == BSM_F64)
         return fail(BSM_ERR_ARG, "mixed CG needs an F32 or F16S inner precision");
@@ -434,7 +438,7 @@ extern "C" bsm_status bsm_cg_solve(bsm_ctx ctx, const bsm_field_desc *desc, cons
     S.st = (hipStream_t)stream;
     S.g = ctx->g;
     S.d = desc->d_R;
-    S.real = desc->rep == BSM_REP_ADJ;
+    S.real = link_real(desc);
     S.schur = prm->schur != 0;
     S.kappa = prm->kappa;
     S.prm = prm;
@@ -443,16 +447,22 @@ extern "C" bsm_status bsm_cg_solve(bsm_ctx ctx, const bsm_field_desc *desc, cons
     S.op64.ctx = ctx;
     S.op64.g = ctx->g;
     S.op64.d = S.d;
-    S.op64.real = S.real;
+    S.op64.real = link_real(desc);
     S.op64.schur = S.schur;
     S.op64.kappa = prm->kappa;
     S.op64.U = U_rep64;
     S.op64.sprec = BSM_F64;
-    S.op64.lprec = BSM_F64;
+    // U_rep64 is stored like U_rep: R(U) in FP64, or U in FP64 with the
+    // representation formed on the fly
+    {
+        bsm_field_desc d64 = *desc;
+        d64.link_prec = BSM_F64 | (desc->link_prec & BSM_LINKS_FUNDAMENTAL);
+        S.op64.lprec = link_code(&d64);
+    }
     S.op64.partials = ctx->partials;
     bsm_status s;
     if (prm->variant == BSM_SOLVER_PLAIN) s = solve_plain(S, stats);
-    else s = solve_mixed(S, desc->prec, desc->link_prec, U_rep, stats);
+    else s = solve_mixed(S, desc->prec, link_code(desc), U_rep, stats);
     hipError_t e = hipStreamSynchronize(S.st);
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (e != hipSuccess) return hip_check(e, "bsm_cg_solve");
@@ -856,6 +866,8 @@ extern "C" bsm_status bsm_batched_solve(bsm_ctx ctx, const bsm_field_desc *desc,
     if (bsm_rep_dim(desc->N, desc->rep) != desc->d_R || desc->d_R < 2 || desc->d_R > 15)
         return fail(BSM_ERR_ARG, "d_R does not match (N, rep) or is outside [2, 15]");
     if (n_rhs < 1) return fail(BSM_ERR_ARG, "n_rhs must be >= 1");
+    if (desc->link_prec & BSM_LINKS_FUNDAMENTAL)
+        return fail(BSM_ERR_ARG, "the batched solver needs links stored in the representation");
     for (int r = 0; r < n_rhs; r++)
         if (!(kappas[r] > 0) || !std::isfinite(kappas[r])) return fail(BSM_ERR_ARG, "kappas must be > 0");
     if (!(prm->tol > 0) || prm->max_iter < 1) return fail(BSM_ERR_ARG, "tol > 0 and max_iter >= 1 required");

@@ -4,6 +4,7 @@
 // scratch memory for the common sizes.
 #pragma once
 #include "bsm_internal.h"
+#include "otf.h"
 
 // Bit d of BSM_DMASK selects whether d_R = d is compiled (development
 // builds may restrict it to shorten compile times; release builds keep all).
@@ -114,6 +115,10 @@ bsm_status launch_hop(const Geom &g, int d, bool real, int prec, int link_prec, 
 // explicitly instantiated in the hop_*.hip sources
 template <int SP, int LP, int D>
 bsm_status hop_run(const Geom &g, bool real, const HopArgs &a, hipStream_t st);
+// fundamental links, representation RN = otf_rn(rep, N) formed on the fly;
+// defined in hop.h, instantiated in hop_otf.hip
+template <int SP, int LP, int RN>
+bsm_status hop_run_otf(const Geom &g, const HopArgs &a, hipStream_t st);
 int hop_blocks(const Geom &g);
 
 }  // namespace bsm

@@ -13,6 +13,7 @@
 // wrapping hops is folded into the reconstruction coefficients.
 #pragma once
 #include "dispatch.h"
+#include "otf.h"
 #include "spinor_io.h"
 
 namespace bsm {
@@ -168,6 +169,39 @@ __device__ inline void hop_dir(const Geom &g, const Coords &c, int p, uint32_t h
     }
 }
 
+// both hops along mu with fundamental links: R(U) (or R(U)^dag) applied to
+// the projected half spinor on the fly
+template <int MU, int RN, int SP, int LP, class T>
+__device__ inline void hop_dir_otf(const Geom &g, const Coords &c, int p, uint32_t h, const char *U,
+                                   size_t lblk, const char *in, T eta, cx<T> (&acc)[4 * otf_dim(RN)]) {
+    constexpr int D = otf_dim(RN), N = otf_n(RN);
+    constexpr bool NT = (BSM_LINK_NT >> SP) & 1;
+#pragma unroll
+    for (int dir = 0; dir < 2; dir++) {
+        const bool back = dir == 1;
+        float wf;
+        const uint32_t hn = neighbour<MU>(g, c, back, wf);
+        cx<T> s[4 * D];
+        load_spinor<SP, D, T>(in, g.Vh_pad, hn, s);
+        const char *blk = back ? link_block<MU, true>(U, lblk, p) : link_block<MU, false>(U, lblk, p);
+        const uint32_t hl = back ? hn : h;
+        cx<T> u[N * N];
+#pragma unroll
+        for (int e = 0; e < N * N; e++) u[e] = load_link<LP, false, T, NT>(blk, g.Vh_pad, e, hl);
+        const T sg = back ? -eta : eta;
+        cx<T> h0[D], h1[D], g0[D], g1[D];
+        project<MU, D, T>(s, sg, h0, h1);
+        if (!back) {
+            rep_apply<RN, false, T>(u, h0, g0);
+            rep_apply<RN, false, T>(u, h1, g1);
+        } else {
+            rep_apply<RN, true, T>(u, h0, g0);
+            rep_apply<RN, true, T>(u, h1, g1);
+        }
+        reconstruct<MU, D, T>(acc, sg, (T)wf, g0, g1);
+    }
+}
+
 // out = a x + b acc, stored; returns |out|^2 contribution when asked
 template <int D, int SP, class T>
 __device__ inline double hop_epilogue(const Geom &g, const HopArgs &a, int p, uint32_t h, cx<T> (&acc)[4 * D]) {
@@ -220,9 +254,10 @@ __device__ inline uint32_t plan_site(const HopArgs &a, uint32_t bl, uint32_t S3,
 #define BSM_HOP_ATTR
 #endif
 
-// one output site per thread (plans 0, 1, 2)
-template <int D, bool REAL, int SP, int LP>
-__global__ __launch_bounds__(256) BSM_HOP_ATTR void k_hop(Geom g, HopArgs a, int nblk) {
+// one output site per thread (plans 0, 1, 2, 4); RN != 0: fundamental links,
+// representation RN formed on the fly
+template <int D, bool REAL, int SP, int LP, int RN>
+__device__ inline void hop_body(const Geom &g, const HopArgs &a, int nblk) {
     using T = typename Compute<SP>::T;
     const uint32_t S3 = (uint32_t)g.Vh / (uint32_t)g.L[0];
     uint32_t lb;
@@ -246,7 +281,7 @@ __global__ __launch_bounds__(256) BSM_HOP_ATTR void k_hop(Geom g, HopArgs a, int
     }
     const int p = a.p0 + pi;
     const bool active = h < (uint32_t)g.Vh;
-    const size_t lblk = link_block_bytes(LP, REAL, D, g.Vh_pad);
+    const size_t lblk = RN ? link_block_bytes(LP, false, otf_n(RN), g.Vh_pad) : link_block_bytes(LP, REAL, D, g.Vh_pad);
     double nrm = 0.0;
     if (active) {
         cx<T> acc[4 * D];
@@ -256,16 +291,36 @@ __global__ __launch_bounds__(256) BSM_HOP_ATTR void k_hop(Geom g, HopArgs a, int
         const char *in = (const char *)a.in[p];
         const char *U = (const char *)a.U;
         const T eta = a.dagger ? (T)-1 : (T)1;
-        hop_dir<0, D, REAL, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
-        hop_dir<1, D, REAL, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
-        hop_dir<2, D, REAL, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
-        hop_dir<3, D, REAL, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
+        if constexpr (RN != 0) {
+            static_assert(otf_dim(RN) == D, "on-the-fly representation does not match d_R");
+            hop_dir_otf<0, RN, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
+            hop_dir_otf<1, RN, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
+            hop_dir_otf<2, RN, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
+            hop_dir_otf<3, RN, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
+        } else {
+            hop_dir<0, D, REAL, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
+            hop_dir<1, D, REAL, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
+            hop_dir<2, D, REAL, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
+            hop_dir<3, D, REAL, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
+        }
         nrm = hop_epilogue<D, SP, T>(g, a, p, h, acc);
     }
     if (a.norm_partials) {
         double s = block_sum_256(nrm);
         if (threadIdx.x == 0) a.norm_partials[lb] = s;
     }
+}
+
+template <int D, bool REAL, int SP, int LP>
+__global__ __launch_bounds__(256) BSM_HOP_ATTR void k_hop(Geom g, HopArgs a, int nblk) {
+    hop_body<D, REAL, SP, LP, 0>(g, a, nblk);
+}
+
+// the on-the-fly form (fundamental links, representation formed per hop)
+template <int D, int SP, int LP, int RN>
+__global__ __launch_bounds__(256) void k_hop_otf(
+    Geom g, HopArgs a, int nblk) {
+    hop_body<D, false, SP, LP, RN>(g, a, nblk);
 }
 
 // Column sweep (plan 3).  A thread owns one spatial half site s and walks
@@ -563,6 +618,21 @@ bsm_status hop_run(const Geom &g, bool real, const HopArgs &a, hipStream_t st) {
     } else {
         k_hop<D, false, SP, LP><<<grid, 256, 0, st>>>(g, a, nblk);
     }
+    BSM_HIP(hipGetLastError());
+    return BSM_OK;
+}
+
+// fundamental links, representation RN formed on the fly (one thread per
+// site; no colour split and no column sweep)
+template <int SP, int LP, int RN>
+bsm_status hop_run_otf(const Geom &g, const HopArgs &a, hipStream_t st) {
+    if (a.wide > 0 || a.order == 3) return fail(BSM_ERR_ARG, "on-the-fly hop: plan not available");
+    const int grid = hop_grid(g, a);
+    const int nblk = grid / a.np;
+    if (a.norm_partials && (int64_t)grid > a.norm_cap)
+        return fail(BSM_ERR_ARG, "fused-norm hop needs " + std::to_string(grid) + " reduction slots, " +
+                                     std::to_string(a.norm_cap) + " available");
+    k_hop_otf<otf_dim(RN), SP, LP, RN><<<grid, 256, 0, st>>>(g, a, nblk);
     BSM_HIP(hipGetLastError());
     return BSM_OK;
 }

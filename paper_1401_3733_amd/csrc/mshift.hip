@@ -1,0 +1,309 @@
+// One Krylov space for a family of masses (Section II.B's inversion, for many
+// kappa at once).  D(kappa) = 1 - kappa H = kappa (sigma - H) with
+// sigma = 1/kappa, so the systems (sigma_i - H) y_i = b, x_i = y_i / kappa_i,
+// differ only by a multiple of the identity: they share the Krylov space of
+// H and b, and one sequence of operator applications serves all of them.
+//
+// The seed is the hardest member (largest kappa, smallest sigma_0); the
+// others are shifted by delta_i = sigma_i - sigma_0 >= 0.  The iteration is
+// BiCG with the shadow sequence gamma5 times the primal one, which is valid
+// because A = sigma_0 - H satisfies A^dag = gamma5 A gamma5: the shadow
+// recurrences then reproduce gamma5 r_n and gamma5 p_n exactly, all
+// coefficients are real (r^dag gamma5 r and p^dag gamma5 A p are real), and
+// one operator application per iteration suffices.  The residual of shift i
+// is zeta_i r_n, with zeta from the three-term recurrence of the residual
+// polynomials evaluated at -delta_i:
+//   zeta_(n+1) = zeta_n zeta_(n-1) a_(n-1) /
+//                (a_(n-1) zeta_(n-1) (1 + delta a_n) + a_n b_(n-1) (zeta_(n-1) - zeta_n)),
+//   a_n^i = a_n zeta_(n+1) / zeta_n,  b_n^i = b_n (zeta_(n+1) / zeta_n)^2,
+//   x^i += a_n^i p^i,  p^i = zeta_(n+1) r_(n+1) + b_n^i p^i.
+// Shift i retires once |zeta_i| |r| <= (the caller's delta) tol |b|; afterwards every x_i is
+// divided by kappa_i and judged by its FP64 true residual ||b - D(kappa_i) x_i||
+// / ||b||; a member that misses tol (or a breakdown, a non-finite value) is
+// finished by plain FP64 Schur CG.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "blas.h"
+#include "dispatch.h"
+#include "solver.h"
+#include "spinor_io.h"
+
+namespace bsm {
+
+constexpr int kMaxShifts = 32;
+constexpr int kMsBlocks = 16384;   // reduction workgroups (grid-stride beyond)
+
+struct MsGeom {
+    size_t n;        // complex elements of a full FP64 field (incl. padding)
+    uint32_t Vh, Vh_pad, planes;   // planes = 4 d per parity block
+};
+
+__device__ inline bool ms_live(const MsGeom &m, size_t e, double &g5) {
+    const uint32_t h = (uint32_t)(e % m.Vh_pad);
+    const uint32_t c = (uint32_t)((e / m.Vh_pad) % m.planes);
+    g5 = c < m.planes / 2 ? 1.0 : -1.0;   // spins 0, 1 then 2, 3 (chiral basis)
+    return h < m.Vh;
+}
+
+// partials[block] = sum Re conj(a) gamma5 b over live elements
+__global__ __launch_bounds__(256) void k_ms_jdot(MsGeom m, const double2 *a, const double2 *b, double *partials) {
+    double s = 0.0;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < m.n; e += (size_t)gridDim.x * 256) {
+        double g5;
+        if (!ms_live(m, e, g5)) continue;
+        const double2 x = a[e], y = b[e];
+        s = fma(g5, x.x * y.x + x.y * y.y, s);
+    }
+    const double t = block_sum_256(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// r -= alpha q; partials of r^dag gamma5 r (first gridDim.x) and |r|^2 (next)
+__global__ __launch_bounds__(256) void k_ms_residual(MsGeom m, double2 *r, const double2 *q, double alpha,
+                                                     double *partials) {
+    double sj = 0.0, s2 = 0.0;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < m.n; e += (size_t)gridDim.x * 256) {
+        double g5;
+        if (!ms_live(m, e, g5)) continue;
+        double2 x = r[e];
+        const double2 y = q[e];
+        x.x = fma(-alpha, y.x, x.x);
+        x.y = fma(-alpha, y.y, x.y);
+        r[e] = x;
+        const double n2 = x.x * x.x + x.y * x.y;
+        sj = fma(g5, n2, sj);
+        s2 += n2;
+    }
+    const double tj = block_sum_256(sj);
+    __syncthreads();   // block_sum_256's LDS slots are read by thread 0 before the second sum reuses them
+    const double t2 = block_sum_256(s2);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = tj;
+        partials[gridDim.x + blockIdx.x] = t2;
+    }
+}
+
+struct MsCoef {
+    double a[kMaxShifts], b[kMaxShifts], z[kMaxShifts];
+    uint32_t mask;   // shifts whose x is updated
+    uint32_t pmask;  // shifts whose p is updated (the seed's always, while any shift runs)
+};
+
+// x_i += a_i p_i ; p_i = z_i r + b_i p_i  for the shifts in the masks; fields
+// are stride complex numbers apart
+__global__ __launch_bounds__(256) void k_ms_update(MsGeom m, const double2 *r, double2 *x, double2 *p, size_t stride,
+                                                   int n, MsCoef c) {
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < m.n; e += (size_t)gridDim.x * 256) {
+        double g5;
+        if (!ms_live(m, e, g5)) continue;
+        const double2 rv = r[e];
+        for (int i = 0; i < n; i++) {
+            if (!((c.pmask >> i) & 1u)) continue;
+            double2 pv = p[i * stride + e];
+            if ((c.mask >> i) & 1u) {
+                double2 xv = x[i * stride + e];
+                xv.x = fma(c.a[i], pv.x, xv.x);
+                xv.y = fma(c.a[i], pv.y, xv.y);
+                x[i * stride + e] = xv;
+            }
+            pv.x = fma(c.z[i], rv.x, c.b[i] * pv.x);
+            pv.y = fma(c.z[i], rv.y, c.b[i] * pv.y);
+            p[i * stride + e] = pv;
+        }
+    }
+}
+
+static int ms_grid(const MsGeom &m) {
+    const size_t nb = (m.n + 255) / 256;
+    return (int)std::min<size_t>(nb, kMsBlocks);
+}
+
+#define TRY(x)                           \
+    do {                                 \
+        bsm_status _s = (x);             \
+        if (_s != BSM_OK) return _s;     \
+    } while (0)
+
+static bsm_status ms_sum(bsm_ctx ctx, const double *partials, int n, double *out, hipStream_t st) {
+    *out = reduce_to_host(ctx, partials, n, st);
+    return BSM_OK;
+}
+
+}  // namespace bsm
+
+using namespace bsm;
+
+extern "C" bsm_status bsm_shifted_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep64,
+                                        const bsm_solver_params *prm, int32_t n_kappa, const double *kappas,
+                                        const void *b, void *x, bsm_solver_stats *stats, void *stream) {
+    if (!ctx || !desc || !prm || !kappas || !b || !x || !stats || !U_rep64) return fail(BSM_ERR_ARG, "null argument");
+    if (n_kappa < 1 || n_kappa > kMaxShifts) return fail(BSM_ERR_ARG, "n_kappa must be in [1, 32]");
+    for (int i = 0; i < n_kappa; i++) stats[i] = bsm_solver_stats{};
+    if (bsm_rep_dim(desc->N, desc->rep) != desc->d_R || desc->d_R < 2 || desc->d_R > 15)
+        return fail(BSM_ERR_ARG, "d_R does not match (N, rep) or is outside [2, 15]");
+    if (desc->prec != BSM_F64 || link_base(desc->link_prec) != BSM_F64)
+        return fail(BSM_ERR_ARG, "the shifted solver runs in FP64: desc prec and link_prec must be F64");
+    for (int i = 0; i < n_kappa; i++)
+        if (!(kappas[i] > 0) || !std::isfinite(kappas[i])) return fail(BSM_ERR_ARG, "kappas must be finite and > 0");
+    if (!(prm->tol > 0) || prm->max_iter < 1) return fail(BSM_ERR_ARG, "tol > 0 and max_iter >= 1 required");
+    if (b == x) return fail(BSM_ERR_ARG, "b and x must differ");
+    hipStream_t st = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    const Geom &g = ctx->g;
+    const int d = desc->d_R, n = n_kappa;
+    const size_t bb = spinor_block_bytes(BSM_F64, d, g.Vh_pad), full = 2 * bb;
+    MsGeom m;
+    m.n = full / sizeof(double2);
+    m.Vh = (uint32_t)g.Vh;
+    m.Vh_pad = (uint32_t)g.Vh_pad;
+    m.planes = 4 * d;
+    // shifts relative to the seed (the largest kappa)
+    int seed = 0;
+    for (int i = 1; i < n; i++)
+        if (kappas[i] > kappas[seed]) seed = i;
+    const double sigma0 = 1.0 / kappas[seed];
+    std::vector<double> delta(n);
+    for (int i = 0; i < n; i++) delta[i] = 1.0 / kappas[i] - sigma0;
+    // scratch: r, A p, the full-lattice residual field, and one p per shift
+    void *work = nullptr;
+    TRY(ctx_work(ctx, (3 + (size_t)n) * full, &work));
+    char *r = (char *)work, *Ap = r + full, *tfull = Ap + full, *P = tfull + full;
+    char *X = (char *)x;
+    const Vec none{nullptr, BSM_F64};
+    BSM_HIP(hipMemsetAsync(X, 0, (size_t)n * full, st));
+    BSM_HIP(hipMemcpyAsync(r, b, full, hipMemcpyDeviceToDevice, st));
+    for (int i = 0; i < n; i++) BSM_HIP(hipMemcpyAsync(P + i * full, b, full, hipMemcpyDeviceToDevice, st));
+    double *parts = ctx->partials;
+    const int grid = ms_grid(m);
+    double bnorm2 = 0.0, rrJ = 0.0;
+    TRY(blas_dot(g, d, 2, Vec{(void *)b, BSM_F64}, none, parts, st));
+    TRY(ms_sum(ctx, parts, blas_blocks(g, 2), &bnorm2, st));
+    k_ms_jdot<<<grid, 256, 0, st>>>(m, (const double2 *)r, (const double2 *)r, parts);
+    BSM_HIP(hipGetLastError());
+    TRY(ms_sum(ctx, parts, grid, &rrJ, st));
+    // the operator A = sigma_0 - H on full fields, links as the descriptor says
+    bsm_field_desc d64 = *desc;
+    const int lc = link_code(&d64);
+    const bool real = link_real(&d64);
+    auto applyA = [&](const char *in, char *out) -> bsm_status {
+        HopArgs a{};
+        a.U = U_rep64;
+        a.dagger = 0;
+        a.p0 = 0;
+        a.np = 2;
+        a.in[0] = in + bb; a.in[1] = in;
+        a.x[0] = in; a.x[1] = in + bb;
+        a.out[0] = out; a.out[1] = out + bb;
+        a.a = sigma0;
+        a.b = -1.0;
+        apply_plan(ctx, d, real, BSM_F64, lc, a);
+        return launch_hop(g, d, real, BSM_F64, lc, a, st);
+    };
+    std::vector<double> zeta(n, 1.0), zeta_prev(n, 1.0), zn(n, 1.0);
+    std::vector<int> iters(n, 0);
+    uint32_t active = n == 32 ? 0xffffffffu : ((1u << n) - 1);
+    double a_prev = 1.0, b_prev = 0.0;
+    const double trig = (prm->delta > 0 ? prm->delta : 0.3) * prm->tol, bnorm = std::sqrt(bnorm2);
+    int it = 0;
+    bool broke = !(bnorm2 > 0) || !std::isfinite(rrJ);
+    while (!broke && active && it < prm->max_iter) {
+        const char *pseed = P + seed * full;
+        TRY(applyA(pseed, Ap));
+        double pAp = 0.0;
+        k_ms_jdot<<<grid, 256, 0, st>>>(m, (const double2 *)pseed, (const double2 *)Ap, parts);
+        BSM_HIP(hipGetLastError());
+        TRY(ms_sum(ctx, parts, grid, &pAp, st));
+        if (!std::isfinite(pAp) || pAp == 0.0) { broke = true; break; }
+        const double alpha = rrJ / pAp;
+        MsCoef c{};
+        // members still iterating (the seed's p drives the recurrence and is
+        // kept while any member runs); retired members keep their zeta
+        const uint32_t run = active | (1u << seed);
+        for (int i = 0; i < n; i++) {
+            if (!((run >> i) & 1u)) continue;
+            const double den = a_prev * zeta_prev[i] * (1.0 + delta[i] * alpha) +
+                               alpha * b_prev * (zeta_prev[i] - zeta[i]);
+            zn[i] = zeta[i] * zeta_prev[i] * a_prev / den;
+            c.a[i] = alpha * zn[i] / zeta[i];
+        }
+        k_ms_residual<<<grid, 256, 0, st>>>(m, (double2 *)r, (const double2 *)Ap, alpha, parts);
+        BSM_HIP(hipGetLastError());
+        double rrJ_new = 0.0, rn2 = 0.0;
+        TRY(ms_sum(ctx, parts, grid, &rrJ_new, st));
+        TRY(ms_sum(ctx, parts + grid, grid, &rn2, st));
+        const double beta = rrJ_new / rrJ;
+        for (int i = 0; i < n; i++) {
+            if (!((run >> i) & 1u)) continue;
+            const double q = zn[i] / zeta[i];
+            c.b[i] = beta * q * q;
+            c.z[i] = zn[i];
+        }
+        c.mask = active;
+        c.pmask = run;
+        k_ms_update<<<std::min<int>((int)((m.n + 255) / 256), 65536), 256, 0, st>>>(
+            m, (const double2 *)r, (double2 *)X, (double2 *)P, full / sizeof(double2), n, c);
+        BSM_HIP(hipGetLastError());
+        it++;
+        bool finite = std::isfinite(alpha) && std::isfinite(beta) && std::isfinite(rn2);
+        for (int i = 0; i < n; i++) {
+            if (!((run >> i) & 1u)) continue;
+            zeta_prev[i] = zeta[i];
+            zeta[i] = zn[i];
+            if (!std::isfinite(zeta[i]) || !std::isfinite(c.a[i]) || !std::isfinite(c.b[i])) finite = false;
+        }
+        if (!finite) { broke = true; break; }
+        a_prev = alpha;
+        b_prev = beta;
+        rrJ = rrJ_new;
+        const double rn = std::sqrt(rn2);
+        for (int i = 0; i < n; i++)
+            if (((active >> i) & 1u) && std::fabs(zeta[i]) * rn <= trig * bnorm) {
+                active &= ~(1u << i);
+                iters[i] = it;
+            }
+    }
+    for (int i = 0; i < n; i++)
+        if (!iters[i]) iters[i] = it;
+    // x_i = y_i / kappa_i (D(kappa) y = kappa b), then each member's FP64 true residual decides
+    for (int i = 0; i < n; i++) {
+        char *xi = X + i * full;
+        TRY(blas_axpby(g, d, 2, Vec{xi, BSM_F64}, 1.0 / kappas[i], Vec{xi, BSM_F64}, 0.0, none, nullptr, st));
+        Op o{};
+        o.ctx = ctx; o.g = g; o.d = d; o.real = real; o.schur = false; o.kappa = kappas[i];
+        o.U = U_rep64; o.sprec = BSM_F64; o.lprec = lc; o.partials = ctx->partials;
+        double res = INFINITY;
+        if (!broke || !((active >> i) & 1u)) TRY(true_residual_full(o, (const char *)b, xi, tfull, bnorm2, &res, st));
+        stats[i].iters = iters[i];
+        stats[i].true_rel_res = res;
+    }
+    // members that missed tol: plain CG (it reuses the context scratch this
+    // solver's fields were carved from, so only caller memory is used here)
+    bsm_status worst = BSM_OK;
+    for (int i = 0; i < n; i++) {
+        char *xi = X + i * full;
+        if (!(stats[i].true_rel_res <= prm->tol)) {
+            // finish this member with plain FP64 Schur CG (from x = 0)
+            bsm_solver_params p1 = *prm;
+            p1.variant = BSM_SOLVER_PLAIN;
+            p1.schur = 1;
+            p1.kappa = kappas[i];
+            bsm_solver_stats s1{};
+            bsm_status cs = bsm_cg_solve(ctx, desc, U_rep64, U_rep64, &p1, b, xi, &s1, stream);
+            stats[i].fell_back = 1;
+            stats[i].iters += s1.iters;
+            stats[i].true_rel_res = s1.true_rel_res;
+            stats[i].restarts = s1.restarts;
+            if (cs != BSM_OK && worst == BSM_OK) worst = cs;
+        }
+        stats[i].converged = stats[i].true_rel_res <= prm->tol;
+    }
+    BSM_HIP(hipStreamSynchronize(st));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int i = 0; i < n; i++) stats[i].seconds = secs;
+    if (worst == BSM_ERR_NOT_CONVERGED) fail(worst, "max_iter reached before every member met tol");
+    if (worst == BSM_ERR_NONFINITE) fail(worst, "non-finite value in a reduction");
+    return worst;
+}

@@ -32,7 +32,7 @@ def dev_build_d():
 class Setup:
     """Context + represented links on the GPU for one lattice and (N, rep)."""
 
-    def __init__(self, lat, N, rep, Uf, prec="f64", link_prec=None):
+    def __init__(self, lat, N, rep, Uf, prec="f64", link_prec=None, fundamental_links=False):
         import torch
         ds = dev_build_d()
         if ds is not None:
@@ -40,7 +40,7 @@ class Setup:
                                "rebuild the full library before running the GPU tests")
         self.lat = lat
         self.ctx = bsm.Context(lat.dims, lat.bc)
-        self.desc = bsm.desc(N, rep, prec, link_prec)
+        self.desc = bsm.desc(N, rep, prec, link_prec, fundamental_links=fundamental_links)
         self.d = self.desc.d_R
         self.Uf_dev = c128(Uf)
         self.U = self.ctx.new_gauge(self.desc)

@@ -1,0 +1,133 @@
+"""The shifted-family solver (one source, many kappas in one Krylov space)
+against the FP64 oracle: every member's solution against the oracle's own
+solve of D(kappa_i) x = b to 1e-13, within 1e-9, and its FP64 true residual
+(computed by the oracle) <= 1e-10."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1401_3733_amd import bsm
+from paper_1401_3733_amd import inputs as gen
+from tests.gpu_util import Setup, note, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _solve(S, b, kappas, via_cg=False, **kw):
+    import torch
+    bb = S.pack(b)
+    x = torch.zeros(len(kappas) * bb.numel(), dtype=bb.dtype, device="cuda")
+    prm = bsm.solver_params(0.1, kw.pop("tol", 1e-10), max_iter=kw.pop("max_iter", 5000),
+                            delta=kw.pop("delta", 0.3), variant=bsm.SOLVER_SHIFTED, kappas=kappas)
+    if via_cg:
+        st, stats = S.ctx.bsm_cg_solve(S.desc, S.U, S.U, prm, bb, x, check=False)
+    else:
+        st, stats = S.ctx.bsm_shifted_solve(S.desc, S.U, prm, kappas, bb, x, check=False)
+    return st, stats, x, S.unpack(x, n_rhs=len(kappas)).reshape((len(kappas),) + b.shape)
+
+
+@pytest.mark.parametrize("N,rep,links,kappas", [
+    (4, "adj", "haar", list(np.linspace(0.10, 0.125, 16))),
+    (3, "fund", "near_identity", list(np.linspace(0.11, 0.13, 8))),
+    (2, "fund", "haar", [0.12, 0.08, 0.1]),
+])
+def test_shifted_family_matches_oracle(N, rep, links, kappas):
+    note(f"shifted solve N={N} {rep} {len(kappas)} kappas")
+    lat = gen.Lattice(8, 4, 6, 4)
+    Uf = gen.gauge_links(lat, N, links, 870 + N, eps=0.3)
+    S = Setup(lat, N, rep, Uf)
+    UR = oracle.represent(Uf, rep)
+    if rep == "adj":
+        UR = UR.real.astype(np.complex128)
+    b = gen.gaussian_spinor(lat, S.d, 871)
+    st, stats, _, xs = _solve(S, b, kappas)
+    assert st == 0
+    worst = 0.0
+    for i, k in enumerate(kappas):
+        tr = oracle.true_residual(lat, UR, k, b, xs[i])
+        assert stats[i]["converged"] and tr <= 1e-10, (i, k, tr)
+        assert abs(tr - stats[i]["true_rel_res"]) < 1e-12
+        xo, _ = oracle.solve(lat, UR, k, b, tol=1e-13, schur=True)
+        worst = max(worst, rel(xs[i], xo))
+        assert rel(xs[i], xo) <= 1e-9
+    its = [s["iters"] for s in stats]
+    print(f"shifted N={N} {rep}: iterations per member {its}, fell back {[s['fell_back'] for s in stats]}, "
+          f"max |x - x_oracle| {worst:.2e}", flush=True)
+    # the hardest member (largest kappa) needs the most shared iterations
+    assert its[int(np.argmax(kappas))] == max(its)
+
+
+def test_shifted_via_cg_solve_and_fundamental_links():
+    """the SHIFTED variant of bsm_cg_solve forwards unchanged; and the family
+    runs on fundamental links with the two-index representation formed on
+    the fly"""
+    import torch
+    note("shifted solve via cg_solve, 2S N=3 with fundamental links")
+    lat = gen.Lattice(4, 4, 6, 4)
+    Uf = gen.gauge_links(lat, 3, "near_identity", 880, eps=0.3)
+    S = Setup(lat, 3, "sym", Uf)
+    So = Setup(lat, 3, "sym", Uf, fundamental_links=True)
+    b = gen.gaussian_spinor(lat, 6, 881)
+    ks = [0.12, 0.1, 0.125]
+    st1, s1, x1, _ = _solve(S, b, ks)
+    st2, s2, x2, _ = _solve(S, b, ks, via_cg=True)
+    assert st1 == st2 == 0 and torch.equal(x1, x2) and [a["iters"] for a in s1] == [a["iters"] for a in s2]
+    st3, s3, _, x3 = _solve(So, b, ks)
+    UR = oracle.represent(Uf, "sym")
+    assert st3 == 0
+    for i, k in enumerate(ks):
+        assert oracle.true_residual(lat, UR, k, b, x3[i]) <= 1e-10
+
+
+def test_shifted_fallback_finishes_with_cg():
+    """a member the shared iteration leaves above tol (here: members retire
+    at a residual estimate of 1e6 tol) is finished by plain FP64 CG and
+    reported as fallen back; with max_iter too small for either phase the
+    solve reports NOT_CONVERGED"""
+    note("shifted solve fallback")
+    lat = gen.Lattice(4, 4, 4, 6)
+    Uf = gen.gauge_links(lat, 3, "haar", 890)
+    S = Setup(lat, 3, "fund", Uf)
+    b = gen.gaussian_spinor(lat, 3, 891)
+    ks = [0.1, 0.12]
+    st, stats, _, xs = _solve(S, b, ks, delta=1e6)
+    assert st == 0
+    assert all(s["fell_back"] == 1 for s in stats)
+    for i, k in enumerate(ks):
+        assert oracle.true_residual(lat, Uf, k, b, xs[i]) <= 1e-10
+    st, stats, _, _ = _solve(S, b, ks, max_iter=3)
+    assert st == bsm.ERR_NOT_CONVERGED and not any(s["converged"] for s in stats)
+
+
+def test_shifted_errors():
+    import torch
+    lat = gen.Lattice(4, 4, 4, 4)
+    S = Setup(lat, 2, "fund", gen.gauge_links(lat, 2, "haar", 892))
+    bb = S.pack(gen.gaussian_spinor(lat, 2, 893))
+    x = torch.zeros(40 * bb.numel(), dtype=bb.dtype, device="cuda")
+    for ks in ([0.1] * 33, [0.1, -0.1]):
+        st, _ = S.ctx.bsm_shifted_solve(S.desc, S.U, bsm.solver_params(0.1, 1e-10), ks, bb, x, check=False)
+        assert st == bsm.ERR_ARG
+    d32 = bsm.desc(2, "fund", "f32")
+    st, _ = S.ctx.bsm_shifted_solve(d32, S.U, bsm.solver_params(0.1), [0.1], bb, x, check=False)
+    assert st == bsm.ERR_ARG
+
+
+def test_shifted_full_size_true_residual():
+    """24^3 x 48 SU(4) adjoint, 16 kappas in [0.10, 0.125], one source (the
+    benchmark's workload and launch configuration): the oracle recomputes the
+    true residual of the hardest and the easiest member at full size."""
+    note("shifted solve full size 24^3x48 SU(4) adj")
+    lat = gen.config_lattice(4)
+    Uf = gen.config_links(4, lat)
+    S = Setup(lat, 4, "adj", Uf)
+    ks = [float(k) for k in gen.CONFIGS[4]["kappa"]]
+    b = gen.gaussian_spinor(lat, 15, gen.SEED_SOURCE + 4)
+    st, stats, _, xs = _solve(S, b, ks)
+    assert st == 0
+    print(f"full-size shifted: iterations {[s['iters'] for s in stats]}, {stats[0]['seconds']:.3f} s", flush=True)
+    UR = oracle.represent(Uf, "adj").real.astype(np.complex128)
+    for i in (int(np.argmax(ks)), int(np.argmin(ks))):
+        tr = oracle.true_residual(lat, UR, ks[i], b, xs[i])
+        print(f"  kappa {ks[i]:.4f}: oracle true residual {tr:.2e} (library {stats[i]['true_rel_res']:.2e})", flush=True)
+        assert tr <= 1e-10
