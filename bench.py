@@ -845,12 +845,12 @@ def _init_weights(channels, seed):
 def measure_copy(bsm, reps=10):
     """Achievable HBM bandwidth of a plain 16-byte copy (bytes read + written
     per launch / mean launch time) and of a read-only sweep, on 1 GiB, each
-    the best of a few launch shapes (2048 to 16384 workgroups; the copy also
-    with streaming accesses)."""
+    the best of a few launch shapes (2048 to 262144 workgroups, ordinary and
+    streaming accesses)."""
     import torch
     src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
-    part = torch.zeros(16384, dtype=torch.float32, device="cuda")
+    part = torch.zeros(262144, dtype=torch.float32, device="cuda")
 
     def rate(fn, nbytes):
         for _ in range(2):
@@ -864,10 +864,10 @@ def measure_copy(bsm, reps=10):
         return nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
     copy = read = 0.0
-    for blocks in (2048, 8192, 16384):
+    for blocks in (2048, 16384, 65536, 262144):
         for nt in (0, 1):
             copy = max(copy, rate(lambda: bsm.bsm_stream_copy(src, dst, nontemporal=nt, blocks=blocks), 2 << 30))
-        read = max(read, rate(lambda: bsm.bsm_stream_read(src, part, blocks=blocks), 1 << 30))
+            read = max(read, rate(lambda: bsm.bsm_stream_read(src, part, blocks=blocks, nontemporal=nt), 1 << 30))
     del src, dst, part
     torch.cuda.empty_cache()
     return copy, read

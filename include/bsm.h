@@ -204,10 +204,12 @@ bsm_status bsm_autotune(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_r
 bsm_status bsm_stream_copy(const void *src, void *dst, size_t bytes, int32_t nontemporal,
                            int32_t blocks, void *stream);
 /* Read-only sweep of bytes (multiple of 16, 16-byte aligned) on `blocks`
- * workgroups (<= 0: 2048); out (device, >= blocks floats) receives one sum
- * per workgroup so the loads are kept.  Calibrates the achievable read
- * bandwidth. */
-bsm_status bsm_stream_read(const void *src, size_t bytes, int32_t blocks, float *out, void *stream);
+ * workgroups (<= 0: 2048), each over its own contiguous chunk, with
+ * streaming loads when nontemporal; out (device, >= blocks floats) receives
+ * one sum per workgroup so the loads are kept.  Calibrates the achievable
+ * read bandwidth. */
+bsm_status bsm_stream_read(const void *src, size_t bytes, int32_t nontemporal, int32_t blocks, float *out,
+                           void *stream);
 
 /* ------------------------------------------------------------- vector ops
  * The Krylov linear algebra of the solvers (paper, Section II.B: CG repeats

@@ -87,7 +87,7 @@ _SIGS = {
                                    C.POINTER(C.c_float)]),
     "bsm_autotune": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, _vp]),
     "bsm_stream_copy": (C.c_int, [_vp, _vp, C.c_size_t, C.c_int32, C.c_int32, _vp]),
-    "bsm_stream_read": (C.c_int, [_vp, C.c_size_t, C.c_int32, _vp, _vp]),
+    "bsm_stream_read": (C.c_int, [_vp, C.c_size_t, C.c_int32, C.c_int32, _vp, _vp]),
     "bsm_vec_axpby": (C.c_int, [_vp, C.POINTER(FieldDesc), C.c_int32, C.c_double, _vp, C.c_double, _vp,
                                 C.c_int32, _vp, _vp]),
     "bsm_vec_dot": (C.c_int, [_vp, C.POINTER(FieldDesc), C.c_int32, _vp, _vp, C.POINTER(C.c_double), _vp]),
@@ -481,9 +481,10 @@ def bsm_stream_copy(src, dst, nbytes=None, nontemporal=0, blocks=0, stream=None)
            "bsm_stream_copy")
 
 
-def bsm_stream_read(src, out, nbytes=None, blocks=0, stream=None):
+def bsm_stream_read(src, out, nbytes=None, blocks=0, nontemporal=0, stream=None):
     n = src.numel() * src.element_size() if nbytes is None else nbytes
-    _check(lib().bsm_stream_read(_ptr(src), n, int(blocks), _ptr(out), _stream(stream)), "bsm_stream_read")
+    _check(lib().bsm_stream_read(_ptr(src), n, int(nontemporal), int(blocks), _ptr(out), _stream(stream)),
+           "bsm_stream_read")
 
 
 # ------------------------------------------------------------- conveniences

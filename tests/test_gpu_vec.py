@@ -57,7 +57,7 @@ def test_conversions():
 
 
 @pytest.mark.parametrize("nbytes", [1 << 20, (1 << 20) + 4096 * 16 + 48])
-@pytest.mark.parametrize("blocks", [1, 7, 2048])
+@pytest.mark.parametrize("blocks", [1, 7, 2048, 65536])
 def test_stream_copy_and_read(nbytes, blocks):
     """the bandwidth calibration kernels: the copy is exact, including a
     ragged chunk per workgroup and a tail, and the read sweep's per-workgroup
@@ -71,9 +71,10 @@ def test_stream_copy_and_read(nbytes, blocks):
         bsm.bsm_stream_copy(src, dst, nontemporal=nt, blocks=blocks)
         torch.cuda.synchronize()
         assert torch.equal(dst, src)
-    part = torch.zeros(blocks, dtype=torch.float32, device="cuda")
-    bsm.bsm_stream_read(src, part, blocks=blocks)
-    torch.cuda.synchronize()
-    assert abs(part.double().sum().item() - src.double().sum().item()) <= 1e-3 * n ** 0.5
+    for nt in (0, 1):
+        part = torch.zeros(blocks, dtype=torch.float32, device="cuda")
+        bsm.bsm_stream_read(src, part, blocks=blocks, nontemporal=nt)
+        torch.cuda.synchronize()
+        assert abs(part.double().sum().item() - src.double().sum().item()) <= 1e-3 * n ** 0.5
     with pytest.raises(bsm.BsmError):
         bsm.bsm_stream_read(src, part, nbytes=nbytes - 4, blocks=blocks)
