@@ -387,11 +387,17 @@ bsm_status bsm_fgcr_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U
                           void *x, bsm_solver_stats *stats, void *stream);
 
 /* ------------------------------------------------------- many right-hand sides
- * Block fields hold up to 16 right-hand sides together (FP32, layout private)
- * so that one link load serves all of them; available for real (adjoint)
+ * Block fields hold up to 16 right-hand sides together (layout private) so
+ * that one link load serves all of them; available for real (adjoint)
  * links, where the hop of 16 RHS at a site is a dense product of the d x d
- * link with a d x 64 block of projected half spinors, done on FP32 matrix
- * cores.  desc->rep must be BSM_REP_ADJ for the block calls below. */
+ * link with a d x 64 block of projected half spinors, done on matrix cores.
+ * desc->rep must be BSM_REP_ADJ for the block calls below.  desc->prec
+ * selects the block precision: BSM_F16S gives FP16 block fields (a float
+ * scale per site and RHS, the codes rounded as the F16S spinors are) and
+ * FP16 block links (d_R 3, 8, 15), with FP16 matrix-core products
+ * accumulated in FP32; any other precision gives FP32 fields and links on
+ * FP32 matrix cores.  desc->link_prec is the precision of the represented
+ * links given to bsm_gauge_to_block (F64 or F32). */
 /* bytes of one full block field (both parities, 16 RHS slots) */
 size_t bsm_block_bytes(bsm_ctx ctx, const bsm_field_desc *desc);
 /* bytes of the links in block layout */
@@ -407,32 +413,40 @@ bsm_status bsm_gauge_to_block(bsm_ctx ctx, const bsm_field_desc *desc, const voi
                               void *stream);
 /* Even-odd hop of every RHS slot: out_r = a_r x_r + b_r H_{p,1-p} in_r, with
  * a, b host arrays of 16 (a nullable: x is not read), in / x / out one parity
- * block of block fields (in must not overlap out). */
+ * block of block fields (in must not overlap out; x may be out). */
 bsm_status bsm_dslash_eo_block(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_block,
                                int32_t out_parity, int32_t dagger, const double *a, const void *x,
                                const double *b, const void *in, void *out, void *stream);
 /* Block hop launch plan per d_R: sites per wavefront (1, or 2 processed
  * interleaved with half the register budget per wavefront), wavefronts
- * per workgroup (1, 2, 4) and the site order (tiled = 1: tiles of a few
+ * per workgroup (1, 2, 4), the site order (tiled = 1: tiles of a few
  * lattice rows in t, z and y, so the neighbours of a site are visited close
  * together and their 16-RHS blocks are fetched fewer times; needs T
- * divisible by 2 or 3 and LY, LZ even, else BSM_ERR_ARG).  bsm_block_autotune times every plan on the
+ * divisible by 2 or 3 and LY, LZ even, else BSM_ERR_ARG) and the order of
+ * workgroups over the 8 XCDs (xcd_chunk = 0: each XCD takes one contiguous
+ * eighth of the sites; c in 1..4096: each XCD takes runs of c consecutive
+ * workgroups in turn, so the XCDs sweep nearby sites together and share the
+ * memory-side cache).  FP16 and FP32 block hops keep separate plans; the
+ * FP16 one runs one site per wavefront (sites_per_wave must be 1).
+ * bsm_block_autotune times every plan on the
  * given block links (scratch fields owned by the context) and keeps the
- * fastest; the batched solver tunes once per d_R and context unless a plan
- * was set by hand.  us: time per hop of the tuned plan (0: default plan,
+ * fastest; the batched solver tunes once per d_R, precision and context
+ * unless a plan was set by hand.  us: time per hop of the tuned plan (0: default plan,
  * -1: set by hand).  Synchronous. */
 bsm_status bsm_block_autotune(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_block, void *stream);
 bsm_status bsm_set_block_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t sites_per_wave,
-                              int32_t waves_per_group, int32_t tiled);
+                              int32_t waves_per_group, int32_t tiled, int32_t xcd_chunk);
 bsm_status bsm_get_block_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t *sites_per_wave,
-                              int32_t *waves_per_group, int32_t *tiled, float *us);
+                              int32_t *waves_per_group, int32_t *tiled, int32_t *xcd_chunk, float *us);
 /* Solve D(kappa_r) x_r = b_r for n_rhs right-hand sides with their own
  * kappa_r (Section II.B's inversion, for a family of masses).  b and x are
  * n_rhs consecutive full internal FP64 fields; U_rep64 are FP64 links.
  * Adjoint links: 16 RHS at a time share every link load on matrix cores
- * (FP32 recurrence captured as a HIP graph of check_every iterations, FP64
+ * (inner recurrence captured as a HIP graph of check_every iterations, FP64
  * reliable updates with threshold delta, each RHS retired once its FP64
- * true residual <= tol).  Other representations: one mixed-precision solve
+ * true residual <= tol); desc->prec = BSM_F16S runs the inner recurrence
+ * on FP16 block fields and links (x and r in FP32), any other precision on
+ * FP32 ones.  Other representations: one mixed-precision solve
  * per RHS at inner precision desc->prec.  stats: host array of n_rhs.
  * Synchronous. */
 bsm_status bsm_batched_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep64,

@@ -99,9 +99,9 @@ _SIGS = {
     "bsm_dslash_eo_block": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.c_int32, C.c_int32,
                                       C.POINTER(C.c_double), _vp, C.POINTER(C.c_double), _vp, _vp, _vp]),
     "bsm_block_autotune": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, _vp]),
-    "bsm_set_block_plan": (C.c_int, [_vp, C.POINTER(FieldDesc), C.c_int32, C.c_int32, C.c_int32]),
+    "bsm_set_block_plan": (C.c_int, [_vp, C.POINTER(FieldDesc), C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "bsm_get_block_plan": (C.c_int, [_vp, C.POINTER(FieldDesc), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                     C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
     "bsm_batched_solve": (C.c_int, [_vp, C.POINTER(FieldDesc), _vp, C.POINTER(SolverParams), C.c_int32,
                                     C.POINTER(C.c_double), _vp, _vp, C.POINTER(SolverStats), _vp]),
     "bsm_net_bytes": (C.c_size_t, [C.c_int32]),
@@ -326,15 +326,16 @@ class Context:
                "bsm_block_autotune")
         return self.bsm_get_block_plan(d)
 
-    def bsm_set_block_plan(self, d, sites_per_wave, waves_per_group, tiled=0):
+    def bsm_set_block_plan(self, d, sites_per_wave, waves_per_group, tiled=0, xcd_chunk=0):
         _check(lib().bsm_set_block_plan(self.handle, C.byref(d), int(sites_per_wave), int(waves_per_group),
-                                        int(tiled)), "bsm_set_block_plan")
+                                        int(tiled), int(xcd_chunk)), "bsm_set_block_plan")
 
     def bsm_get_block_plan(self, d):
-        s, w, t, us = C.c_int32(), C.c_int32(), C.c_int32(), C.c_float()
-        _check(lib().bsm_get_block_plan(self.handle, C.byref(d), C.byref(s), C.byref(w), C.byref(t), C.byref(us)),
-               "bsm_get_block_plan")
-        return dict(sites_per_wave=s.value, waves_per_group=w.value, tiled=t.value, us=us.value)
+        s, w, t, c, us = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_float()
+        _check(lib().bsm_get_block_plan(self.handle, C.byref(d), C.byref(s), C.byref(w), C.byref(t), C.byref(c),
+                                        C.byref(us)), "bsm_get_block_plan")
+        return dict(sites_per_wave=s.value, waves_per_group=w.value, tiled=t.value, xcd_chunk=c.value,
+                    us=us.value)
 
     def bsm_batched_solve(self, d, U_rep64, params: SolverParams, kappas, b, x, stream=None, check=True):
         n = len(kappas)

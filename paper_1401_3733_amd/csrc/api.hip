@@ -462,14 +462,21 @@ static bsm_status check_block(bsm_ctx ctx, const bsm_field_desc *desc) {
     return BSM_OK;
 }
 
+// FP16 block fields and links for an F16S descriptor, FP32 ones otherwise
+static bool block_half(const bsm_field_desc *desc) { return desc->prec == BSM_F16S; }
+
+static size_t block_parity_bytes_of(const Geom &g, const bsm_field_desc *desc) {
+    return block_half(desc) ? blockh_parity_bytes(g, desc->d_R) : block_parity_bytes(g, desc->d_R);
+}
+
 size_t bsm_block_bytes(bsm_ctx ctx, const bsm_field_desc *desc) {
     if (check_block(ctx, desc) != BSM_OK) return 0;
-    return 2 * block_parity_bytes(ctx->g, desc->d_R);
+    return 2 * block_parity_bytes_of(ctx->g, desc);
 }
 
 size_t bsm_block_gauge_bytes(bsm_ctx ctx, const bsm_field_desc *desc) {
     if (check_block(ctx, desc) != BSM_OK) return 0;
-    return block_link_bytes(ctx->g, desc->d_R);
+    return block_half(desc) ? blockh_link_bytes(ctx->g, desc->d_R) : block_link_bytes(ctx->g, desc->d_R);
 }
 
 bsm_status bsm_pack_block(bsm_ctx ctx, const bsm_field_desc *desc, int32_t n_rhs, const void *canon,
@@ -477,6 +484,8 @@ bsm_status bsm_pack_block(bsm_ctx ctx, const bsm_field_desc *desc, int32_t n_rhs
     CHECK(check_block(ctx, desc));
     if (!canon || !block) return fail(BSM_ERR_ARG, "null field pointer");
     if (n_rhs < 1 || n_rhs > kNR) return fail(BSM_ERR_ARG, "n_rhs must be in [1, 16]");
+    if (block_half(desc))
+        return launch_pack_blockh(ctx->g, desc->d_R, n_rhs, canon, block, false, (hipStream_t)stream);
     return launch_pack_block(ctx->g, desc->d_R, n_rhs, canon, block, false, (hipStream_t)stream);
 }
 
@@ -485,6 +494,9 @@ bsm_status bsm_unpack_block(bsm_ctx ctx, const bsm_field_desc *desc, int32_t n_r
     CHECK(check_block(ctx, desc));
     if (!canon || !block) return fail(BSM_ERR_ARG, "null field pointer");
     if (n_rhs < 1 || n_rhs > kNR) return fail(BSM_ERR_ARG, "n_rhs must be in [1, 16]");
+    if (block_half(desc))
+        return launch_pack_blockh(ctx->g, desc->d_R, n_rhs, canon, const_cast<void *>(block), true,
+                                  (hipStream_t)stream);
     return launch_pack_block(ctx->g, desc->d_R, n_rhs, canon, const_cast<void *>(block), true,
                              (hipStream_t)stream);
 }
@@ -493,6 +505,9 @@ bsm_status bsm_gauge_to_block(bsm_ctx ctx, const bsm_field_desc *desc, const voi
                               void *stream) {
     CHECK(check_block(ctx, desc));
     if (!U_rep || !U_block) return fail(BSM_ERR_ARG, "null field pointer");
+    if (block_half(desc))
+        return launch_gauge_to_blockh(ctx->g, desc->d_R, desc->link_prec, U_rep, (__half *)U_block,
+                                      (hipStream_t)stream);
     return launch_gauge_to_block(ctx->g, desc->d_R, desc->link_prec, U_rep, (float *)U_block,
                                  (hipStream_t)stream);
 }
@@ -504,10 +519,28 @@ bsm_status bsm_dslash_eo_block(bsm_ctx ctx, const bsm_field_desc *desc, const vo
     if (out_parity != 0 && out_parity != 1) return fail(BSM_ERR_ARG, "out_parity must be 0 or 1");
     if (!U_block || !in || !out || !b) return fail(BSM_ERR_ARG, "null pointer");
     if (a && !x) return fail(BSM_ERR_ARG, "x is null but a is given");
-    const size_t bb = block_parity_bytes(ctx->g, desc->d_R);
+    const size_t bb = block_parity_bytes_of(ctx->g, desc);
     const char *ip = (const char *)in;
     char *op = (char *)out;
     if (op < ip + bb && ip < op + bb) return fail(BSM_ERR_ARG, "in and out must not overlap");
+    const BlockPlan &plan = ctx->block_plans[desc->d_R][block_half(desc) ? 1 : 0];
+    if (block_half(desc)) {
+        BlockHopHArgs h{};
+        h.U = (const __half *)U_block;
+        h.in[out_parity] = ip;
+        h.x[out_parity] = (const char *)x;
+        h.out[out_parity] = op;
+        h.use_x = a ? 1 : 0;
+        for (int r = 0; r < kNR; r++) {
+            h.a[r] = a ? (float)a[r] : 0.f;
+            h.b[r] = (float)b[r];
+        }
+        h.dagger = dagger ? 1 : 0;
+        h.p0 = out_parity;
+        h.np = 1;
+        apply_blockh_plan(ctx->g, plan, h);
+        return launch_hop_blockh(ctx->g, desc->d_R, h, (hipStream_t)stream);
+    }
     BlockHopArgs h{};
     h.U = (const float *)U_block;
     h.in[out_parity] = (const float2 *)in;
@@ -521,47 +554,53 @@ bsm_status bsm_dslash_eo_block(bsm_ctx ctx, const bsm_field_desc *desc, const vo
     h.dagger = dagger ? 1 : 0;
     h.p0 = out_parity;
     h.np = 1;
-    h.spw = ctx->block_plans[desc->d_R].spw;
-    h.wpb = ctx->block_plans[desc->d_R].wpb;
-    if (ctx->block_plans[desc->d_R].tiled) h.tile = block_tile_for(ctx->g);
+    apply_block_plan(ctx->g, plan, h);
     return launch_hop_block(ctx->g, desc->d_R, h, (hipStream_t)stream);
 }
 
 bsm_status bsm_block_autotune(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_block, void *stream) {
     CHECK(check_block(ctx, desc));
     if (!U_block) return fail(BSM_ERR_ARG, "null pointer");
-    const size_t bb = block_parity_bytes(ctx->g, desc->d_R);
+    const size_t bb = block_parity_bytes_of(ctx->g, desc);
     void *w = nullptr;
     CHECK(ctx_work(ctx, 2 * bb + 256, &w));
-    float2 *in = (float2 *)w;
-    float2 *out = (float2 *)((char *)w + (bb + 255) / 256 * 256);
-    return block_autotune(ctx, desc->d_R, (const float *)U_block, in, out, (hipStream_t)stream);
+    char *in = (char *)w;
+    char *out = (char *)w + (bb + 255) / 256 * 256;
+    if (block_half(desc))
+        return blockh_autotune(ctx, desc->d_R, (const __half *)U_block, in, out, (hipStream_t)stream);
+    return block_autotune(ctx, desc->d_R, (const float *)U_block, (float2 *)in, (float2 *)out,
+                          (hipStream_t)stream);
 }
 
 bsm_status bsm_set_block_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t sites_per_wave,
-                              int32_t waves_per_group, int32_t tiled) {
+                              int32_t waves_per_group, int32_t tiled, int32_t xcd_chunk) {
     CHECK(check_block(ctx, desc));
     if (sites_per_wave != 1 && sites_per_wave != 2) return fail(BSM_ERR_ARG, "sites_per_wave must be 1 or 2");
+    if (sites_per_wave != 1 && block_half(desc))
+        return fail(BSM_ERR_ARG, "the FP16 block hop runs one site per wavefront");
     if (waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4)
         return fail(BSM_ERR_ARG, "waves_per_group must be 1, 2 or 4");
     if (tiled != 0 && tiled != 1) return fail(BSM_ERR_ARG, "tiled must be 0 or 1");
     if (tiled && block_tile_for(ctx->g).tt == 0)
         return fail(BSM_ERR_ARG, "tiled order needs T divisible by 2 or 3 and LY, LZ even");
-    BlockPlan &b = ctx->block_plans[desc->d_R];
+    if (xcd_chunk < 0 || xcd_chunk > 4096) return fail(BSM_ERR_ARG, "xcd_chunk must be in 0..4096");
+    BlockPlan &b = ctx->block_plans[desc->d_R][block_half(desc) ? 1 : 0];
     b.spw = sites_per_wave;
     b.wpb = waves_per_group;
     b.tiled = tiled;
+    b.xchunk = xcd_chunk;
     b.us = -1.f;   // set by hand: not tuned, and the batched solver keeps it
     return BSM_OK;
 }
 
 bsm_status bsm_get_block_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t *sites_per_wave,
-                              int32_t *waves_per_group, int32_t *tiled, float *us) {
+                              int32_t *waves_per_group, int32_t *tiled, int32_t *xcd_chunk, float *us) {
     CHECK(check_block(ctx, desc));
-    const BlockPlan &b = ctx->block_plans[desc->d_R];
+    const BlockPlan &b = ctx->block_plans[desc->d_R][block_half(desc) ? 1 : 0];
     if (sites_per_wave) *sites_per_wave = b.spw;
     if (waves_per_group) *waves_per_group = b.wpb;
     if (tiled) *tiled = b.tiled;
+    if (xcd_chunk) *xcd_chunk = b.xchunk;
     if (us) *us = b.us;
     return BSM_OK;
 }

@@ -52,9 +52,12 @@ struct BlockHopArgs {
     double *norm_partials;   // [workgroup][kNR]
     int spw = 1, wpb = 4;    // plan: sites per wavefront, wavefronts per workgroup
     BlockTile tile;          // plan: site order
+    int xchunk = 0;          // plan: workgroup run length per XCD (xcd_chunk_remap)
 };
 
 bsm_status launch_hop_block(const Geom &g, int d, const BlockHopArgs &a, hipStream_t st);
+// a tuned plan into the launch arguments
+void apply_block_plan(const Geom &g, const BlockPlan &p, BlockHopArgs &a);
 // workgroups (= norm partials) of a launch under its plan
 int hop_block_grid(const Geom &g, const BlockHopArgs &a);
 // largest partial count of any plan (one site per workgroup), per parity
@@ -63,6 +66,57 @@ inline int hop_block_grid_max(const Geom &g) { return g.Vh; }
 // fastest in ctx->block_plans[d]
 bsm_status block_autotune(bsm_ctx ctx, int d, const float *U_block, float2 *scratch_in, float2 *scratch_out,
                           hipStream_t st);
+
+// FP16 block fields (the batched solver's inner recurrence in F16S): per
+// parity block the codes [h][c < d][rhs][spin] half2 (16 bytes per colour and
+// RHS: the four spin components), then one float scale per site and RHS
+// [h][rhs].  A value is code * scale; scale = max |re|, |im| over the 4 d
+// components of that site and RHS, codes = rne_f16(v * (1 / scale)) (the
+// per-site F16S quantisation of the single-RHS fields, per RHS).
+__host__ __device__ inline size_t blockh_site_bytes(int d) { return (size_t)d * kNR * 16; }
+__host__ __device__ inline size_t blockh_scale_off(const Geom &g, int d) { return blockh_site_bytes(d) * g.Vh_pad; }
+__host__ __device__ inline size_t blockh_parity_bytes(const Geom &g, int d) { return (blockh_site_bytes(d) + kNR * 4) * g.Vh_pad; }
+// FP16 block links: row-major d x kpad halves (kpad = d rounded up to 4,
+// zero padded) per (parity, mu, site), in two orientations: [0] U, [1] U^T,
+// so that the matrix-core operand of the forward and of the backward hop is
+// one 8-byte load of a row either way.  [o][q * 4 + mu][h][i][k]
+constexpr int blockh_kpad(int d) { return (d + 3) & ~3; }
+inline size_t blockh_link_bytes(const Geom &g, int d) {
+    return (size_t)2 * 8 * g.Vh_pad * d * blockh_kpad(d) * 2;
+}
+
+struct BlockHopHArgs {
+    const __half *U;         // FP16 block links
+    const char *in[2];       // FP16 parity blocks
+    const char *x[2];
+    char *out[2];
+    float a[kNR], b[kNR];    // out_r = a_r x_r + b_r H in_r
+    int use_x;
+    int dagger;
+    int p0, np;
+    double *norm_partials;   // [workgroup][kNR]: |out_r|^2 of the stored (rounded) values
+    int wpb = 4;             // plan: wavefronts (= sites) per workgroup
+    BlockTile tile;          // plan: site order
+    int xchunk = 0;          // plan: workgroup run length per XCD (xcd_chunk_remap)
+};
+bsm_status launch_hop_blockh(const Geom &g, int d, const BlockHopHArgs &a, hipStream_t st);
+int hop_blockh_grid(const Geom &g, const BlockHopHArgs &a);
+void apply_blockh_plan(const Geom &g, const BlockPlan &p, BlockHopHArgs &a);
+bsm_status blockh_autotune(bsm_ctx ctx, int d, const __half *U_blockh, char *scratch_in, char *scratch_out,
+                           hipStream_t st);
+// represented links (LP F64 or F32) -> FP16 block links
+bsm_status launch_gauge_to_blockh(const Geom &g, int d, int link_prec, const void *U_rep, __half *U_blockh,
+                                  hipStream_t st);
+// canonical complex128 [n_rhs][V][4][d] <-> FP16 block field (both parities)
+bsm_status launch_pack_blockh(const Geom &g, int d, int n_rhs, const void *canon, void *block, bool unpack,
+                              hipStream_t st);
+// per-RHS vector kernels of the F16S inner recurrence (one parity block):
+// p16 = r32 + beta p16 ;  x32 += alpha p16, r32 -= alpha q16 with |r32|^2
+// partials [workgroup][kNR] (blockh_blas_grid workgroups)
+int blockh_blas_grid(const Geom &g);
+bsm_status blockh_xpay(const Geom &g, int d, char *p, const float2 *r, const double *beta, hipStream_t st);
+bsm_status blockh_update(const Geom &g, int d, float2 *x, const char *p, float2 *r, const char *q,
+                         const double *alpha, double *partials, hipStream_t st);
 
 // FP64 block fields (the batched solver's reliable updates): [h][c][spin][rhs]
 // double2, links [q][mu][h][i*d + j] double
@@ -79,6 +133,7 @@ struct BlockHop64Args {
     int dagger;
     int p0, np;
     BlockTile tile;          // site order (block_tile_for)
+    int xchunk = 0;          // workgroup run length per XCD (xcd_chunk_remap)
 };
 bsm_status launch_hop_block64(const Geom &g, int d, const BlockHop64Args &a, hipStream_t st);
 bsm_status launch_gauge_to_block64(const Geom &g, int d, const void *U_rep64, double *U_block, hipStream_t st);

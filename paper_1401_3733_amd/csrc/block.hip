@@ -13,51 +13,11 @@
 // 4(l/16)+v of the result: the per-RHS epilogue coefficients, the spin
 // reconstruction and the per-RHS norms never leave the lane.
 #include "block.h"
+#include "block_dev.h"
 #include "dispatch.h"
 #include "spinor_io.h"
 
 namespace bsm {
-
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-template <int MU>
-__device__ inline void project_c(const float2 (&s)[4], float sg, float2 &h0, float2 &h1) {
-    const float2 s0 = s[0], s1 = s[1], s2 = s[2], s3 = s[3];
-    if constexpr (MU == 0) {
-        h0 = make_float2(fmaf(-sg, s2.x, s0.x), fmaf(-sg, s2.y, s0.y));
-        h1 = make_float2(fmaf(-sg, s3.x, s1.x), fmaf(-sg, s3.y, s1.y));
-    } else if constexpr (MU == 1) {
-        h0 = make_float2(fmaf(-sg, s3.y, s0.x), fmaf(sg, s3.x, s0.y));
-        h1 = make_float2(fmaf(-sg, s2.y, s1.x), fmaf(sg, s2.x, s1.y));
-    } else if constexpr (MU == 2) {
-        h0 = make_float2(fmaf(sg, s3.x, s0.x), fmaf(sg, s3.y, s0.y));
-        h1 = make_float2(fmaf(-sg, s2.x, s1.x), fmaf(-sg, s2.y, s1.y));
-    } else {
-        h0 = make_float2(fmaf(-sg, s2.y, s0.x), fmaf(sg, s2.x, s0.y));
-        h1 = make_float2(fmaf(sg, s3.y, s1.x), fmaf(-sg, s3.x, s1.y));
-    }
-}
-
-// acc[spin][re/im] (rows 4q+v of colour) += hop contribution from G = U h
-template <int MU>
-__device__ inline void reconstruct_c(f4 (&acc)[4][2], float sg, float w, f4 g0r, f4 g0i, f4 g1r, f4 g1i) {
-    const float v = -sg * w;
-    acc[0][0] += w * g0r; acc[0][1] += w * g0i;
-    acc[1][0] += w * g1r; acc[1][1] += w * g1i;
-    if constexpr (MU == 0) {          // A^dag g = (g0, g1)
-        acc[2][0] += v * g0r; acc[2][1] += v * g0i;
-        acc[3][0] += v * g1r; acc[3][1] += v * g1i;
-    } else if constexpr (MU == 1) {   // (i g1, i g0)
-        acc[2][0] -= v * g1i; acc[2][1] += v * g1r;
-        acc[3][0] -= v * g0i; acc[3][1] += v * g0r;
-    } else if constexpr (MU == 2) {   // (g1, -g0)
-        acc[2][0] += v * g1r; acc[2][1] += v * g1i;
-        acc[3][0] -= v * g0r; acc[3][1] -= v * g0i;
-    } else {                          // (i g0, -i g1)
-        acc[2][0] -= v * g0i; acc[2][1] += v * g0r;
-        acc[3][0] += v * g1i; acc[3][1] -= v * g1r;
-    }
-}
 
 // Both hops along MU for the S sites of this wavefront (S independent MFMA
 // chains, so the loads of one site overlap the products of the other).
@@ -123,7 +83,7 @@ void k_hop_block(Geom g, BlockHopArgs a, int nblk) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wpb = blockDim.x >> 6;
     const int r = lane & 15, q = lane >> 4;
-    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t lb = xcd_chunk_remap(blockIdx.x, gridDim.x, (uint32_t)a.xchunk);
     const int pi = lb >= (uint32_t)nblk ? 1 : 0;
     const uint32_t base = (lb - pi * nblk) * (uint32_t)(wpb * S);
     const int p = a.p0 + pi;
@@ -204,6 +164,13 @@ BlockTile block_tile_for(const Geom &g) {
 
 static int block_sites_per_wg(const BlockHopArgs &a) { return a.wpb * a.spw; }
 
+void apply_block_plan(const Geom &g, const BlockPlan &p, BlockHopArgs &a) {
+    a.spw = p.spw;
+    a.wpb = p.wpb;
+    a.tile = p.tiled ? block_tile_for(g) : BlockTile{};
+    a.xchunk = p.xchunk;
+}
+
 int hop_block_grid(const Geom &g, const BlockHopArgs &a) {
     const int per = block_sites_per_wg(a);
     return (g.Vh + per - 1) / per * a.np;
@@ -243,6 +210,7 @@ bsm_status block_autotune(bsm_ctx ctx, int d, const float *U_block, float2 *scra
     bsm_status status = BSM_OK;
     const BlockTile tile = block_tile_for(g);
     for (int tiled = 0; tiled <= (tile.tt ? 1 : 0) && status == BSM_OK; tiled++)
+    for (int xchunk : {0, 1, 16})
     for (int spw = 1; spw <= 2 && status == BSM_OK; spw++) {
         for (int wpb : {1, 2, 4}) {
             BlockHopArgs a{};
@@ -254,6 +222,7 @@ bsm_status block_autotune(bsm_ctx ctx, int d, const float *U_block, float2 *scra
             for (int r = 0; r < kNR; r++) { a.a[r] = 0.f; a.b[r] = 1.f; }
             a.spw = spw;
             a.wpb = wpb;
+            a.xchunk = xchunk;
             if (tiled) a.tile = tile;
             const int reps = 5;
             if ((status = launch_hop_block(g, d, a, st)) != BSM_OK) break;   // warm-up
@@ -271,13 +240,14 @@ bsm_status block_autotune(bsm_ctx ctx, int d, const float *U_block, float2 *scra
                 best.spw = spw;
                 best.wpb = wpb;
                 best.tiled = tiled;
+                best.xchunk = xchunk;
                 best.us = us;
             }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (status == BSM_OK) ctx->block_plans[d] = best;
+    if (status == BSM_OK) ctx->block_plans[d][0] = best;
     return status;
 }
 

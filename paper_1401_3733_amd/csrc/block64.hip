@@ -104,7 +104,7 @@ void k_hop_block64(Geom g, BlockHop64Args a, int nblk) {
     constexpr size_t SITE = (size_t)D * 4 * kNR;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, q = lane >> 4;
-    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t lb = xcd_chunk_remap(blockIdx.x, gridDim.x, (uint32_t)a.xchunk);
     const int pi = lb >= (uint32_t)nblk ? 1 : 0;
     const uint32_t s = (lb - pi * nblk) * 4 + wave;
     const int p = a.p0 + pi;

@@ -150,6 +150,19 @@ __device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nblk) {
     return (b % kXcds) * per + b / kXcds;
 }
 
+// Workgroup order across the XCDs with a run length: c = 0 is xcd_remap (each
+// XCD one contiguous share of the grid); c > 0 deals each XCD runs of c
+// consecutive logical workgroups, so all XCDs work on nearby parts of the grid
+// at the same time and share the memory-side cache (c = 1: the hardware's own
+// round-robin order).  A bijection on [0, nblk).
+__device__ inline uint32_t xcd_chunk_remap(uint32_t b, uint32_t nblk, uint32_t c) {
+    if (c == 0) return xcd_remap(b, nblk);
+    const uint32_t span = c * kXcds, full = nblk / span * span;
+    if (b >= full) return b;
+    const uint32_t x = b % kXcds, k = b / kXcds;
+    return (k / c) * span + x * c + k % c;
+}
+
 // ------------------------------------------------------------ link storage
 // Internal link code of a descriptor: the link precision (bits 0-1), and for
 // fundamental storage of a higher representation (BSM_LINKS_FUNDAMENTAL) the
@@ -181,6 +194,7 @@ struct HopPlan {
 struct BlockPlan {
     int spw = 1, wpb = 4;
     int tiled = 0;    // 1: tiled site order (block_tile_for)
+    int xchunk = 0;   // workgroup run length per XCD (xcd_chunk_remap)
     float us = 0.f;   // measured time per hop when tuned (0: default plan)
 };
 
@@ -207,7 +221,7 @@ struct bsm_ctx_s {
     size_t pinned_bytes;
     hipStream_t solver_stream;
     bsm::HopPlan plans[16][2][3][6];   // [d_R][adjoint][spinor prec][link prec (+3: on the fly)]
-    bsm::BlockPlan block_plans[16];     // [d_R]
+    bsm::BlockPlan block_plans[16][2];  // [d_R][FP16 block fields]
 };
 
 namespace bsm {

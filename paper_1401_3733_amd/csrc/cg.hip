@@ -474,8 +474,10 @@ extern "C" bsm_status bsm_cg_solve(bsm_ctx ctx, const bsm_field_desc *desc, cons
 // ===================================================================== batched
 // Many right-hand sides D(kappa_r) x_r = b_r at once (even-odd Schur CG on
 // the normal equations, one kappa per RHS).  For real (adjoint) links the
-// recurrence runs on 16-RHS block fields in FP32 with the matrix-core hop,
-// so every link load serves all RHS; K iterations are captured once as a HIP
+// recurrence runs on 16-RHS block fields with the matrix-core hop, so every
+// link load serves all RHS: FP32 fields and links on FP32 matrix cores, or
+// (F16S) FP16 search directions and hop outputs with per-site scales, FP16
+// links and FP16 matrix cores, x and r kept in FP32; K iterations are captured once as a HIP
 // graph and replayed.  Every RHS keeps its own alpha, beta and |r|^2 on the
 // device; between replays the host folds the FP32 solutions into the FP64
 // ones, recomputes in FP64 the residual of every RHS whose |r| dropped by
@@ -495,7 +497,8 @@ struct BlockSolve {
     const double *kappas;
     const char *b;
     char *x;
-    size_t full64, bb64, bbB;
+    size_t full64, bb64, bbB, bbH;
+    bool half;   // F16S inner recurrence (FP16 block fields)
     // FP64 per RHS
     std::vector<Op> ops;
     char *t64, *tfull, *tmp64;
@@ -503,42 +506,64 @@ struct BlockSolve {
     // FP64 block fields for the reliable updates (all RHS share each link load)
     double *Ublk64;
     double2 *X64, *BH64, *T1, *T2, *T3;
-    // FP32 block fields
+    // inner block fields: p, t, q and the odd intermediate tmpB in the inner
+    // precision (FP32 or FP16), x and r in FP32; links FP32 or FP16
     float *Ublk;
-    float2 *p, *t, *q, *xlo, *rlo, *tmpB;
+    __half *Uh;
+    char *p, *t, *q, *tmpB;
+    float2 *xlo, *rlo;
     double *partials, *scal, *presum;
     int *mask;
     hipGraphExec_t graph = nullptr;
     int K;
+    BlockPlan &plan() const { return ctx->block_plans[d][half ? 1 : 0]; }
 };
 
-static bsm_status block_op(BlockSolve &B, int dagger, const float2 *in, float2 *out, bool norm, int *nparts) {
-    BlockHopArgs a{};
-    a.U = B.Ublk;
+// the two hops of the Schur operator (or its adjoint) on inner block fields:
+// tmp_o = H_oe in_e ;  out_e = in_e - kappa_r^2 H_eo tmp_o
+template <class Args>
+static void block_op_args(BlockSolve &B, int dagger, Args &a, Args &c) {
     a.dagger = dagger;
     a.np = 1;
-    a.spw = B.ctx->block_plans[B.d].spw;
-    a.wpb = B.ctx->block_plans[B.d].wpb;
-    if (B.ctx->block_plans[B.d].tiled) a.tile = block_tile_for(B.g);
-    // tmp_o = H_oe in_e
     a.p0 = 1;
-    a.in[1] = in;
-    a.out[1] = B.tmpB;
     a.use_x = 0;
     for (int r = 0; r < kNR; r++) { a.a[r] = 0.f; a.b[r] = 1.f; }
-    TRY(launch_hop_block(B.g, B.d, a, B.st));
-    // out_e = in_e - kappa_r^2 H_eo tmp_o
-    BlockHopArgs c = a;
+    c = a;
     c.p0 = 0;
-    c.in[0] = B.tmpB;
-    c.x[0] = in;
-    c.out[0] = out;
     c.use_x = 1;
     for (int r = 0; r < kNR; r++) {
         const double k = r < B.n ? B.kappas[r] : 0.0;
         c.a[r] = 1.f;
         c.b[r] = (float)(-k * k);
     }
+}
+
+static bsm_status block_op(BlockSolve &B, int dagger, const char *in, char *out, bool norm, int *nparts) {
+    if (B.half) {
+        BlockHopHArgs a{}, c{};
+        a.U = B.Uh;
+        apply_blockh_plan(B.g, B.plan(), a);
+        block_op_args(B, dagger, a, c);
+        a.in[1] = in;
+        a.out[1] = B.tmpB;
+        TRY(launch_hop_blockh(B.g, B.d, a, B.st));
+        c.in[0] = B.tmpB;
+        c.x[0] = in;
+        c.out[0] = out;
+        c.norm_partials = norm ? B.partials : nullptr;
+        if (nparts) *nparts = hop_blockh_grid(B.g, c);
+        return launch_hop_blockh(B.g, B.d, c, B.st);
+    }
+    BlockHopArgs a{}, c{};
+    a.U = B.Ublk;
+    apply_block_plan(B.g, B.plan(), a);
+    block_op_args(B, dagger, a, c);
+    a.in[1] = (const float2 *)in;
+    a.out[1] = (float2 *)B.tmpB;
+    TRY(launch_hop_block(B.g, B.d, a, B.st));
+    c.in[0] = (const float2 *)B.tmpB;
+    c.x[0] = (const float2 *)in;
+    c.out[0] = (float2 *)out;
     c.norm_partials = norm ? B.partials : nullptr;
     if (nparts) *nparts = hop_block_grid(B.g, c);
     return launch_hop_block(B.g, B.d, c, B.st);
@@ -550,8 +575,9 @@ static bsm_status block_op64(BlockSolve &B, int dagger, const double2 *in, doubl
     BlockHop64Args a{};
     a.U = B.Ublk64;
     a.dagger = dagger;
-    // the FP64 blocks follow the site order tuned for the FP32 ones
-    if (B.ctx->block_plans[B.d].tiled) a.tile = block_tile_for(B.g);
+    // the FP64 blocks follow the site and workgroup orders tuned for the inner ones
+    if (B.plan().tiled) a.tile = block_tile_for(B.g);
+    a.xchunk = B.plan().xchunk;
     a.np = 1;
     a.p0 = 1;
     a.in[1] = in;
@@ -576,13 +602,20 @@ static bsm_status block_op64(BlockSolve &B, int dagger, const double2 *in, doubl
 // q = M^dag t ; x += alpha p ; r -= alpha q ; beta, |r|^2 -> history slot k
 static bsm_status block_iteration(BlockSolve &B, int k) {
     const Geom &g = B.g;
-    TRY(block_xpay(g, B.d, 1, B.p, B.rlo, B.scal + B_BETA * kNR, B.st));
+    if (B.half) TRY(blockh_xpay(g, B.d, B.p, B.rlo, B.scal + B_BETA * kNR, B.st));
+    else TRY(block_xpay(g, B.d, 1, (float2 *)B.p, B.rlo, B.scal + B_BETA * kNR, B.st));
     int np = 0;
     TRY(block_op(B, 0, B.p, B.t, true, &np));
     TRY(block_scalars(B.partials, np, B.scal, B.mask, 0, 0, B.presum, B.st));
     TRY(block_op(B, 1, B.t, B.q, false, nullptr));
-    TRY(block_update(g, B.d, 1, B.xlo, B.p, B.rlo, B.q, B.scal + B_ALPHA * kNR, B.partials, B.st));
-    TRY(block_scalars(B.partials, block_blas_grid(g, B.d, 1), B.scal, B.mask, 1, k, B.presum, B.st));
+    if (B.half) {
+        TRY(blockh_update(g, B.d, B.xlo, B.p, B.rlo, B.q, B.scal + B_ALPHA * kNR, B.partials, B.st));
+        TRY(block_scalars(B.partials, blockh_blas_grid(g), B.scal, B.mask, 1, k, B.presum, B.st));
+    } else {
+        TRY(block_update(g, B.d, 1, B.xlo, (const float2 *)B.p, B.rlo, (const float2 *)B.q,
+                         B.scal + B_ALPHA * kNR, B.partials, B.st));
+        TRY(block_scalars(B.partials, block_blas_grid(g, B.d, 1), B.scal, B.mask, 1, k, B.presum, B.st));
+    }
     return BSM_OK;
 }
 
@@ -591,21 +624,25 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
     const int d = B.d, n = B.n;
     hipStream_t st = B.st;
     // ---- work memory
-    const size_t linkB = block_link_bytes(g, d);
+    const size_t linkB = B.half ? blockh_link_bytes(g, d) : block_link_bytes(g, d);
+    const size_t bbI = B.half ? B.bbH : B.bbB;   // inner-precision block fields
     // partials for any plan (the autotuner below may change it)
-    const size_t parts = std::max((size_t)hop_block_grid_max(g), (size_t)block_blas_grid(g, d, 1)) * kNR;
+    const size_t parts = std::max({(size_t)hop_block_grid_max(g), (size_t)block_blas_grid(g, d, 1),
+                                   (size_t)blockh_blas_grid(g)}) * kNR;
     // 20 carve-outs below, each rounded up to 256 bytes
     const size_t link64 = block64_link_bytes(g, d), bb64B = block64_parity_bytes(g, d);
-    size_t need = linkB + 6 * B.bbB + (size_t)4 * B.bb64 + parts * 8 +
+    size_t need = linkB + 4 * bbI + 2 * B.bbB + (size_t)4 * B.bb64 + parts * 8 +
                   (size_t)kBlockPresum * kNR * 8 + block_scal_doubles() * 8 + 64 * sizeof(int) + link64 +
                   5 * bb64B + 22 * 256;
     void *work = nullptr;
     TRY(ctx_work(B.ctx, need, &work));
     char *w = (char *)work;
     auto take = [&](size_t bytes) { char *r = w; w += (bytes + 255) / 256 * 256; return r; };
-    B.Ublk = (float *)take(linkB);
-    B.p = (float2 *)take(B.bbB); B.t = (float2 *)take(B.bbB); B.q = (float2 *)take(B.bbB);
-    B.xlo = (float2 *)take(B.bbB); B.rlo = (float2 *)take(B.bbB); B.tmpB = (float2 *)take(B.bbB);
+    char *links = take(linkB);
+    B.Ublk = B.half ? nullptr : (float *)links;
+    B.Uh = B.half ? (__half *)links : nullptr;
+    B.p = take(bbI); B.t = take(bbI); B.q = take(bbI); B.tmpB = take(bbI);
+    B.xlo = (float2 *)take(B.bbB); B.rlo = (float2 *)take(B.bbB);
     B.t64 = take(B.bb64); B.tmp64 = take(B.bb64); B.tfull = take(2 * B.bb64);
     B.partials = (double *)take(parts * 8);
     B.presum = (double *)take((size_t)kBlockPresum * kNR * 8);
@@ -615,11 +652,15 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
     B.X64 = (double2 *)take(bb64B); B.BH64 = (double2 *)take(bb64B);
     B.T1 = (double2 *)take(bb64B); B.T2 = (double2 *)take(bb64B); B.T3 = (double2 *)take(bb64B);
     // ---- links in block layout, per-RHS FP64 operators and right-hand sides
-    TRY(launch_gauge_to_block(g, d, BSM_F64, B.ops[0].U, B.Ublk, st));
+    if (B.half) TRY(launch_gauge_to_blockh(g, d, BSM_F64, B.ops[0].U, B.Uh, st));
+    else TRY(launch_gauge_to_block(g, d, BSM_F64, B.ops[0].U, B.Ublk, st));
     TRY(launch_gauge_to_block64(g, d, B.ops[0].U, B.Ublk64, st));
-    // first batched solve for this d_R on the context: tune the block hop plan
-    // (t and q are outputs of every iteration, free to use as scratch here)
-    if (B.ctx->block_plans[d].us == 0.f) TRY(block_autotune(B.ctx, d, B.Ublk, B.t, B.q, st));
+    // first batched solve for this d_R and precision on the context: tune the
+    // block hop plan (t and q are outputs of every iteration, free as scratch)
+    if (B.plan().us == 0.f) {
+        if (B.half) TRY(blockh_autotune(B.ctx, d, B.Uh, B.t, B.q, st));
+        else TRY(block_autotune(B.ctx, d, B.Ublk, (float2 *)B.t, (float2 *)B.q, st));
+    }
     BSM_HIP(hipMemsetAsync(B.x, 0, n * B.full64, st));
     B.bnorm2.assign(n, 0.0);
     B.rhs_norm2.assign(n, 0.0);
@@ -635,7 +676,8 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
         a.x[p0] = xin;
         a.out[p0] = out;
         a.use_x = 1;
-        if (B.ctx->block_plans[d].tiled) a.tile = block_tile_for(g);
+        if (B.plan().tiled) a.tile = block_tile_for(g);
+        a.xchunk = B.plan().xchunk;
         for (int r = 0; r < kNR; r++) {
             a.a[r] = 1.0;
             a.b[r] = r < n ? sgn * B.kappas[r] : 0.0;
@@ -717,7 +759,7 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
     };
     TRY(refresh(all));
     BSM_HIP(hipMemsetAsync(B.xlo, 0, B.bbB, st));
-    BSM_HIP(hipMemsetAsync(B.p, 0, B.bbB, st));
+    BSM_HIP(hipMemsetAsync(B.p, 0, bbI, st));
     // pinned host mirrors of the device scalars and mask (context scratch)
     void *pin = nullptr;
     const size_t hs_bytes = (block_scal_doubles() * 8 + 255) / 256 * 256;
@@ -921,6 +963,8 @@ extern "C" bsm_status bsm_batched_solve(bsm_ctx ctx, const bsm_field_desc *desc,
         B.full64 = 2 * bb64;
         B.bb64 = bb64;
         B.bbB = block_parity_bytes(g, d);
+        B.bbH = blockh_parity_bytes(g, d);
+        B.half = desc->prec == BSM_F16S;
         for (int r = 0; r < B.n; r++) {
             Op o{};
             o.ctx = ctx; o.g = g; o.d = d; o.real = true; o.schur = true; o.kappa = B.kappas[r];
