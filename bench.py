@@ -522,7 +522,18 @@ def bench_cfg4(bsm, gen):
     tb = stats[0]["seconds"]
     plan = ctx.bsm_get_block_plan(d64)
     log(f"  {tb:.3f} s, iters {[s['iters'] for s in stats]}, block plan {plan}")
-    tseq, its, worst = 0.0, [], 0.0
+    # the same solve with the F16S inner recurrence (FP16 block fields, links
+    # and matrix cores; FP64 reliable updates and true residuals)
+    dh = bsm.desc(4, "adj", "f16s", "f64")
+    xh = torch.zeros_like(b)
+    log("cfg4 batched F16S (warm-up call) ...")
+    ctx.bsm_batched_solve(dh, U, prm, kappas, b, xh, check=False)
+    log("cfg4 batched F16S ...")
+    sth, statsh = ctx.bsm_batched_solve(dh, U, prm, kappas, b, xh, check=False)
+    tbh = statsh[0]["seconds"]
+    planh = ctx.bsm_get_block_plan(dh)
+    log(f"  {tbh:.3f} s, iters {[s['iters'] for s in statsh]}, block plan {planh}")
+    tseq, its, worst, worst_h = 0.0, [], 0.0, 0.0
     log("cfg4 sequential plain FP64 ...")
     # one untimed solve first (the context's plain-CG scratch is allocated there)
     ctx.bsm_cg_solve(d64, U, U, bsm.solver_params(kappas[0], 1e-10, schur=True), b[0:fb], xs[0:fb], check=False)
@@ -533,6 +544,7 @@ def bench_cfg4(bsm, gen):
         tseq += st1["seconds"]
         its.append(st1["iters"])
         worst = max(worst, rel_diff(ctx, d64, xb[sl], xs[sl]))
+        worst_h = max(worst_h, rel_diff(ctx, d64, xh[sl], xs[sl]))
     log(f"  {tseq:.3f} s, iters {its}")
     # the 16-RHS block hop on its own, under the plan the batched solve tuned,
     # on block fields holding the 16 sources
@@ -557,6 +569,29 @@ def bench_cfg4(bsm, gen):
                  "bytes_model": "8 real FP32 d x d links + 16 x (input + output) FP32 spinors per output site"}
     log(f"  {block_hop}")
     del A, B, Ub
+    # the FP16 block hop under the plan the F16S batched solve tuned
+    Uh = ctx.new_block_gauge(dh)
+    ctx.bsm_gauge_to_block(dh, U, Uh)
+    canon = torch.zeros((n, lat.V, 4, 15), dtype=torch.complex128, device="cuda")
+    for r in range(n):
+        ctx.bsm_unpack_spinor(d64, b[r * fb:(r + 1) * fb], canon[r])
+    A, B = ctx.new_block(dh), ctx.new_block(dh)
+    ctx.bsm_pack_block(dh, canon, A, n)
+    del canon
+    torch.cuda.synchronize()
+    log("cfg4 FP16 block hop timing ...")
+    ms = time_block_hops(ctx, dh, Uh, A, B, 40)
+    # links: 8 FP16 d x d (the zero padding of the rows to 16 is not counted);
+    # spinors: 16 RHS x 4 d complex FP16 codes + 16 float scales, in and out
+    nbytes_h = (8 * 15 * 15 * 2 + 2 * (16 * 4 * 15 * 4 + 16 * 4)) * Vh
+    block_hop_h = {"us": round(ms * 1e3, 2), "gbs": round(nbytes_h / ms / 1e6, 1),
+                   "frac": round(nbytes_h / ms / 1e6 / PEAK_HBM_GBS, 4), "tflops": round(flops / ms / 1e9, 2),
+                   "bytes": nbytes_h, "plan": ctx.bsm_get_block_plan(dh),
+                   "speedup_vs_fp32_block_hop": round(block_hop["us"] / (ms * 1e3), 3),
+                   "bytes_model": "8 FP16 d x d links (row padding not counted) + 16 x (input + output) FP16 "
+                                  "spinors with a float scale per site and RHS, per output site"}
+    log(f"  {block_hop_h}")
+    del A, B, Uh
     # the shifted family: one source (the first RHS), all 16 kappas in one
     # Krylov space, against 16 sequential plain FP64 solves of that source
     log("cfg4 shifted family (one source, 16 kappas; warm-up call first) ...")
@@ -593,10 +628,16 @@ def bench_cfg4(bsm, gen):
            "batched": dict(status=st, seconds=round(tb, 4), iters=[s["iters"] for s in stats], block_plan=plan,
                            max_true_rel_res=max(s["true_rel_res"] for s in stats),
                            reliable_updates=[s["reliable_updates"] for s in stats]),
+           "batched_f16s": dict(status=sth, seconds=round(tbh, 4), iters=[s["iters"] for s in statsh],
+                                block_plan=planh, max_true_rel_res=max(s["true_rel_res"] for s in statsh),
+                                reliable_updates=[s["reliable_updates"] for s in statsh],
+                                speedup_vs_plain_f64=round(tseq / tbh, 3) if tbh > 0 else None,
+                                max_x_rel_diff_vs_plain=worst_h),
            "sequential_plain_f64": dict(seconds=round(tseq, 4), iters=its),
            "speedup_vs_plain_f64": round(tseq / tb, 3) if tb > 0 else None,
            "max_x_rel_diff_vs_plain": worst,
            "block_hop": block_hop,
+           "block_hop_f16": block_hop_h,
            "shifted_family": shifted,
            "conditioning": cond}
     ctx.close()

@@ -79,10 +79,16 @@ __host__ __device__ inline size_t blockh_parity_bytes(const Geom &g, int d) { re
 // FP16 block links: row-major d x kpad halves (kpad = d rounded up to 4,
 // zero padded) per (parity, mu, site), in two orientations: [0] U, [1] U^T,
 // so that the matrix-core operand of the forward and of the backward hop is
-// one 8-byte load of a row either way.  [o][q * 4 + mu][h][i][k]
+// one 8-byte load of a row either way.  [o][q * 4 + mu][h][i][k], one link
+// every blockh_link_halves(d) halves: links of 128 bytes or more start on a
+// 128-byte cache line (d = 15: 480 -> 512 bytes), so a streamed link never
+// shares a line with the next one.
 constexpr int blockh_kpad(int d) { return (d + 3) & ~3; }
+__host__ __device__ constexpr int blockh_link_halves(int d) {
+    return d * blockh_kpad(d) * 2 < 128 ? d * blockh_kpad(d) : (d * blockh_kpad(d) * 2 + 127) / 128 * 64;
+}
 inline size_t blockh_link_bytes(const Geom &g, int d) {
-    return (size_t)2 * 8 * g.Vh_pad * d * blockh_kpad(d) * 2;
+    return (size_t)2 * 8 * g.Vh_pad * blockh_link_halves(d) * 2;
 }
 
 struct BlockHopHArgs {

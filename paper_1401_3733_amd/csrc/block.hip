@@ -115,7 +115,17 @@ void k_hop_block(Geom g, BlockHopArgs a, int nblk) {
         for (int j = 0; j < S; j++) {
             if (!live[j]) continue;
             float2 *o = a.out[p] + (size_t)h[j] * SITE;
-            const float2 *x = a.use_x ? a.x[p] + (size_t)h[j] * SITE : nullptr;
+            // x first, every load unconditional (rows i >= D read row D - 1
+            // and are not stored): a load inside the divergent i < D branch
+            // would be waited for there, one memory latency per element
+            float2 xv[4][4];
+            if (a.use_x) {
+                const float2 *x = a.x[p] + (size_t)h[j] * SITE;
+#pragma unroll
+                for (int v = 0; v < 4; v++)
+#pragma unroll
+                    for (int sp = 0; sp < 4; sp++) xv[v][sp] = x[(size_t)(min(4 * q + v, D - 1) * 4 + sp) * kNR + r];
+            }
 #pragma unroll
             for (int v = 0; v < 4; v++) {
                 const int i = 4 * q + v;
@@ -124,10 +134,9 @@ void k_hop_block(Geom g, BlockHopArgs a, int nblk) {
                     for (int sp = 0; sp < 4; sp++) {
                         const size_t e = (size_t)(i * 4 + sp) * kNR + r;
                         float re = br * acc[j][sp][0][v], im = br * acc[j][sp][1][v];
-                        if (x) {
-                            const float2 xv = x[e];
-                            re = fmaf(ar, xv.x, re);
-                            im = fmaf(ar, xv.y, im);
+                        if (a.use_x) {
+                            re = fmaf(ar, xv[v][sp].x, re);
+                            im = fmaf(ar, xv[v][sp].y, im);
                         }
                         o[e] = make_float2(re, im);
                         nrm += (double)re * re + (double)im * im;

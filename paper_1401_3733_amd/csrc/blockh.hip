@@ -15,6 +15,8 @@
 // the neighbour multiplies column j of the product, i.e. one factor per lane.
 // Products of FP16 operands are exact in FP32; the projected half spinor is
 // rounded to FP16 (relative 2^-11), the same order as the storage rounding.
+#include <type_traits>
+
 #include "block.h"
 #include "block_dev.h"
 #include "dispatch.h"
@@ -74,15 +76,17 @@ __device__ inline double store_site_h(char *blk, size_t scale_off, uint32_t h, i
     return nrm;
 }
 
-// the colours 4q + s (s < 4) of one site and RHS, decoded
+// the colours 4q + s (s < 4) of one site and RHS, decoded (slots of colours
+// >= D hold a copy of colour D - 1)
 template <int D>
 __device__ inline void load_site_h(const char *blk, size_t scale_off, uint32_t h, int r, int q, float2 (&v)[4][4]) {
     const uint4 *ip = (const uint4 *)(blk + (size_t)h * blockh_site_bytes(D)) + r;
     const float sc = ((const float *)(blk + scale_off))[(size_t)h * kNR + r];
+    // colours >= D load colour D - 1 (unconditional loads; the caller never
+    // stores or sums those slots)
 #pragma unroll
     for (int s = 0; s < 4; s++) {
-        const int c = 4 * q + s;
-        const uint4 w = c < D ? ip[c * kNR] : make_uint4(0, 0, 0, 0);
+        const uint4 w = ip[min(4 * q + s, D - 1) * kNR];
         const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
         for (int sp = 0; sp < 4; sp++) {
@@ -92,54 +96,110 @@ __device__ inline void load_site_h(const char *blk, size_t scale_off, uint32_t h
     }
 }
 
-// Both hops along MU of one site
-template <int MU, int D>
-__device__ inline void hop_dir_blockh(const Geom &g, const BlockHopHArgs &a, const Coords &c, int p, uint32_t h,
-                                      int r, int q, float eta, size_t scale_off, f4 (&acc)[4][2]) {
+// Operands of one hop K = 2 mu + (backward ? 1 : 0) of one site: the four
+// colours 4q + 0..3 of the neighbour for RHS r (16 bytes each), its scale,
+// the link row (8 bytes) and the boundary weight.
+struct HopHOps {
+    uint4 sv[4];
+    u32x2 lk;
+    float scl, w;
+};
+
+template <int K, int D>
+__device__ inline void hoph_load(const Geom &g, const BlockHopHArgs &a, const Coords &c, int p, uint32_t h, int r,
+                                 int q, size_t scale_off, HopHOps &o) {
+    constexpr int MU = K >> 1;
+    constexpr bool back = (K & 1) != 0;
     constexpr int KP = blockh_kpad(D);
     const char *in = a.in[p];
-    const float *isc = (const float *)(in + scale_off);
-#pragma unroll 1
-    for (int dir = 0; dir < 2; dir++) {
-        const bool back = dir == 1;
-        float w;
-        const uint32_t hn = neighbour<MU>(g, c, back, w);
-        const uint4 *sp = (const uint4 *)(in + (size_t)hn * blockh_site_bytes(D)) + r;
-        uint4 sv[4];
+    const uint32_t hn = neighbour<MU>(g, c, back, o.w);
+    const uint4 *sp = (const uint4 *)(in + (size_t)hn * blockh_site_bytes(D)) + r;
+    // Every load is unconditional, at a clamped index, so that no load sits in
+    // a divergent branch (the compiler waits for such a load inside its
+    // branch, which serialises the hops).  A colour k >= D loads colour D - 1:
+    // its product is zero, as the link columns k >= D are zero (padding, or
+    // the operand masked in hoph_apply); a row i >= D loads row D - 1 and
+    // gives result rows that are never stored.
+    // scale first: loads complete in order, and the scale is the last
+    // operand the products need
+    o.scl = ((const float *)(in + scale_off))[(size_t)hn * kNR + r];
+    const int qm = (back ? 1 - p : p) * 4 + MU;
+    const __half *L = a.U + ((size_t)((back ? 8 : 0) + qm) * g.Vh_pad + (back ? hn : h)) * blockh_link_halves(D) +
+                      min(r, D - 1) * KP + 4 * min(q, (D - 1) / 4);
+    o.lk = __builtin_nontemporal_load((const u32x2 *)L);
 #pragma unroll
-        for (int s = 0; s < 4; s++) {
-            const int cc = 4 * q + s;
-            sv[s] = cc < D ? sp[cc * kNR] : make_uint4(0, 0, 0, 0);
-        }
-        const float scl = isc[(size_t)hn * kNR + r];
-        u32x2 lk = {0u, 0u};
-        if (r < D && 4 * q < D) {
-            const int qm = (back ? 1 - p : p) * 4 + MU;
-            const __half *L =
-                a.U + ((size_t)((back ? 8 : 0) + qm) * g.Vh_pad + (back ? hn : h)) * (D * KP) + r * KP + 4 * q;
-            lk = __builtin_nontemporal_load((const u32x2 *)L);
-        }
-        const float sg = back ? -eta : eta;
-        h4 b0r, b0i, b1r, b1i;
+    for (int s = 0; s < 4; s++) o.sv[s] = sp[min(4 * q + s, D - 1) * kNR];
+}
+
+template <int K, int D>
+__device__ inline void hoph_apply(const HopHOps &o, int q, float eta, f4 (&acc)[4][2]) {
+    constexpr int MU = K >> 1;
+    const float sg = (K & 1) ? -eta : eta;
+    h4 b0r, b0i, b1r, b1i;
 #pragma unroll
-        for (int s = 0; s < 4; s++) {
-            const float2 s4[4] = {half2_to_f(sv[s].x), half2_to_f(sv[s].y), half2_to_f(sv[s].z),
-                                  half2_to_f(sv[s].w)};
-            float2 h0, h1;
-            project_c<MU>(s4, sg, h0, h1);
-            b0r[s] = (_Float16)h0.x;
-            b0i[s] = (_Float16)h0.y;
-            b1r[s] = (_Float16)h1.x;
-            b1i[s] = (_Float16)h1.y;
-        }
-        const h4 A = __builtin_bit_cast(h4, lk);
-        const f4 z = {0.f, 0.f, 0.f, 0.f};
-        const f4 g0r = __builtin_amdgcn_mfma_f32_16x16x16f16(A, b0r, z, 0, 0, 0);
-        const f4 g0i = __builtin_amdgcn_mfma_f32_16x16x16f16(A, b0i, z, 0, 0, 0);
-        const f4 g1r = __builtin_amdgcn_mfma_f32_16x16x16f16(A, b1r, z, 0, 0, 0);
-        const f4 g1i = __builtin_amdgcn_mfma_f32_16x16x16f16(A, b1i, z, 0, 0, 0);
-        reconstruct_c<MU>(acc, sg, w * scl, g0r, g0i, g1r, g1i);
+    for (int s = 0; s < 4; s++) {
+        const float2 s4[4] = {half2_to_f(o.sv[s].x), half2_to_f(o.sv[s].y), half2_to_f(o.sv[s].z),
+                              half2_to_f(o.sv[s].w)};
+        float2 h0, h1;
+        project_c<MU>(s4, sg, h0, h1);
+        b0r[s] = (_Float16)h0.x;
+        b0i[s] = (_Float16)h0.y;
+        b1r[s] = (_Float16)h1.x;
+        b1i[s] = (_Float16)h1.y;
     }
+    u32x2 lk = o.lk;
+    if constexpr (D <= 12) {   // column groups 4q >= D hold no link columns
+        lk.x = 4 * q < D ? lk.x : 0u;
+        lk.y = 4 * q < D ? lk.y : 0u;
+    }
+    const h4 A = __builtin_bit_cast(h4, lk);
+    const f4 z = {0.f, 0.f, 0.f, 0.f};
+    const f4 g0r = __builtin_amdgcn_mfma_f32_16x16x16f16(A, b0r, z, 0, 0, 0);
+    const f4 g0i = __builtin_amdgcn_mfma_f32_16x16x16f16(A, b0i, z, 0, 0, 0);
+    const f4 g1r = __builtin_amdgcn_mfma_f32_16x16x16f16(A, b1r, z, 0, 0, 0);
+    const f4 g1i = __builtin_amdgcn_mfma_f32_16x16x16f16(A, b1i, z, 0, 0, 0);
+    reconstruct_c<MU>(acc, sg, o.w * o.scl, g0r, g0i, g1r, g1i);
+}
+
+template <int B, int E, class F>
+__device__ inline void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// The eight hops of one site in groups of NB: the loads of a whole group
+// are issued before its products, so NB neighbour fetches are in flight per
+// wavefront (the operands of one hop are 19 registers).  Measured at
+// 24^3 x 48, d_R = 15: NB = 2 1144 us, 4 1163 us, 8 1430 us (occupancy 4,
+// 3, 2 wavefronts per SIMD).
+constexpr int kHopHDepth = 2;
+
+template <int D>
+__device__ inline void hoph_site(const Geom &g, const BlockHopHArgs &a, const Coords &c, int p, uint32_t h, int r,
+                                 int q, float eta, size_t scale_off, f4 (&acc)[4][2]) {
+    constexpr int NB = kHopHDepth;
+    static_assert(8 % NB == 0, "hop groups must divide the eight hops");
+    static_for<0, 8 / NB>([&](auto gi) {
+        constexpr int base = decltype(gi)::value * NB;
+        HopHOps o[NB];
+        static_for<0, NB>([&](auto j) {
+            hoph_load<base + decltype(j)::value, D>(g, a, c, p, h, r, q, scale_off, o[decltype(j)::value]);
+        });
+        static_for<0, NB>([&](auto j) { hoph_apply<base + decltype(j)::value, D>(o[decltype(j)::value], q, eta, acc); });
+        // The group's sums are complete here: the empty statements pin the
+        // accumulators to this point (the optimiser would otherwise sink every
+        // hop's reconstruction to the end of the site and hold all 32 products
+        // at once), and the barrier keeps the next group's loads after this
+        // group's products.
+#pragma unroll
+        for (int sp = 0; sp < 4; sp++) {
+            asm volatile("" : "+v"(acc[sp][0]));
+            asm volatile("" : "+v"(acc[sp][1]));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    });
 }
 
 // One wavefront per site, WPB = blockDim.x / 64 sites per workgroup.
@@ -161,10 +221,7 @@ __global__ __launch_bounds__(256) void k_hop_blockh(Geom g, BlockHopHArgs a, int
         for (int sp = 0; sp < 4; sp++) acc[sp][0] = acc[sp][1] = f4{0.f, 0.f, 0.f, 0.f};
         const Coords c = decode(g, h, p);
         const float eta = a.dagger ? -1.f : 1.f;
-        hop_dir_blockh<0, D>(g, a, c, p, h, r, q, eta, scale_off, acc);
-        hop_dir_blockh<1, D>(g, a, c, p, h, r, q, eta, scale_off, acc);
-        hop_dir_blockh<2, D>(g, a, c, p, h, r, q, eta, scale_off, acc);
-        hop_dir_blockh<3, D>(g, a, c, p, h, r, q, eta, scale_off, acc);
+        hoph_site<D>(g, a, c, p, h, r, q, eta, scale_off, acc);
         float2 v[4][4];
         if (a.use_x) load_site_h<D>(a.x[p], scale_off, h, r, q, v);
         const float ar = a.use_x ? a.a[r] : 0.f, br = a.b[r];
@@ -276,7 +333,7 @@ __global__ __launch_bounds__(256) void k_gauge_to_blockh(Geom g, int d, const ch
     const uint32_t h = blockIdx.x * 256 + threadIdx.x;
     const int qm = blockIdx.y;
     if (h >= (uint32_t)g.Vh_pad) return;
-    const int kp = blockh_kpad(d), dk = d * kp;
+    const int kp = blockh_kpad(d), dk = blockh_link_halves(d);
     const char *blk = src + (size_t)qm * link_block_bytes(LP, true, d, g.Vh_pad);
     __half *o0 = dst + ((size_t)qm * g.Vh_pad + h) * dk;
     __half *o1 = dst + ((size_t)(8 + qm) * g.Vh_pad + h) * dk;
@@ -287,6 +344,7 @@ __global__ __launch_bounds__(256) void k_gauge_to_blockh(Geom g, int d, const ch
             o0[i * kp + k] = __float2half_rn(u);
             o1[i * kp + k] = __float2half_rn(ut);
         }
+    for (int e = d * kp; e < dk; e++) o0[e] = o1[e] = __float2half_rn(0.f);   // line padding
 }
 
 bsm_status launch_gauge_to_blockh(const Geom &g, int d, int link_prec, const void *U_rep, __half *U_blockh,
@@ -391,12 +449,13 @@ __global__ __launch_bounds__(256) void k_blockh_xpay(Geom g, char *p, const floa
     for (uint32_t h = blockIdx.x * 4 + (threadIdx.x >> 6); h < (uint32_t)g.Vh; h += gridDim.x * 4) {
         float2 v[4][4];
         load_site_h<D>(p, scale_off, h, r, q, v);
+        // unconditional loads at clamped colours (slots >= D are not stored)
 #pragma unroll
         for (int s = 0; s < 4; s++) {
-            const int c = 4 * q + s;
+            const int c = min(4 * q + s, D - 1);
 #pragma unroll
             for (int sp = 0; sp < 4; sp++) {
-                const float2 rv = c < D ? r32[f32_elem<D>(h, c, sp, r)] : make_float2(0.f, 0.f);
+                const float2 rv = r32[f32_elem<D>(h, c, sp, r)];
                 v[s][sp] = make_float2(fmaf(b, v[s][sp].x, rv.x), fmaf(b, v[s][sp].y, rv.y));
             }
         }
@@ -413,9 +472,19 @@ __global__ __launch_bounds__(256) void k_blockh_update(Geom g, float2 *x32, cons
     const size_t scale_off = blockh_scale_off(g, D);
     double nrm = 0.0;
     for (uint32_t h = blockIdx.x * 4 + (threadIdx.x >> 6); h < (uint32_t)g.Vh; h += gridDim.x * 4) {
-        float2 pv[4][4], qv[4][4];
+        float2 pv[4][4], qv[4][4], xv[4][4], rv[4][4];
         load_site_h<D>(p, scale_off, h, r, q, pv);
         load_site_h<D>(qf, scale_off, h, r, q, qv);
+        // all loads first, unconditional at clamped colours; stores only for
+        // the colours < D
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+            for (int sp = 0; sp < 4; sp++) {
+                const size_t e = f32_elem<D>(h, min(4 * q + s, D - 1), sp, r);
+                xv[s][sp] = x32[e];
+                rv[s][sp] = r32[e];
+            }
 #pragma unroll
         for (int s = 0; s < 4; s++) {
             const int c = 4 * q + s;
@@ -423,14 +492,14 @@ __global__ __launch_bounds__(256) void k_blockh_update(Geom g, float2 *x32, cons
 #pragma unroll
             for (int sp = 0; sp < 4; sp++) {
                 const size_t e = f32_elem<D>(h, c, sp, r);
-                float2 xv = x32[e], rv = r32[e];
-                xv.x = fmaf(a, pv[s][sp].x, xv.x);
-                xv.y = fmaf(a, pv[s][sp].y, xv.y);
-                rv.x = fmaf(-a, qv[s][sp].x, rv.x);
-                rv.y = fmaf(-a, qv[s][sp].y, rv.y);
-                x32[e] = xv;
-                r32[e] = rv;
-                nrm += (double)rv.x * rv.x + (double)rv.y * rv.y;
+                float2 xn = xv[s][sp], rn = rv[s][sp];
+                xn.x = fmaf(a, pv[s][sp].x, xn.x);
+                xn.y = fmaf(a, pv[s][sp].y, xn.y);
+                rn.x = fmaf(-a, qv[s][sp].x, rn.x);
+                rn.y = fmaf(-a, qv[s][sp].y, rn.y);
+                x32[e] = xn;
+                r32[e] = rn;
+                nrm += (double)rn.x * rn.x + (double)rn.y * rn.y;
             }
         }
     }

@@ -849,7 +849,12 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
                     fprintf(stderr, "[batched]   rhs %d update: recurrence %.3e recomputed %.3e (rel^2)\n", r,
                             hs[B_RR * kNR + r] / B.rhs_norm2[r], rr[r] / B.rhs_norm2[r]);
                 updates[r]++;
-                hs[B_BETA * kNR + r] = before[r] > 0 ? rr[r] / before[r] : 0.0;
+                // beta from the recomputed residual, the search direction
+                // kept; but when the recomputed residual is not below the
+                // recurrence's value two steps back, the recurrence has run
+                // ahead of the true residual (as a fast-converging FP16
+                // recurrence does within one replay): restart from r (beta 0)
+                hs[B_BETA * kNR + r] = (before[r] > 0 && rr[r] < before[r]) ? rr[r] / before[r] : 0.0;
                 hs[B_RR * kNR + r] = rr[r];
                 maxrr[r] = rr[r];
                 prev[r] = rr[r];
