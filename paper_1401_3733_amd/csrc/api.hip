@@ -10,6 +10,7 @@
 #include "blas.h"
 #include "block.h"
 #include "dispatch.h"
+#include "dphi.h"
 
 namespace bsm {
 
@@ -375,6 +376,22 @@ bsm_status bsm_dslash_apply(bsm_ctx ctx, const bsm_field_desc *desc, const void 
     const char *ip = (const char *)in;
     char *op = (char *)out;
     if (op < ip + 2 * bb && ip < op + 2 * bb) return fail(BSM_ERR_ARG, "in and out must not overlap");
+    // one pass over both parities with most links read once, where the
+    // lattice and the precision allow; otherwise both parities in one launch
+    // of the even-odd hop
+    const int lc = link_code(desc);
+    if (!link_is_otf(lc) && desc->prec == lc && (lc == BSM_F32 || lc == BSM_F64) &&
+        dphi_compiled(desc->prec, desc->d_R) && dphi_fits(ctx->g)) {
+        DphiArgs d{};
+        d.U = U_rep;
+        d.in = in;
+        d.out = out;
+        d.a = 1.0;
+        d.b = -kappa;
+        d.dagger = dagger ? 1 : 0;
+        d.tc = dphi_tchunk(ctx->g);
+        return launch_dphi(ctx->g, desc->d_R, link_real(desc), desc->prec, lc, d, (hipStream_t)stream);
+    }
     HopArgs a{};
     a.U = U_rep;
     a.in[0] = ip + bb;    // even output reads odd sites
