@@ -121,7 +121,16 @@ void k_hop_block64(Geom g, BlockHop64Args a, int nblk) {
     hop_dir_block64<3, D>(g, a, c, p, h, r, q, eta, acc);
     const double ar = a.a[r], br = a.b[r];
     double2 *o = a.out[p] + (size_t)h * SITE;
-    const double2 *x = a.use_x ? a.x[p] + (size_t)h * SITE : nullptr;
+    // x first, every load unconditional (rows i >= D read row D - 1 and are
+    // not stored): a load inside the divergent i < D test is waited for there
+    double2 xv[4][4];
+    if (a.use_x) {
+        const double2 *x = a.x[p] + (size_t)h * SITE;
+#pragma unroll
+        for (int v = 0; v < 4; v++)
+#pragma unroll
+            for (int s = 0; s < 4; s++) xv[v][s] = x[(size_t)(min(q + 4 * v, D - 1) * 4 + s) * kNR + r];
+    }
 #pragma unroll
     for (int v = 0; v < 4; v++) {
         const int i = q + 4 * v;   // the FP64 result interleave
@@ -130,10 +139,9 @@ void k_hop_block64(Geom g, BlockHop64Args a, int nblk) {
             for (int s = 0; s < 4; s++) {
                 const size_t e = (size_t)(i * 4 + s) * kNR + r;
                 double re = br * acc[s][0][v], im = br * acc[s][1][v];
-                if (x) {
-                    const double2 xv = x[e];
-                    re = fma(ar, xv.x, re);
-                    im = fma(ar, xv.y, im);
+                if (a.use_x) {
+                    re = fma(ar, xv[v][s].x, re);
+                    im = fma(ar, xv[v][s].y, im);
                 }
                 o[e] = make_double2(re, im);
             }
