@@ -524,12 +524,14 @@ def bench_cfg4(bsm, gen):
     log(f"  {tb:.3f} s, iters {[s['iters'] for s in stats]}, block plan {plan}")
     # the same solve with the F16S inner recurrence (FP16 block fields, links
     # and matrix cores; FP64 reliable updates and true residuals)
+    # (replays of 4 iterations, the library's default for F16S)
     dh = bsm.desc(4, "adj", "f16s", "f64")
     xh = torch.zeros_like(b)
+    prm_h = bsm.solver_params(kappas[0], 1e-10, schur=True, max_iter=5000, check_every=0)
     log("cfg4 batched F16S (warm-up call) ...")
-    ctx.bsm_batched_solve(dh, U, prm, kappas, b, xh, check=False)
+    ctx.bsm_batched_solve(dh, U, prm_h, kappas, b, xh, check=False)
     log("cfg4 batched F16S ...")
-    sth, statsh = ctx.bsm_batched_solve(dh, U, prm, kappas, b, xh, check=False)
+    sth, statsh = ctx.bsm_batched_solve(dh, U, prm_h, kappas, b, xh, check=False)
     tbh = statsh[0]["seconds"]
     planh = ctx.bsm_get_block_plan(dh)
     log(f"  {tbh:.3f} s, iters {[s['iters'] for s in statsh]}, block plan {planh}")

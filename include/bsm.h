@@ -241,7 +241,7 @@ typedef struct {
     double tol;            /* target true relative residual ||b - D x|| / ||b|| */
     int32_t max_iter;
     double delta;          /* reliable update threshold (MIXED), e.g. 0.1 */
-    int32_t check_every;   /* iterations between host convergence checks (>= 1) */
+    int32_t check_every;   /* iterations between host convergence checks (<= 0: the solver's default) */
     int32_t restart;       /* FGCR: Krylov vectors per cycle (e.g. 16) */
     int32_t precond_layers; /* FGCR: 0 applies the network as one collapsed operator
                                (bsm_precond_apply_collapsed) where d_R <= 3; 1 always
@@ -442,7 +442,8 @@ bsm_status bsm_get_block_plan(bsm_ctx ctx, const bsm_field_desc *desc, int32_t *
  * kappa_r (Section II.B's inversion, for a family of masses).  b and x are
  * n_rhs consecutive full internal FP64 fields; U_rep64 are FP64 links.
  * Adjoint links: 16 RHS at a time share every link load on matrix cores
- * (inner recurrence captured as a HIP graph of check_every iterations, FP64
+ * (inner recurrence captured as a HIP graph of check_every iterations, or
+ * with check_every <= 0 of 8 (FP32) or 4 (F16S) iterations, FP64
  * reliable updates with threshold delta, each RHS retired once its FP64
  * true residual <= tol); desc->prec = BSM_F16S runs the inner recurrence
  * on FP16 block fields and links (x and r in FP32), any other precision on
