@@ -275,6 +275,9 @@ typedef struct {
  * that is F64).  x is overwritten (start x = 0).  Stopping: the normal
  * residual only triggers a check; the FP64 full-lattice true residual must be
  * <= tol, otherwise iteration continues with the trigger tightened by 0.3.
+ * Both run check_every iterations between host checks (check_every <= 0:
+ * 8); MIXED decides its reliable updates there, from the |r|^2 of every
+ * iteration of the chunk.
  * Synchronous: returns when done, with stats filled in even on failure. */
 bsm_status bsm_cg_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep,
                         const void *U_rep64, const bsm_solver_params *params, const void *b,

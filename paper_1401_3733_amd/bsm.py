@@ -449,10 +449,10 @@ def _darr(vals, n=None):
 
 
 def solver_params(kappa, tol=1e-10, schur=True, variant=SOLVER_PLAIN, max_iter=100000, delta=0.1,
-                  check_every=8, restart=16, precond_layers=0, kappas=None, channels=0,
+                  check_every=0, restart=16, precond_layers=0, kappas=None, channels=0,
                   net=None) -> SolverParams:
     """kappas (BATCHED) and net (FGCR_NET, a device tensor) are kept alive on
-    the returned structure."""
+    the returned structure; check_every 0 takes each solver's default."""
     ka = _darr(kappas)
     p = SolverParams(variant, int(schur), float(kappa), float(tol), int(max_iter), float(delta),
                      int(check_every), int(restart), int(precond_layers), len(kappas) if kappas is not None else 1,
