@@ -169,6 +169,24 @@ __device__ inline void hop_dir(const Geom &g, const Coords &c, int p, uint32_t h
     }
 }
 
+// F16 spinors with on-the-fly links: the accumulators are pinned after each
+// hop (an empty statement that holds them in registers there) and the
+// scheduler may not move instructions across, so the small FP16 neighbour
+// loads of later directions are not hoisted over this one's arithmetic;
+// without it the compiler issued all eight directions' loads first and held
+// 256 registers (one wavefront per SIMD).  Other forms are left alone.
+template <int SP, int D, class T>
+__device__ inline void otf_pin(cx<T> (&acc)[4 * D]) {
+    if constexpr (SP == BSM_F16S) {
+#pragma unroll
+        for (int k = 0; k < 4 * D; k++) {
+            asm volatile("" : "+v"(acc[k].re));
+            asm volatile("" : "+v"(acc[k].im));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // both hops along mu with fundamental links: R(U) (or R(U)^dag) applied to
 // the projected half spinor on the fly
 template <int MU, int RN, int SP, int LP, class T>
@@ -199,6 +217,7 @@ __device__ inline void hop_dir_otf(const Geom &g, const Coords &c, int p, uint32
             rep_apply<RN, true, T>(u, h1, g1);
         }
         reconstruct<MU, D, T>(acc, sg, (T)wf, g0, g1);
+        otf_pin<SP, D>(acc);
     }
 }
 
