@@ -169,17 +169,25 @@ __device__ inline void hop_dir(const Geom &g, const Coords &c, int p, uint32_t h
     }
 }
 
-// F16 spinors with on-the-fly links: the accumulators are pinned after each
-// hop (an empty statement that holds them in registers there) and the
-// scheduler may not move instructions across, so the small FP16 neighbour
-// loads of later directions are not hoisted over this one's arithmetic;
-// without it the compiler issued all eight directions' loads first and held
-// 256 registers (one wavefront per SIMD).  Other forms are left alone.
-template <int SP, int D, class T>
-__device__ inline void otf_pin(cx<T> (&acc)[4 * D]) {
-    if constexpr (SP == BSM_F16S) {
+// Hops with on-the-fly links: the accumulators are pinned after each hop (an
+// empty statement that holds them in registers there) and the scheduler may
+// not move instructions across, so later directions' neighbour loads are not
+// hoisted over this one's arithmetic.  Without it the F16 spinor forms issued
+// all eight directions' loads first and held 256 registers (one wavefront per
+// SIMD).  Measured per form on 32^3 x 64: pinned is faster for F16 spinors
+// (2S SU(3) 432 -> 172 us), FP32 (2S SU(3) 295 -> 257 us, 2S SU(2)
+// 147 -> 112 us; the SU(2) adjoint loses 3 %) and FP64 at d_R >= 6 (2S SU(3)
+// 520 -> 486 us), and slower for FP64 at d_R = 3 (2S SU(2) 209 -> 262 us).
+template <int SP, int RN>
+constexpr bool kOtfPin = SP == BSM_F16S ||
+                         (SP == BSM_F32 && !(otf_rep(RN) == BSM_REP_ADJ && otf_n(RN) == 2)) ||
+                         (SP == BSM_F64 && otf_dim(RN) >= 6);
+
+template <int SP, int RN, class T>
+__device__ inline void otf_pin(cx<T> (&acc)[4 * otf_dim(RN)]) {
+    if constexpr (kOtfPin<SP, RN>) {
 #pragma unroll
-        for (int k = 0; k < 4 * D; k++) {
+        for (int k = 0; k < 4 * otf_dim(RN); k++) {
             asm volatile("" : "+v"(acc[k].re));
             asm volatile("" : "+v"(acc[k].im));
         }
@@ -217,7 +225,7 @@ __device__ inline void hop_dir_otf(const Geom &g, const Coords &c, int p, uint32
             rep_apply<RN, true, T>(u, h1, g1);
         }
         reconstruct<MU, D, T>(acc, sg, (T)wf, g0, g1);
-        otf_pin<SP, D>(acc);
+        otf_pin<SP, RN>(acc);
     }
 }
 
