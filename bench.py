@@ -298,6 +298,42 @@ def _to_host(ctx, bsm, d64, x, V, d):
     return h
 
 
+class OracleChecks:
+    """GPU solutions of full-size workloads, kept on the host for the oracle's
+    FP64 true residual ||b - D_W x|| / ||b|| (computed by the oracle's own D_W
+    at the end of the run, after the timed GPU sections).  b is the
+    generator's source, never read back from the GPU."""
+
+    def __init__(self):
+        self.groups = {}
+
+    def group(self, key, lat, Uf_host, rep, workload):
+        self.groups[key] = {"lat": lat, "Uf": Uf_host, "rep": rep, "workload": workload, "items": []}
+
+    def add(self, key, label, kappa, b_host, x_host, gpu_res):
+        self.groups[key]["items"].append((label, kappa, b_host, x_host, gpu_res))
+
+    def run(self, threads):
+        import oracle
+        oracle.set_num_threads(threads)
+        out = {}
+        for key, g in self.groups.items():
+            t0 = time.time()
+            U = oracle.represent(g["Uf"], g["rep"])
+            rows = {}
+            for label, kappa, b, x, gpu_res in g["items"]:
+                r = oracle.true_residual(g["lat"], U, kappa, b, x)
+                rows[label] = {"oracle": r, "gpu": gpu_res}
+            del U
+            worst = max(v["oracle"] for v in rows.values())
+            out[key] = {"workload": g["workload"], "true_rel_res": rows, "max_oracle_true_rel_res": worst,
+                        "all_at_or_below_1e-10": bool(worst <= 1e-10),
+                        "max_abs_diff_gpu_vs_oracle": max(abs(v["oracle"] - v["gpu"]) for v in rows.values()),
+                        "threads": oracle.num_threads(), "seconds": round(time.time() - t0, 1)}
+            g["items"] = []
+        return out
+
+
 def bench_cg_cfg2(ctx, lat, Uf_dev, psi_dev, kappa, bsm, Uf_host=None, keep=None):
     """keep (dict or None): receives the host copy of each form's solution
     for the oracle comparison of the CPU leg"""
@@ -376,8 +412,9 @@ def bench_cfg1(bsm, gen, keep=None):
     return out
 
 
-def bench_cfg3(bsm, gen):
-    """Mixed-precision reliable-update CG, 32^3 x 64 SU(3) two-index symmetric."""
+def bench_cfg3(bsm, gen, checks=None):
+    """Mixed-precision reliable-update CG, 32^3 x 64 SU(3) two-index symmetric.
+    checks (OracleChecks or None): receives every solution for the oracle."""
     import torch
     c = gen.CONFIGS[3]
     lat = gen.config_lattice(3)
@@ -386,7 +423,12 @@ def bench_cfg3(bsm, gen):
     Uf = bsm.to_device_c128(Uf_host)
     ctx = bsm.Context(lat.dims, lat.bc)
     d64 = bsm.desc(3, "sym", "f64")
-    src = bsm.to_device_c128(gen.config_source(3, d64.d_R, lat))
+    src_host = gen.config_source(3, d64.d_R, lat)
+    src = bsm.to_device_c128(src_host)
+    if checks is not None:
+        checks.group("cfg3", lat, Uf_host, "sym", "32^3x64 SU(3) 2S (d_R=6), every solver form's solution")
+    else:
+        del src_host
     U64 = ctx.new_gauge(d64)
     ctx.bsm_gauge_represent(d64, Uf, U64)
     b = ctx.new_spinor(d64)
@@ -411,6 +453,8 @@ def bench_cfg3(bsm, gen):
             base = st["seconds"]
         else:
             out[name]["x_rel_diff_vs_plain"] = rel_diff(ctx, d64, x, x64)
+        if checks is not None:
+            checks.add("cfg3", name, c["kappa"], src_host, _to_host(ctx, bsm, d64, xo, lat.V, 6), st["true_rel_res"])
         log(f"  {out[name]}")
         if prec != "f64":
             del Ul
@@ -480,6 +524,8 @@ def bench_cfg3(bsm, gen):
         status, st = warm_solve(lambda: ctx.bsm_cg_solve(dl, Ul, U64o, prm, b, x64o, check=False))
         out[name] = solve_row(status, st, base)
         out[name]["x_rel_diff_vs_plain"] = rel_diff(ctx, d64, x64o, x64_keep)
+        if checks is not None:
+            checks.add("cfg3", name, c["kappa"], src_host, _to_host(ctx, bsm, d64, x64o, lat.V, 6), st["true_rel_res"])
         log(f"  {out[name]}")
         if prec != "f64":
             del Ul
@@ -491,8 +537,12 @@ def bench_cfg3(bsm, gen):
     return out
 
 
-def bench_cfg4(bsm, gen):
-    """16 right-hand sides, 24^3 x 48 SU(4) adjoint: batched vs sequential."""
+def bench_cfg4(bsm, gen, checks=None):
+    """16 right-hand sides, 24^3 x 48 SU(4) adjoint: batched vs sequential.
+    checks (OracleChecks or None): receives the 16 solutions of each of the
+    batched (FP32 and F16S inner) and shifted-family solves, and those of
+    kappa 0.10, 0.108, 0.117, 0.125 of the sequential FP64 solves, for the
+    oracle."""
     import torch
     c = gen.CONFIGS[4]
     lat = gen.config_lattice(4)
@@ -508,9 +558,17 @@ def bench_cfg4(bsm, gen):
     n = len(kappas)
     fb = ctx.spinor_bytes(d64, 2, 1)
     b = ctx.new_spinor(d64, 2, n)
+    srcs = []
     for r in range(n):   # one Philox stream per right-hand side
         src = gen.gaussian_spinor(lat, d64.d_R, gen.SEED_SOURCE + 4 + 100 * r)
         ctx.bsm_pack_spinor(d64, bsm.to_device_c128(src), b[r * fb:(r + 1) * fb])
+        if checks is not None:
+            srcs.append(src)
+    sample = (0, 5, 10, 15)
+    if checks is not None:
+        checks.group("cfg4", lat, Uf_host, "adj", "24^3x48 SU(4) adjoint: all 16 solutions of the batched (FP32 "
+                     "and F16S inner) and shifted-family solves; kappa indices 0, 5, 10, 15 of the sequential "
+                     "plain FP64 solves")
     torch.cuda.synchronize()
     xb = torch.zeros_like(b)
     xs = torch.zeros_like(b)
@@ -520,6 +578,10 @@ def bench_cfg4(bsm, gen):
     log("cfg4 batched ...")
     st, stats = ctx.bsm_batched_solve(d64, U, prm, kappas, b, xb, check=False)
     tb = stats[0]["seconds"]
+    if checks is not None:
+        for r in range(n):
+            checks.add("cfg4", f"batched_k{r}", kappas[r], srcs[r],
+                       _to_host(ctx, bsm, d64, xb[r * fb:(r + 1) * fb], lat.V, 15), stats[r]["true_rel_res"])
     plan = ctx.bsm_get_block_plan(d64)
     log(f"  {tb:.3f} s, iters {[s['iters'] for s in stats]}, block plan {plan}")
     # the same solve with the F16S inner recurrence (FP16 block fields, links
@@ -533,6 +595,10 @@ def bench_cfg4(bsm, gen):
     log("cfg4 batched F16S ...")
     sth, statsh = ctx.bsm_batched_solve(dh, U, prm_h, kappas, b, xh, check=False)
     tbh = statsh[0]["seconds"]
+    if checks is not None:
+        for r in range(n):
+            checks.add("cfg4", f"batched_f16s_k{r}", kappas[r], srcs[r],
+                       _to_host(ctx, bsm, d64, xh[r * fb:(r + 1) * fb], lat.V, 15), statsh[r]["true_rel_res"])
     planh = ctx.bsm_get_block_plan(dh)
     log(f"  {tbh:.3f} s, iters {[s['iters'] for s in statsh]}, block plan {planh}")
     tseq, its, worst, worst_h = 0.0, [], 0.0, 0.0
@@ -545,6 +611,9 @@ def bench_cfg4(bsm, gen):
         s1, st1 = ctx.bsm_cg_solve(d64, U, U, p1, b[sl], xs[sl], check=False)
         tseq += st1["seconds"]
         its.append(st1["iters"])
+        if checks is not None and r in sample:
+            checks.add("cfg4", f"sequential_f64_k{r}", kappas[r], srcs[r], _to_host(ctx, bsm, d64, xs[sl], lat.V, 15),
+                       st1["true_rel_res"])
         worst = max(worst, rel_diff(ctx, d64, xb[sl], xs[sl]))
         worst_h = max(worst_h, rel_diff(ctx, d64, xh[sl], xs[sl]))
     log(f"  {tseq:.3f} s, iters {its}")
@@ -601,6 +670,11 @@ def bench_cfg4(bsm, gen):
     ctx.bsm_shifted_solve(d64, U, prm_s, kappas, b[0:fb], xb, check=False)
     s_st, s_stats = ctx.bsm_shifted_solve(d64, U, prm_s, kappas, b[0:fb], xb, check=False)
     t_shift = s_stats[0]["seconds"]
+    if checks is not None:
+        for r in range(n):
+            checks.add("cfg4", f"shifted_k{r}", kappas[r], srcs[0],
+                       _to_host(ctx, bsm, d64, xb[r * fb:(r + 1) * fb], lat.V, 15), s_stats[r]["true_rel_res"])
+        del srcs
     log(f"  {t_shift:.3f} s, iters {[s['iters'] for s in s_stats]}, fell back {[s['fell_back'] for s in s_stats]}")
     tseq1, its1, worst1 = 0.0, [], 0.0
     for r in range(n):
@@ -1174,10 +1248,11 @@ def main():
     forms = {}
     keep1 = {}
     cfg1 = bench_cfg1(bsm, gen, keep1) if "cfg1" in sections else None
+    checks = OracleChecks() if "cpu" in sections else None
     if "cfg3" in sections:
-        forms["mixed_precision"] = bench_cfg3(bsm, gen)
+        forms["mixed_precision"] = bench_cfg3(bsm, gen, checks)
     if "cfg4" in sections:
-        forms["batched"] = bench_cfg4(bsm, gen)
+        forms["batched"] = bench_cfg4(bsm, gen, checks)
     if "cfg5" in sections:
         forms["learned_preconditioner"] = bench_cfg5(bsm, gen)
     tasks = bench_tasks(bsm, gen, lat, Uf, args.task_seconds) if "tasks" in sections else None
@@ -1190,6 +1265,14 @@ def main():
         ref = finish_oracle_reference(*oracle_job, keep, max(1, cores - 2))
         log(f"  {ref}")
         keep = None
+    if checks is not None and checks.groups:
+        log("oracle FP64 true residuals of the full-size GPU solutions ...")
+        for key, v in checks.run(cores).items():
+            form = {"cfg3": "mixed_precision", "cfg4": "batched"}[key]
+            forms[form]["oracle_check"] = v
+            log(f"  {key}: max {v['max_oracle_true_rel_res']:.3e}, |gpu - oracle| <= "
+                f"{v['max_abs_diff_gpu_vs_oracle']:.1e}, {v['seconds']} s")
+        checks = None
     if "cpu" in sections:
         log("CPU oracle baseline ...")
         cpu = cpu_baseline(lat, Uf, psi, res["f32"]["bytes"])
