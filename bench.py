@@ -1020,72 +1020,95 @@ def cpu_baseline(lat, Uf, psi, bytes_per_hop, min_seconds=10.0):
                       f"algorithmic bytes per hop as the GPU FP32 figure, so the ratio is a ratio of hop rates"}
 
 
-def _oracle_cfg2_job(path, threads):
-    """Child process of the CPU leg: the oracle's FP64 Schur CG on the
-    headline workload (32^3 x 64 SU(3), kappa 0.13) to a 1e-10 true residual,
-    timed, then continued from that iterate to a true residual <= 1e-13 (the
-    reference every GPU solution of that workload is compared with).  Writes
-    the solution and a JSON summary next to path."""
-    import json as _json
+def _oracle_solve_to(lat, U, kappa, b, x, info, target=1e-13):
+    """Continue the oracle's Schur recurrence from the even part of x (a
+    solution at a looser tolerance) until the true residual is <= target:
+    bhat_e = b_e + kappa H_eo b_o, then x_o = b_o + kappa H_oe x_e."""
     import oracle
-    from paper_1401_3733_amd import inputs as gen
-    oracle.set_num_threads(threads)
-    lat = gen.config_lattice(2)
-    kappa = gen.CONFIGS[2]["kappa"]
-    U = oracle.represent(gen.config_links(2, lat), "fund")
-    b = gen.config_source(2, 3, lat)
-    t0 = time.perf_counter()
-    x, info = oracle.solve(lat, U, kappa, b, tol=1e-10, schur=True)
-    t10 = time.perf_counter() - t0
-    # continue the Schur recurrence from the even part of x: bhat_e = b_e +
-    # kappa H_eo b_o, then rebuild x_o = b_o + kappa H_oe x_e
     odd = oracle.parity_mask(lat).astype(bool)
     bh = b + kappa * oracle.hop(lat, U, b, parity=0)
     bh[odd] = 0
     xe = x.copy()
     xe[odd] = 0
-    res, extra, trig = info["true_res"], 0, 1e-13
-    t1 = time.perf_counter()
-    while res > 1e-13 and extra < 4000 and trig > 1e-17:
+    res, extra, trig = info["true_res"], 0, target
+    while res > target and extra < 4000 and trig > 1e-17:
         xe, it, _ = oracle.cgnr_raw(lat, U, kappa, bh, x0=xe, tol=trig, schur=True)
         extra += it
         x = xe.copy()
         x[odd] = (b + kappa * oracle.hop(lat, U, xe, parity=1))[odd]
         res = oracle.true_residual(lat, U, kappa, b, x)
         trig *= 0.3
-    np.save(path, x)
-    with open(path + ".json", "w") as f:
-        _json.dump({"tts_1e-10_seconds": round(t10, 3), "iters_1e-10": info["iters"],
-                    "true_rel_res_1e-10": info["true_res"], "reference_true_rel_res": res,
-                    "reference_extra_iters": extra, "reference_extra_seconds": round(time.perf_counter() - t1, 3),
-                    "threads": oracle.num_threads()}, f)
+    return x, res, extra
+
+
+def _oracle_reference_job(path, threads):
+    """Child process of the CPU leg: the oracle's FP64 Schur CG on the
+    headline workload (32^3 x 64 SU(3) fundamental, kappa 0.13) and on the
+    two-index one (32^3 x 64 SU(3) 2S, kappa 0.125), each to a 1e-10 true
+    residual, timed, then continued to a true residual <= 1e-13 (the
+    reference the GPU solutions of that workload are compared with).  Writes
+    each solution and a JSON summary next to path (suffixes _2 and _3)."""
+    import json as _json
+    import oracle
+    from paper_1401_3733_amd import inputs as gen
+    oracle.set_num_threads(threads)
+    for k in (2, 3):
+        c = gen.CONFIGS[k]
+        lat = gen.config_lattice(k)
+        kappa = c["kappa"]
+        U = oracle.represent(gen.config_links(k, lat), c["rep"])
+        b = gen.config_source(k, oracle.rep_dim(c["N"], c["rep"]), lat)
+        t0 = time.perf_counter()
+        x, info = oracle.solve(lat, U, kappa, b, tol=1e-10, schur=True)
+        t10 = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        x, res, extra = _oracle_solve_to(lat, U, kappa, b, x, info)
+        np.save(f"{path}_{k}.npy", x)
+        with open(f"{path}_{k}.json", "w") as f:
+            _json.dump({"tts_1e-10_seconds": round(t10, 3), "iters_1e-10": info["iters"],
+                        "true_rel_res_1e-10": info["true_res"], "reference_true_rel_res": res,
+                        "reference_extra_iters": extra,
+                        "reference_extra_seconds": round(time.perf_counter() - t1, 3),
+                        "threads": oracle.num_threads()}, f)
+        del U, b, x
 
 
 def start_oracle_reference(threads):
-    """Start the oracle's headline-workload solve in a child process (it runs
-    while the GPU sections run in this one); returns (process, path)."""
+    """Start the oracle's reference solves in a child process (it runs while
+    the GPU sections run in this one); returns (process, path)."""
     import multiprocessing as mp
     import tempfile
-    path = os.path.join(tempfile.mkdtemp(prefix="bsm_oracle_"), "x_ref.npy")
-    proc = mp.get_context("spawn").Process(target=_oracle_cfg2_job, args=(path, threads), daemon=True)
+    path = os.path.join(tempfile.mkdtemp(prefix="bsm_oracle_"), "x_ref")
+    proc = mp.get_context("spawn").Process(target=_oracle_reference_job, args=(path, threads), daemon=True)
     proc.start()
     return proc, path
 
 
+WORKLOAD_NAMES = {2: "32^3x64 SU(3) fund, exp(0.3iH) links, kappa 0.13",
+                  3: "32^3x64 SU(3) 2S (d_R=6), exp(0.3iH) links, kappa 0.125"}
+
+
 def finish_oracle_reference(proc, path, solutions, threads):
-    """Wait for the child, then compare each kept GPU solution of the headline
-    workload with the oracle's reference solution."""
+    """Wait for the child, then compare each kept GPU solution with the
+    oracle's reference solution of its workload.  solutions: {2 or 3:
+    {label: host solution}}; returns {2 or 3: summary}."""
     import shutil
     proc.join()
-    if proc.exitcode != 0 or not os.path.exists(path + ".json"):
-        return {"error": f"oracle reference job failed (exit code {proc.exitcode})"}
-    with open(path + ".json") as f:
-        out = json.load(f)
-    xr = np.load(path)
-    nr = np.linalg.norm(xr)
-    out["x_rel_err_vs_oracle"] = {k: float(np.linalg.norm(v - xr) / nr) for k, v in solutions.items()}
-    out["workload"] = ("32^3x64 SU(3) fund, exp(0.3iH) links, kappa 0.13, oracle FP64 Schur CG; timed on "
-                       f"{threads} host threads while the GPU sections ran in the parent process")
+    out = {}
+    for k in (2, 3):
+        if proc.exitcode != 0 or not os.path.exists(f"{path}_{k}.json"):
+            out[k] = {"error": f"oracle reference job failed (exit code {proc.exitcode})"}
+            continue
+        with open(f"{path}_{k}.json") as f:
+            o = json.load(f)
+        xr = np.load(f"{path}_{k}.npy")
+        nr = np.linalg.norm(xr)
+        o["x_rel_err_vs_oracle"] = {lab: float(np.linalg.norm(v - xr) / nr)
+                                    for lab, v in solutions.get(k, {}).items()}
+        o["workload"] = (f"{WORKLOAD_NAMES[k]}, oracle FP64 Schur CG; timed on {threads} host threads while "
+                         "the GPU sections ran in the parent process")
+        out[k] = o
+        del xr
     shutil.rmtree(os.path.dirname(path), ignore_errors=True)
     return out
 
@@ -1261,10 +1284,17 @@ def main():
     ref = None
     if oracle_job is not None:
         # the rest of the CPU leg times the oracle on every core: wait first
-        log("waiting for the oracle reference solve of the headline workload ...")
-        ref = finish_oracle_reference(*oracle_job, keep, max(1, cores - 2))
+        log("waiting for the oracle reference solves ...")
+        sols = {2: keep}
+        if checks is not None and "cfg3" in checks.groups:
+            sols[3] = {item[0]: item[3] for item in checks.groups["cfg3"]["items"]}
+        refs = finish_oracle_reference(*oracle_job, sols, max(1, cores - 2))
+        ref = refs[2]
         log(f"  {ref}")
-        keep = None
+        if "mixed_precision" in forms:
+            forms["mixed_precision"]["oracle_reference"] = refs[3]
+            log(f"  {refs[3]}")
+        keep = sols = None
     if checks is not None and checks.groups:
         log("oracle FP64 true residuals of the full-size GPU solutions ...")
         for key, v in checks.run(cores).items():
