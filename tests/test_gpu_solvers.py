@@ -78,6 +78,50 @@ def test_mixed_reliable_update(prec, link_prec, schur):
     assert rel(x, xo) <= 1e-9
 
 
+@pytest.mark.parametrize("check_every", [1, 3, 40])
+def test_mixed_chunk_lengths(check_every):
+    """The mixed solver enqueues check_every iterations between host reads and
+    takes its reliable updates at chunk boundaries: every chunk length,
+    including one longer than the solve, reaches the oracle's solution."""
+    note(f"cg mixed chunk {check_every}")
+    lat = gen.Lattice(8, 4, 6, 4)
+    Uf = gen.gauge_links(lat, 3, "near_identity", 42, eps=0.3)
+    S64 = Setup(lat, 3, "fund", Uf)
+    Slo = Setup(lat, 3, "fund", Uf, prec="f16s", link_prec="f16s")
+    Slo.desc64 = S64.desc
+    b = gen.gaussian_spinor(lat, 3, 43)
+    prm = bsm.solver_params(0.13, 1e-10, schur=True, variant=bsm.SOLVER_MIXED, check_every=check_every)
+    st, stats, x = _solve(Slo, b, prm, U64=S64.U, desc=Slo.desc)
+    print(stats)
+    assert st == 0 and stats["reliable_updates"] >= 1
+    tr = oracle.true_residual(lat, Uf, 0.13, b, x)
+    assert tr <= 1e-10 and abs(tr - stats["true_rel_res"]) < 1e-12
+    xo, _ = oracle.solve(lat, Uf, 0.13, b, tol=1e-13, schur=True)
+    assert rel(x, xo) <= 1e-9
+
+
+def test_mixed_max_iter_inside_a_chunk():
+    """max_iter that ends inside a chunk of 8: the solver stops there and
+    reports NOT_CONVERGED with the FP64 true residual of the iterate it
+    returns (checked by the oracle)."""
+    note("cg mixed max_iter 5")
+    lat = gen.Lattice(4, 4, 4, 4)
+    Uf = gen.gauge_links(lat, 3, "haar", 44)
+    S64 = Setup(lat, 3, "fund", Uf)
+    Slo = Setup(lat, 3, "fund", Uf, prec="f32", link_prec="f32")
+    Slo.desc64 = S64.desc
+    b = gen.gaussian_spinor(lat, 3, 45)
+    import torch
+    bb = Slo.pack(b, desc=S64.desc)
+    x = torch.zeros_like(bb)
+    prm = bsm.solver_params(0.12, 1e-10, schur=True, variant=bsm.SOLVER_MIXED, max_iter=5, check_every=8)
+    status, stats = Slo.ctx.bsm_cg_solve(Slo.desc, Slo.U, S64.U, prm, bb, x, check=False)
+    assert status == bsm.ERR_NOT_CONVERGED and stats["iters"] == 5
+    xs = Slo.unpack(x, desc=S64.desc)
+    tr = oracle.true_residual(lat, Uf, 0.12, b, xs)
+    assert 1e-10 < tr < 1.0 and abs(tr - stats["true_rel_res"]) < 1e-12
+
+
 def test_zero_source_and_max_iter():
     lat = gen.Lattice(4, 4, 4, 4)
     Uf = gen.gauge_links(lat, 3, "haar", 3)
