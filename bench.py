@@ -276,6 +276,19 @@ def bench_hop(ctx, lat, Uf_dev, psi_dev, args, bsm):
         if not args.no_autotune:
             log(f"autotune {prec} hop ...")
             ctx.bsm_autotune(d, U)
+        sweep = {}
+        if args.hop_plans and prec == "f32":
+            # every listed walk plan in turn (counter runs separate them by
+            # dispatch order: warmup + steps dispatches per plan), then the
+            # tuned or default plan again
+            keep_plan = ctx.bsm_get_hop_plan(d)
+            for item in args.hop_plans.split(","):
+                order, tc = (int(v) for v in item.split(":"))
+                ctx.bsm_set_hop_plan(d, order, tc)
+                ms_p = time_hops(ctx, d, U, A, B, args.steps, args.warmup)
+                sweep[item] = round(ms_p * 1e3, 2)
+                log(f"  plan {item}: {ms_p * 1e3:.1f} us")
+            ctx.bsm_set_hop_plan(d, keep_plan["order"], keep_plan["tchunk"])
         plan = ctx.bsm_get_hop_plan(d)
         steps = args.steps if prec == "f32" else max(10, args.steps // 4)
         log(f"timing {prec} even-odd hop: {steps} steps, plan {plan}")
@@ -283,6 +296,8 @@ def bench_hop(ctx, lat, Uf_dev, psi_dev, args, bsm):
         nbytes = hop_bytes(3, False, prec, prec, Vh)
         res[prec] = dict(ms=ms, gbs=nbytes / ms / 1e6, tflops=hop_flops(3, False, Vh) / ms / 1e9,
                          bytes=nbytes, plan=plan, steps=steps)
+        if sweep:
+            res[prec]["plan_sweep_us"] = sweep
         log(f"  {prec}: {ms * 1e3:.1f} us/hop, {res[prec]['gbs']:.0f} GB/s")
         del U, A, B
     torch.cuda.empty_cache()
@@ -1209,6 +1224,8 @@ def main():
                     help="keep the default hop plan (counter runs: every hop dispatch is the same kernel)")
     ap.add_argument("--task-seconds", type=float, default=0.25,
                     help="minimum timed period of each task of the paper's benchmark")
+    ap.add_argument("--hop-plans", type=str, default="",
+                    help="also time the FP32 hop under each listed walk plan, 'order:tchunk,...'")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run N plain 1 GiB device copies (counter calibration)")
     args = ap.parse_args()
@@ -1340,6 +1357,7 @@ def main():
                      "algorithmic_bytes_per_launch": r32["bytes"], "traffic_source": traffic_note,
                      "achievable_gbs": {"copy": round(copy_gbs, 1), "read": round(read_gbs, 1)}},
         "tflops_f32": round(r32["tflops"], 2),
+        **({"hop_plan_sweep_us": r32["plan_sweep_us"]} if "plan_sweep_us" in r32 else {}),
         "hop_f64": None if "f64" not in res else {
             "gbs": round(res["f64"]["gbs"], 1), "us": round(res["f64"]["ms"] * 1e3, 2),
             "frac": round(res["f64"]["gbs"] / PEAK_HBM_GBS, 4), "plan": res["f64"]["plan"]},
