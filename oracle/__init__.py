@@ -124,10 +124,23 @@ def _d_of(U):
     return U.shape[-1]
 
 
+def _check(lat, U, *fields):
+    """The C loops read V*4*d*d link and V*4*d spinor elements: refuse arrays
+    of any other size instead of reading past them."""
+    V = int(np.prod(lat.dims))
+    d = _d_of(U)
+    if U.size != V * 4 * d * d:
+        raise ValueError(f"links: {U.size} elements, expected V*4*d*d = {V * 4 * d * d}")
+    for f in fields:
+        if f is not None and f.size != V * 4 * d:
+            raise ValueError(f"spinor field: {f.size} elements, expected V*4*d = {V * 4 * d}")
+
+
 def hop(lat, U, psi, dagger=False, parity=-1):
     """H psi (D = 1 - kappa H); parity >= 0 gives the even-odd block that
     writes sites of that parity (other sites zero)."""
     U, psi = _c128(U), _c128(psi)
+    _check(lat, U, psi)
     out = np.zeros_like(psi)
     lib().orc_hop(_ip(lat.dims), _ip(lat.bc), _d_of(U), _dp(U), int(dagger), int(parity),
                   _dp(psi), _dp(out))
@@ -137,6 +150,7 @@ def hop(lat, U, psi, dagger=False, parity=-1):
 def dslash(lat, U, kappa, psi, dagger=False):
     """D_W psi = psi - kappa H psi (dagger: D_W^dag psi)."""
     U, psi = _c128(U), _c128(psi)
+    _check(lat, U, psi)
     out = np.zeros_like(psi)
     lib().orc_dslash(_ip(lat.dims), _ip(lat.bc), _d_of(U), _dp(U), float(kappa), int(dagger),
                      _dp(psi), _dp(out))
@@ -146,7 +160,10 @@ def dslash(lat, U, kappa, psi, dagger=False):
 def dslash_sites(lat, U, kappa, psi, sites, dagger=False):
     """(D_W psi)(x) at the listed canonical site indices only."""
     U, psi = _c128(U), _c128(psi)
+    _check(lat, U, psi)
     sites = np.ascontiguousarray(sites, dtype=np.int64)
+    if len(sites) and (sites.min() < 0 or sites.max() >= int(np.prod(lat.dims))):
+        raise ValueError("site index outside the lattice")
     d = _d_of(U)
     out = np.zeros((len(sites), 4, d), np.complex128)
     lib().orc_dslash_sites(_ip(lat.dims), _ip(lat.bc), d, _dp(U), float(kappa), int(dagger),
@@ -158,6 +175,7 @@ def dslash_sites(lat, U, kappa, psi, sites, dagger=False):
 def schur_apply(lat, U, kappa, psi, dagger=False):
     """Dhat psi on even sites (odd sites of the result are zero)."""
     U, psi = _c128(U), _c128(psi)
+    _check(lat, U, psi)
     out = np.zeros_like(psi)
     lib().orc_op_apply(_ip(lat.dims), _ip(lat.bc), _d_of(U), _dp(U), float(kappa), 1,
                        int(dagger), _dp(psi), _dp(out))
@@ -166,6 +184,7 @@ def schur_apply(lat, U, kappa, psi, dagger=False):
 
 def true_residual(lat, U, kappa, b, x) -> float:
     U, b, x = _c128(U), _c128(b), _c128(x)
+    _check(lat, U, b, x)
     return lib().orc_true_residual(_ip(lat.dims), _ip(lat.bc), _d_of(U), _dp(U), float(kappa),
                                    _dp(b), _dp(x))
 
@@ -173,6 +192,7 @@ def true_residual(lat, U, kappa, b, x) -> float:
 def solve(lat, U, kappa, b, tol=1e-10, schur=False, maxit=100000):
     """x with ||b - D x|| / ||b|| <= tol.  Returns (x, info dict)."""
     U, b = _c128(U), _c128(b)
+    _check(lat, U, b)
     x = np.zeros_like(b)
     info = np.zeros(3)
     rc = lib().orc_solve(_ip(lat.dims), _ip(lat.bc), _d_of(U), _dp(U), float(kappa), int(schur),
@@ -186,6 +206,7 @@ def cgnr_raw(lat, U, kappa, b, x0=None, tol=1e-10, maxit=100000, schur=False):
     (x, iterations, relative normal residual)."""
     U, b = _c128(U), _c128(b)
     x = np.zeros_like(b) if x0 is None else _c128(x0).copy()
+    _check(lat, U, b, x)
     rel = C.c_double(0)
     it = lib().orc_cgnr_raw(_ip(lat.dims), _ip(lat.bc), _d_of(U), _dp(U), float(kappa),
                             int(schur), _dp(b), _dp(x), float(tol), int(maxit), C.byref(rel))

@@ -85,10 +85,11 @@ def test_block_hop_without_x():
         assert err < FP32_TOL
 
 
-@pytest.mark.parametrize("n_rhs", [16, 7, 3])
+@pytest.mark.parametrize("n_rhs", [16, 7, 3, 1])
 def test_batched_solve_adjoint(n_rhs):
     """16 and 7 RHS retire together and take the block operator's FP64 true
-    residual (and odd-site rebuild); 3 RHS take the per-RHS one"""
+    residual (and odd-site rebuild); 3 RHS and a single one take the per-RHS
+    one"""
     note(f"batched solve adjoint n_rhs={n_rhs}")
     lat = gen.Lattice(8, 4, 4, 6)
     Uf = gen.gauge_links(lat, 4, "haar", 720)
@@ -101,7 +102,7 @@ def test_batched_solve_adjoint(n_rhs):
     x = torch.zeros_like(bb)
     prm = bsm.solver_params(0.1, 1e-10, schur=True, check_every=8)
     status, stats = S.ctx.bsm_batched_solve(S.desc, S.U, prm, kappas, bb, x)
-    xs = S.unpack(x, n_rhs=n_rhs)
+    xs = S.unpack(x, n_rhs=n_rhs).reshape(b.shape)
     print(stats[0], stats[-1])
     assert status == 0
     for r in range(n_rhs):
@@ -369,6 +370,43 @@ def test_half_block_hop_matches_oracle_per_rhs(N, n_rhs):
     print(f"half block hop N={N} n_rhs={n_rhs}: max rel err {worst:.2e}", flush=True)
 
 
+def test_half_block_hop_full_size_sampled():
+    """24^3x48 SU(4) adjoint, FP16 blocks and links, under the plan the F16S
+    batched solver tunes: out_r = x_r - H in_r with x = in = the FP16 storage
+    of psi_r gives D(kappa=1) on the output parity, compared at sampled sites
+    with the oracle applied to the decoded FP16 input."""
+    note("half block hop full size sampled")
+    lat = gen.config_lattice(4)
+    Uf = gen.config_links(4, lat)
+    S = Setup(lat, 4, "adj", Uf, prec="f64")
+    UR = oracle.represent(Uf, "adj").real.astype(np.complex128)
+    dh = _half_desc(4)
+    Uh = S.ctx.new_block_gauge(dh)
+    S.ctx.bsm_gauge_to_block(dh, S.U, Uh)
+    S.ctx.bsm_block_autotune(dh, Uh)
+    n_rhs = 3
+    psi = gen.gaussian_spinor(lat, 15, 745, n_rhs=n_rhs)
+    A = S.ctx.new_block(dh)
+    S.ctx.bsm_pack_block(dh, c128(psi), A, n_rhs)
+    psi_q = _quantised(psi)
+    del psi
+    nb = S.ctx.block_bytes(dh) // 2
+    par = oracle.parity_mask(lat)
+    rng = np.random.default_rng(6)
+    for p in (0, 1):
+        out = S.ctx.new_block(dh)
+        S.ctx.bsm_dslash_eo_block(dh, Uh, p, 0, np.ones(16), A[p * nb:(p + 1) * nb], -np.ones(16),
+                                  A[(1 - p) * nb:(2 - p) * nb], out[p * nb:(p + 1) * nb])
+        got = _unpack_block_as(S, dh, out, n_rhs)
+        sites = np.flatnonzero(par == p)
+        sample = np.concatenate([sites[:64], sites[-64:], rng.choice(sites, 256, replace=False)])
+        for r in range(n_rhs):
+            ref = oracle.dslash_sites(lat, UR, 1.0, psi_q[r], sample)
+            err = rel(got[r][sample], ref)
+            print(f"full-size FP16 block hop p={p} rhs {r}: rel err {err:.2e}", flush=True)
+            assert err < F16_TOL, (p, r, err)
+
+
 def _unpack_block_as(S, d, blk, n):
     import torch
     out = torch.zeros((n, S.lat.V, 4, S.d), dtype=torch.complex128, device="cuda")
@@ -419,7 +457,7 @@ def test_half_block_autotune_picks_a_plan():
     assert plan["us"] > 0 and plan["sites_per_wave"] == 1 and plan["waves_per_group"] in (1, 2, 4)
 
 
-@pytest.mark.parametrize("n_rhs", [16, 3])
+@pytest.mark.parametrize("n_rhs", [16, 3, 1])
 def test_batched_solve_adjoint_f16(n_rhs):
     """F16S inner recurrence (FP16 block fields, links and matrix cores) with
     FP64 reliable updates: every RHS to a 1e-10 FP64 true residual"""
@@ -435,7 +473,7 @@ def test_batched_solve_adjoint_f16(n_rhs):
     x = torch.zeros_like(bb)
     prm = bsm.solver_params(0.1, 1e-10, schur=True, check_every=0)   # the F16S default replay length
     status, stats = S.ctx.bsm_batched_solve(_half_desc(4), S.U, prm, kappas, bb, x)
-    xs = S.unpack(x, n_rhs=n_rhs)
+    xs = S.unpack(x, n_rhs=n_rhs).reshape(b.shape)
     print(stats[0], stats[-1], flush=True)
     assert status == 0
     for r in range(n_rhs):
