@@ -50,8 +50,11 @@ TASK_THEORIES = ((2, "fund", "comms"), (3, "fund", "balance"), (6, "fund", "comp
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hop_f32_32x32x32x64_su3_traffic.md")
 
 
+_T0 = time.time()
+
+
 def log(msg):
-    print(msg, file=sys.stderr, flush=True)
+    print(f"[{time.time() - _T0:6.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def hop_bytes(d, real, sprec, lprec, n_out_sites):
