@@ -17,6 +17,15 @@
 //                (a_(n-1) zeta_(n-1) (1 + delta a_n) + a_n b_(n-1) (zeta_(n-1) - zeta_n)),
 //   a_n^i = a_n zeta_(n+1) / zeta_n,  b_n^i = b_n (zeta_(n+1) / zeta_n)^2,
 //   x^i += a_n^i p^i,  p^i = zeta_(n+1) r_(n+1) + b_n^i p^i.
+// The member vectors are not touched every iteration: x_i and p_i are linear
+// combinations of the seed's residuals, so the last L residuals are kept (a
+// ring of L + 1 fields) and each member carries, on the host, its
+// coefficients on p_i and x_i as they stood at the start of the chunk and on
+// those residuals; every L iterations (and at the end) one pass forms
+// x_i += cx0 p_i + sum_k cx_k r_k and p_i = cp0 p_i + sum_k cp_k r_k for all
+// members.  That reads the L residuals once per chunk instead of reading and
+// writing 2 n member fields every iteration; the seed's own direction, which
+// the operator needs every iteration, is kept explicitly.
 // Shift i retires once |zeta_i| |r| <= (the caller's delta) tol |b|; afterwards every x_i is
 // divided by kappa_i and judged by its FP64 true residual ||b - D(kappa_i) x_i||
 // / ||b||; a member that misses tol (or a breakdown, a non-finite value) is
@@ -35,6 +44,8 @@ namespace bsm {
 
 constexpr int kMaxShifts = 32;
 constexpr int kMsBlocks = 16384;   // reduction workgroups (grid-stride beyond)
+constexpr int kMsChunk = 16;       // iterations between member updates (at most)
+constexpr int kMsCoefRow = 2 * (kMsChunk + 2);   // per member: cx0, cx[0..L], cp0, cp[0..L]
 
 struct MsGeom {
     size_t n;        // complex elements of a full FP64 field (incl. padding)
@@ -61,9 +72,10 @@ __global__ __launch_bounds__(256) void k_ms_jdot(MsGeom m, const double2 *a, con
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-// r -= alpha q; partials of r^dag gamma5 r (first gridDim.x) and |r|^2 (next)
-__global__ __launch_bounds__(256) void k_ms_residual(MsGeom m, double2 *r, const double2 *q, double alpha,
-                                                     double *partials) {
+// r_out = r - alpha q; partials of r_out^dag gamma5 r_out (first gridDim.x)
+// and |r_out|^2 (next)
+__global__ __launch_bounds__(256) void k_ms_residual(MsGeom m, const double2 *r, const double2 *q, double alpha,
+                                                     double2 *r_out, double *partials) {
     double sj = 0.0, s2 = 0.0;
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < m.n; e += (size_t)gridDim.x * 256) {
         double g5;
@@ -72,7 +84,7 @@ __global__ __launch_bounds__(256) void k_ms_residual(MsGeom m, double2 *r, const
         const double2 y = q[e];
         x.x = fma(-alpha, y.x, x.x);
         x.y = fma(-alpha, y.y, x.y);
-        r[e] = x;
+        r_out[e] = x;
         const double n2 = x.x * x.x + x.y * x.y;
         sj = fma(g5, n2, sj);
         s2 += n2;
@@ -86,32 +98,51 @@ __global__ __launch_bounds__(256) void k_ms_residual(MsGeom m, double2 *r, const
     }
 }
 
-struct MsCoef {
-    double a[kMaxShifts], b[kMaxShifts], z[kMaxShifts];
-    uint32_t mask;   // shifts whose x is updated
-    uint32_t pmask;  // shifts whose p is updated (the seed's always, while any shift runs)
-};
-
-// x_i += a_i p_i ; p_i = z_i r + b_i p_i  for the shifts in the masks; fields
-// are stride complex numbers apart
-__global__ __launch_bounds__(256) void k_ms_update(MsGeom m, const double2 *r, double2 *x, double2 *p, size_t stride,
-                                                   int n, MsCoef c) {
+// One chunk's member updates.  R holds nring residual fields (stride complex
+// numbers apart); chunk residual k is field (ring0 + k) % nring, k < nk.  For
+// member i (coefficient row coef + i kMsCoefRow: cx0, cx[0..nk), then at
+// kMsChunk + 2: cp0, cp[0..nk)):
+//   x_i += cx0 p_i + sum_k cx_k r_k   (members in xmask)
+//   p_i  = cp0 p_i + sum_k cp_k r_k   (members in pmask)
+// The coefficients are read by every lane alike (scalar loads).
+__global__ __launch_bounds__(256) void k_ms_flush(MsGeom m, const double2 *R, size_t stride, int ring0, int nring,
+                                                  int nk, double2 *x, double2 *p, int n, uint32_t xmask,
+                                                  uint32_t pmask, const double *coef) {
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < m.n; e += (size_t)gridDim.x * 256) {
         double g5;
         if (!ms_live(m, e, g5)) continue;
-        const double2 rv = r[e];
+        double2 rv[kMsChunk + 1];
+#pragma unroll
+        for (int k = 0; k <= kMsChunk; k++)
+            if (k < nk) rv[k] = R[(size_t)((ring0 + k) % nring) * stride + e];
         for (int i = 0; i < n; i++) {
-            if (!((c.pmask >> i) & 1u)) continue;
-            double2 pv = p[i * stride + e];
-            if ((c.mask >> i) & 1u) {
+            const uint32_t bit = 1u << i;
+            if (!((xmask | pmask) & bit)) continue;
+            const double *c = coef + (size_t)i * kMsCoefRow;
+            const double2 pv = p[i * stride + e];
+            if (xmask & bit) {
                 double2 xv = x[i * stride + e];
-                xv.x = fma(c.a[i], pv.x, xv.x);
-                xv.y = fma(c.a[i], pv.y, xv.y);
+                xv.x = fma(c[0], pv.x, xv.x);
+                xv.y = fma(c[0], pv.y, xv.y);
+#pragma unroll
+                for (int k = 0; k <= kMsChunk; k++)
+                    if (k < nk) {
+                        xv.x = fma(c[1 + k], rv[k].x, xv.x);
+                        xv.y = fma(c[1 + k], rv[k].y, xv.y);
+                    }
                 x[i * stride + e] = xv;
             }
-            pv.x = fma(c.z[i], rv.x, c.b[i] * pv.x);
-            pv.y = fma(c.z[i], rv.y, c.b[i] * pv.y);
-            p[i * stride + e] = pv;
+            if (pmask & bit) {
+                const double *cq = c + kMsChunk + 2;
+                double2 np = make_double2(cq[0] * pv.x, cq[0] * pv.y);
+#pragma unroll
+                for (int k = 0; k <= kMsChunk; k++)
+                    if (k < nk) {
+                        np.x = fma(cq[1 + k], rv[k].x, np.x);
+                        np.y = fma(cq[1 + k], rv[k].y, np.y);
+                    }
+                p[i * stride + e] = np;
+            }
         }
     }
 }
@@ -167,21 +198,35 @@ extern "C" bsm_status bsm_shifted_solve(bsm_ctx ctx, const bsm_field_desc *desc,
     const double sigma0 = 1.0 / kappas[seed];
     std::vector<double> delta(n);
     for (int i = 0; i < n; i++) delta[i] = 1.0 / kappas[i] - sigma0;
-    // scratch: r, A p, the full-lattice residual field, and one p per shift
+    // scratch: A p, the full-lattice residual field, the seed's explicit
+    // direction, a ring of L + 1 residuals, one p per shift and the member
+    // coefficients; L shrinks when the device cannot hold the ring
+    const size_t coef_bytes = (size_t)n * kMsCoefRow * sizeof(double);
+    int L = kMsChunk;
     void *work = nullptr;
-    TRY(ctx_work(ctx, (3 + (size_t)n) * full, &work));
-    char *r = (char *)work, *Ap = r + full, *tfull = Ap + full, *P = tfull + full;
+    for (;;) {
+        const size_t need = (3 + (size_t)L + 1 + n) * full + (coef_bytes + 255) / 256 * 256;
+        const bsm_status ws = ctx_work(ctx, need, &work);
+        if (ws == BSM_OK) break;
+        (void)hipGetLastError();   // the failed allocation's error is not this solve's
+        if (L == 1) return ws;
+        L /= 2;
+    }
+    char *Ap = (char *)work, *tfull = Ap + full, *Pd = tfull + full, *R = Pd + full;
+    char *P = R + (size_t)(L + 1) * full;
+    double *dcoef = (double *)(P + (size_t)n * full);
     char *X = (char *)x;
     const Vec none{nullptr, BSM_F64};
     BSM_HIP(hipMemsetAsync(X, 0, (size_t)n * full, st));
-    BSM_HIP(hipMemcpyAsync(r, b, full, hipMemcpyDeviceToDevice, st));
+    BSM_HIP(hipMemcpyAsync(R, b, full, hipMemcpyDeviceToDevice, st));
+    BSM_HIP(hipMemcpyAsync(Pd, b, full, hipMemcpyDeviceToDevice, st));
     for (int i = 0; i < n; i++) BSM_HIP(hipMemcpyAsync(P + i * full, b, full, hipMemcpyDeviceToDevice, st));
     double *parts = ctx->partials;
     const int grid = ms_grid(m);
     double bnorm2 = 0.0, rrJ = 0.0;
     TRY(blas_dot(g, d, 2, Vec{(void *)b, BSM_F64}, none, parts, st));
     TRY(ms_sum(ctx, parts, blas_blocks(g, 2), &bnorm2, st));
-    k_ms_jdot<<<grid, 256, 0, st>>>(m, (const double2 *)r, (const double2 *)r, parts);
+    k_ms_jdot<<<grid, 256, 0, st>>>(m, (const double2 *)R, (const double2 *)R, parts);
     BSM_HIP(hipGetLastError());
     TRY(ms_sum(ctx, parts, grid, &rrJ, st));
     // the operator A = sigma_0 - H on full fields, links as the descriptor says
@@ -202,7 +247,33 @@ extern "C" bsm_status bsm_shifted_solve(bsm_ctx ctx, const bsm_field_desc *desc,
         apply_plan(ctx, d, real, BSM_F64, lc, a);
         return launch_hop(g, d, real, BSM_F64, lc, a, st);
     };
-    std::vector<double> zeta(n, 1.0), zeta_prev(n, 1.0), zn(n, 1.0);
+    // member coefficients on (p_i at the chunk start, chunk residuals 0..j)
+    std::vector<double> coef((size_t)n * kMsCoefRow, 0.0);
+    auto cx = [&](int i, int k) -> double & { return coef[(size_t)i * kMsCoefRow + 1 + k]; };   // k = -1: cx0
+    auto cp = [&](int i, int k) -> double & { return coef[(size_t)i * kMsCoefRow + kMsChunk + 3 + k]; };
+    auto reset = [&]() {
+        std::fill(coef.begin(), coef.end(), 0.0);
+        for (int i = 0; i < n; i++) cp(i, -1) = 1.0;
+    };
+    reset();
+    int ring0 = 0, j = 0;        // the chunk's first residual field, iterations done in the chunk
+    uint32_t xtouched = 0;       // members whose x has a contribution pending
+    auto Rk = [&](int k) { return R + (size_t)((ring0 + k) % (L + 1)) * full; };
+    auto flush = [&](uint32_t pkeep) -> bsm_status {
+        if (j == 0) return BSM_OK;
+        BSM_HIP(hipMemcpyAsync(dcoef, coef.data(), coef_bytes, hipMemcpyHostToDevice, st));
+        k_ms_flush<<<std::min<int>((int)((m.n + 255) / 256), 65536), 256, 0, st>>>(
+            m, (const double2 *)R, full / sizeof(double2), ring0, L + 1, j + 1, (double2 *)X, (double2 *)P, n,
+            xtouched, pkeep, dcoef);
+        BSM_HIP(hipGetLastError());
+        BSM_HIP(hipStreamSynchronize(st));   // coef is rewritten below
+        ring0 = (ring0 + j) % (L + 1);
+        j = 0;
+        xtouched = 0;
+        reset();
+        return BSM_OK;
+    };
+    std::vector<double> zeta(n, 1.0), zeta_prev(n, 1.0), zn(n, 1.0), ca(n, 0.0), cb(n, 0.0);
     std::vector<int> iters(n, 0);
     uint32_t active = n == 32 ? 0xffffffffu : ((1u << n) - 1);
     double a_prev = 1.0, b_prev = 0.0;
@@ -210,51 +281,58 @@ extern "C" bsm_status bsm_shifted_solve(bsm_ctx ctx, const bsm_field_desc *desc,
     int it = 0;
     bool broke = !(bnorm2 > 0) || !std::isfinite(rrJ);
     while (!broke && active && it < prm->max_iter) {
-        const char *pseed = P + seed * full;
-        TRY(applyA(pseed, Ap));
+        TRY(applyA(Pd, Ap));
         double pAp = 0.0;
-        k_ms_jdot<<<grid, 256, 0, st>>>(m, (const double2 *)pseed, (const double2 *)Ap, parts);
+        k_ms_jdot<<<grid, 256, 0, st>>>(m, (const double2 *)Pd, (const double2 *)Ap, parts);
         BSM_HIP(hipGetLastError());
         TRY(ms_sum(ctx, parts, grid, &pAp, st));
         if (!std::isfinite(pAp) || pAp == 0.0) { broke = true; break; }
         const double alpha = rrJ / pAp;
-        MsCoef c{};
-        // members still iterating (the seed's p drives the recurrence and is
-        // kept while any member runs); retired members keep their zeta
+        // members still iterating (the seed's direction drives the recurrence
+        // and is kept while any member runs); retired members keep their zeta
         const uint32_t run = active | (1u << seed);
         for (int i = 0; i < n; i++) {
             if (!((run >> i) & 1u)) continue;
             const double den = a_prev * zeta_prev[i] * (1.0 + delta[i] * alpha) +
                                alpha * b_prev * (zeta_prev[i] - zeta[i]);
             zn[i] = zeta[i] * zeta_prev[i] * a_prev / den;
-            c.a[i] = alpha * zn[i] / zeta[i];
+            ca[i] = alpha * zn[i] / zeta[i];
         }
-        k_ms_residual<<<grid, 256, 0, st>>>(m, (double2 *)r, (const double2 *)Ap, alpha, parts);
+        k_ms_residual<<<grid, 256, 0, st>>>(m, (const double2 *)Rk(j), (const double2 *)Ap, alpha,
+                                            (double2 *)Rk(j + 1), parts);
         BSM_HIP(hipGetLastError());
         double rrJ_new = 0.0, rn2 = 0.0;
         TRY(ms_sum(ctx, parts, grid, &rrJ_new, st));
         TRY(ms_sum(ctx, parts + grid, grid, &rn2, st));
         const double beta = rrJ_new / rrJ;
+        bool finite = std::isfinite(alpha) && std::isfinite(beta) && std::isfinite(rn2);
         for (int i = 0; i < n; i++) {
             if (!((run >> i) & 1u)) continue;
             const double q = zn[i] / zeta[i];
-            c.b[i] = beta * q * q;
-            c.z[i] = zn[i];
+            cb[i] = beta * q * q;
+            if (!std::isfinite(zn[i]) || !std::isfinite(ca[i]) || !std::isfinite(cb[i])) finite = false;
         }
-        c.mask = active;
-        c.pmask = run;
-        k_ms_update<<<std::min<int>((int)((m.n + 255) / 256), 65536), 256, 0, st>>>(
-            m, (const double2 *)r, (double2 *)X, (double2 *)P, full / sizeof(double2), n, c);
-        BSM_HIP(hipGetLastError());
+        if (!finite) { broke = true; break; }
+        // x_i += a_i p_i (members still active), p_i = z_i r_(n+1) + b_i p_i
+        // (members running), on the coefficients; the seed's direction itself
+        for (int i = 0; i < n; i++) {
+            if (!((run >> i) & 1u)) continue;
+            if ((active >> i) & 1u) {
+                for (int k = -1; k <= j; k++) cx(i, k) += ca[i] * cp(i, k);
+                xtouched |= 1u << i;
+            }
+            for (int k = -1; k <= j; k++) cp(i, k) *= cb[i];
+            cp(i, j + 1) += zn[i];
+        }
+        TRY(blas_axpby(g, d, 2, Vec{Pd, BSM_F64}, 1.0, Vec{Rk(j + 1), BSM_F64}, beta, Vec{Pd, BSM_F64}, nullptr,
+                       st));
+        j++;
         it++;
-        bool finite = std::isfinite(alpha) && std::isfinite(beta) && std::isfinite(rn2);
         for (int i = 0; i < n; i++) {
             if (!((run >> i) & 1u)) continue;
             zeta_prev[i] = zeta[i];
             zeta[i] = zn[i];
-            if (!std::isfinite(zeta[i]) || !std::isfinite(c.a[i]) || !std::isfinite(c.b[i])) finite = false;
         }
-        if (!finite) { broke = true; break; }
         a_prev = alpha;
         b_prev = beta;
         rrJ = rrJ_new;
@@ -264,7 +342,9 @@ extern "C" bsm_status bsm_shifted_solve(bsm_ctx ctx, const bsm_field_desc *desc,
                 active &= ~(1u << i);
                 iters[i] = it;
             }
+        if (j == L && active) TRY(flush(active | (1u << seed)));
     }
+    TRY(flush(0));
     for (int i = 0; i < n; i++)
         if (!iters[i]) iters[i] = it;
     // x_i = y_i / kappa_i (D(kappa) y = kappa b), then each member's FP64 true residual decides
