@@ -471,7 +471,11 @@ bsm_status bsm_batched_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void
  * with BSM_LINKS_FUNDAMENTAL); b: full FP64 field; x: n_kappa consecutive
  * full FP64 fields, overwritten; stats: host array of n_kappa (iters =
  * shared iterations until the member retired, plus fallback iterations).
- * Scratch: the context's, (3 + n_kappa) full FP64 fields.  Synchronous. */
+ * The members' solutions and directions are formed from the kept seed
+ * residuals every 16 iterations (and at the end) rather than each iteration.
+ * Scratch: the context's, (20 + n_kappa) full FP64 fields (fewer residuals
+ * are kept, down to (5 + n_kappa) fields, when that much device memory is
+ * not available; BSM_ERR_NOMEM below that).  Synchronous. */
 bsm_status bsm_shifted_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep64,
                              const bsm_solver_params *params, int32_t n_kappa, const double *kappas,
                              const void *b, void *x, bsm_solver_stats *stats, void *stream);
