@@ -104,10 +104,17 @@ __global__ __launch_bounds__(256) void k_ms_residual(MsGeom m, const double2 *r,
 // kMsChunk + 2: cp0, cp[0..nk)):
 //   x_i += cx0 p_i + sum_k cx_k r_k   (members in xmask)
 //   p_i  = cp0 p_i + sum_k cp_k r_k   (members in pmask)
-// The coefficients are read by every lane alike (scalar loads).
+// The members to touch come as a list; four are loaded together so their
+// loads overlap.  The coefficients are read by every lane alike.
+struct MsFlushList {
+    int n;
+    int idx[kMaxShifts];
+    uint32_t xmask, pmask;
+};
+
 __global__ __launch_bounds__(256) void k_ms_flush(MsGeom m, const double2 *R, size_t stride, int ring0, int nring,
-                                                  int nk, double2 *x, double2 *p, int n, uint32_t xmask,
-                                                  uint32_t pmask, const double *coef) {
+                                                  int nk, double2 *x, double2 *p, MsFlushList L,
+                                                  const double *coef) {
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < m.n; e += (size_t)gridDim.x * 256) {
         double g5;
         if (!ms_live(m, e, g5)) continue;
@@ -115,33 +122,43 @@ __global__ __launch_bounds__(256) void k_ms_flush(MsGeom m, const double2 *R, si
 #pragma unroll
         for (int k = 0; k <= kMsChunk; k++)
             if (k < nk) rv[k] = R[(size_t)((ring0 + k) % nring) * stride + e];
-        for (int i = 0; i < n; i++) {
-            const uint32_t bit = 1u << i;
-            if (!((xmask | pmask) & bit)) continue;
-            const double *c = coef + (size_t)i * kMsCoefRow;
-            const double2 pv = p[i * stride + e];
-            if (xmask & bit) {
-                double2 xv = x[i * stride + e];
-                xv.x = fma(c[0], pv.x, xv.x);
-                xv.y = fma(c[0], pv.y, xv.y);
+        for (int q0 = 0; q0 < L.n; q0 += 4) {
+            double2 pv[4], xv[4];
 #pragma unroll
-                for (int k = 0; k <= kMsChunk; k++)
-                    if (k < nk) {
-                        xv.x = fma(c[1 + k], rv[k].x, xv.x);
-                        xv.y = fma(c[1 + k], rv[k].y, xv.y);
-                    }
-                x[i * stride + e] = xv;
+            for (int u = 0; u < 4; u++) {
+                if (q0 + u >= L.n) continue;
+                const int i = L.idx[q0 + u];
+                pv[u] = p[i * stride + e];
+                if ((L.xmask >> i) & 1u) xv[u] = x[i * stride + e];
             }
-            if (pmask & bit) {
-                const double *cq = c + kMsChunk + 2;
-                double2 np = make_double2(cq[0] * pv.x, cq[0] * pv.y);
 #pragma unroll
-                for (int k = 0; k <= kMsChunk; k++)
-                    if (k < nk) {
-                        np.x = fma(cq[1 + k], rv[k].x, np.x);
-                        np.y = fma(cq[1 + k], rv[k].y, np.y);
-                    }
-                p[i * stride + e] = np;
+            for (int u = 0; u < 4; u++) {
+                if (q0 + u >= L.n) continue;
+                const int i = L.idx[q0 + u];
+                const double *c = coef + (size_t)i * kMsCoefRow;
+                if ((L.xmask >> i) & 1u) {
+                    double2 a = xv[u];
+                    a.x = fma(c[0], pv[u].x, a.x);
+                    a.y = fma(c[0], pv[u].y, a.y);
+#pragma unroll
+                    for (int k = 0; k <= kMsChunk; k++)
+                        if (k < nk) {
+                            a.x = fma(c[1 + k], rv[k].x, a.x);
+                            a.y = fma(c[1 + k], rv[k].y, a.y);
+                        }
+                    x[i * stride + e] = a;
+                }
+                if ((L.pmask >> i) & 1u) {
+                    const double *cq = c + kMsChunk + 2;
+                    double2 np = make_double2(cq[0] * pv[u].x, cq[0] * pv[u].y);
+#pragma unroll
+                    for (int k = 0; k <= kMsChunk; k++)
+                        if (k < nk) {
+                            np.x = fma(cq[1 + k], rv[k].x, np.x);
+                            np.y = fma(cq[1 + k], rv[k].y, np.y);
+                        }
+                    p[i * stride + e] = np;
+                }
             }
         }
     }
@@ -261,10 +278,15 @@ extern "C" bsm_status bsm_shifted_solve(bsm_ctx ctx, const bsm_field_desc *desc,
     auto Rk = [&](int k) { return R + (size_t)((ring0 + k) % (L + 1)) * full; };
     auto flush = [&](uint32_t pkeep) -> bsm_status {
         if (j == 0) return BSM_OK;
+        MsFlushList fl{};
+        fl.xmask = xtouched;
+        fl.pmask = pkeep;
+        for (int i = 0; i < n; i++)
+            if (((xtouched | pkeep) >> i) & 1u) fl.idx[fl.n++] = i;
         BSM_HIP(hipMemcpyAsync(dcoef, coef.data(), coef_bytes, hipMemcpyHostToDevice, st));
         k_ms_flush<<<std::min<int>((int)((m.n + 255) / 256), 65536), 256, 0, st>>>(
-            m, (const double2 *)R, full / sizeof(double2), ring0, L + 1, j + 1, (double2 *)X, (double2 *)P, n,
-            xtouched, pkeep, dcoef);
+            m, (const double2 *)R, full / sizeof(double2), ring0, L + 1, j + 1, (double2 *)X, (double2 *)P, fl,
+            dcoef);
         BSM_HIP(hipGetLastError());
         BSM_HIP(hipStreamSynchronize(st));   // coef is rewritten below
         ring0 = (ring0 + j) % (L + 1);
