@@ -1131,6 +1131,39 @@ def finish_oracle_reference(proc, path, solutions, threads):
     return out
 
 
+def oracle_cfg4_reference(group, threads):
+    """The oracle's FP64 Schur CG on the 24^3 x 48 SU(4) adjoint workload for
+    the extreme kappas (0.10 with source 0, 0.125 with source 15), each to
+    1e-10 (timed) and continued to 1e-13; every kept GPU solution of the same
+    (kappa, source) is compared with that reference.  About 4 minutes on 16
+    host threads, so only with --oracle-cfg4."""
+    import oracle
+    oracle.set_num_threads(threads)
+    lat = group["lat"]
+    U = oracle.represent(group["Uf"], "adj").real.astype(np.complex128)
+    items = group["items"]
+    kappas = sorted({it[1] for it in items})
+    out = {}
+    for kappa, r in ((kappas[0], 0), (kappas[-1], 15)):
+        # the source of RHS r is the one its batched solution was checked with
+        b = next(it[2] for it in items if it[0] == f"batched_k{r}")
+        t0 = time.perf_counter()
+        x, info = oracle.solve(lat, U, kappa, b, tol=1e-10, schur=True)
+        t10 = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        x, res, extra = _oracle_solve_to(lat, U, kappa, b, x, info)
+        nr = np.linalg.norm(x)
+        errs = {it[0]: float(np.linalg.norm(it[3] - x) / nr) for it in items
+                if it[1] == kappa and it[2] is b}
+        out[f"kappa_{kappa:.4f}_source_{r}"] = {
+            "tts_1e-10_seconds": round(t10, 3), "iters_1e-10": info["iters"],
+            "true_rel_res_1e-10": info["true_res"], "reference_true_rel_res": res,
+            "reference_extra_iters": extra, "reference_extra_seconds": round(time.perf_counter() - t1, 3),
+            "threads": oracle.num_threads(), "x_rel_err_vs_oracle": errs}
+        log(f"  oracle cfg4 kappa {kappa:.4f}: {out[f'kappa_{kappa:.4f}_source_{r}']}")
+    return out
+
+
 def cpu_cfg1(solution):
     """The oracle's FP64 CG on the full D^dag D for the 4^4 SU(2) workload:
     time-to-solution at 1e-10 and the GPU solution against the oracle's
@@ -1229,6 +1262,8 @@ def main():
                     help="minimum timed period of each task of the paper's benchmark")
     ap.add_argument("--hop-plans", type=str, default="",
                     help="also time the FP32 hop under each listed walk plan, 'order:tchunk,...'")
+    ap.add_argument("--oracle-cfg4", action="store_true",
+                    help="also solve the adjoint workload's extreme kappas with the oracle (about 4 min)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run N plain 1 GiB device copies (counter calibration)")
     args = ap.parse_args()
@@ -1315,6 +1350,9 @@ def main():
             forms["mixed_precision"]["oracle_reference"] = refs[3]
             log(f"  {refs[3]}")
         keep = sols = None
+    if args.oracle_cfg4 and checks is not None and "cfg4" in checks.groups:
+        log("oracle FP64 reference solves of the adjoint workload (kappa 0.10 and 0.125) ...")
+        forms["batched"]["oracle_reference"] = oracle_cfg4_reference(checks.groups["cfg4"], cores)
     if checks is not None and checks.groups:
         log("oracle FP64 true residuals of the full-size GPU solutions ...")
         for key, v in checks.run(cores).items():
