@@ -261,20 +261,33 @@ bsm_status block_autotune(bsm_ctx ctx, int d, const float *U_block, float2 *scra
 }
 
 // --------------------------------------------------------------- layouts
+// 32 sites per workgroup: the link elements are read plane by plane (lanes
+// on consecutive sites) into LDS as [site][i * d + j], which is already the
+// block layout of those 32 sites, then written out contiguously (one thread
+// per site wrote 225 floats 900 bytes apart from its neighbour's)
+constexpr int kLinkTile = 32;
+
 template <int LP>
 __global__ __launch_bounds__(256) void k_gauge_to_block(Geom g, int d, const char *src, float *dst) {
-    const uint32_t h = blockIdx.x * 256 + threadIdx.x;
+    __shared__ float t[kLinkTile * 225];
+    const uint32_t h0 = blockIdx.x * kLinkTile;
     const int qm = blockIdx.y;   // parity * 4 + mu
-    if (h >= (uint32_t)g.Vh_pad) return;
-    const int dd = d * d;
+    const int dd = d * d, ldt = dd | 1;   // odd row stride: no LDS bank conflicts
+    const int ns = min(kLinkTile, (int)((uint32_t)g.Vh_pad - h0));
     const char *blk = src + (size_t)qm * link_block_bytes(LP, true, d, g.Vh_pad);
-    float *o = dst + ((size_t)qm * g.Vh_pad + h) * dd;
-    for (int e = 0; e < dd; e++) o[e] = (float)load_link<LP, true, float>(blk, g.Vh_pad, e, h).re;
+    for (int idx = threadIdx.x; idx < kLinkTile * dd; idx += 256) {
+        const int e = idx / kLinkTile, s = idx - e * kLinkTile;
+        if (s < ns) t[s * ldt + e] = (float)load_link<LP, true, float>(blk, g.Vh_pad, e, h0 + s).re;
+    }
+    __syncthreads();
+    float *o = dst + ((size_t)qm * g.Vh_pad + h0) * dd;
+    for (int idx = threadIdx.x; idx < ns * dd; idx += 256) o[idx] = t[(idx / dd) * ldt + idx % dd];
 }
 
 bsm_status launch_gauge_to_block(const Geom &g, int d, int link_prec, const void *U_rep, float *U_block,
                                  hipStream_t st) {
-    dim3 grid((g.Vh_pad + 255) / 256, 8);
+    if (d > 15) return fail(BSM_ERR_ARG, "block links: d_R above 15");
+    dim3 grid((g.Vh_pad + kLinkTile - 1) / kLinkTile, 8);
     switch (link_prec) {
     case BSM_F64: k_gauge_to_block<BSM_F64><<<grid, 256, 0, st>>>(g, d, (const char *)U_rep, U_block); break;
     case BSM_F32: k_gauge_to_block<BSM_F32><<<grid, 256, 0, st>>>(g, d, (const char *)U_rep, U_block); break;

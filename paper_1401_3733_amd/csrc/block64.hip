@@ -167,19 +167,28 @@ bsm_status launch_hop_block64(const Geom &g, int d, const BlockHop64Args &a, hip
 }
 
 // --------------------------------------------------------------- layouts
+// 32 sites per workgroup, transposed through LDS as for the FP32 block links
 template <int LP>
 __global__ __launch_bounds__(256) void k_gauge_to_block64(Geom g, int d, const char *src, double *dst) {
-    const uint32_t h = blockIdx.x * 256 + threadIdx.x;
+    constexpr int S = 32;
+    __shared__ double t[S * 225];
+    const uint32_t h0 = blockIdx.x * S;
     const int qm = blockIdx.y;
-    if (h >= (uint32_t)g.Vh_pad) return;
-    const int dd = d * d;
+    const int dd = d * d, ldt = dd | 1;   // odd row stride: no LDS bank conflicts
+    const int ns = min(S, (int)((uint32_t)g.Vh_pad - h0));
     const char *blk = src + (size_t)qm * link_block_bytes(LP, true, d, g.Vh_pad);
-    double *o = dst + ((size_t)qm * g.Vh_pad + h) * dd;
-    for (int e = 0; e < dd; e++) o[e] = load_link<LP, true, double>(blk, g.Vh_pad, e, h).re;
+    for (int idx = threadIdx.x; idx < S * dd; idx += 256) {
+        const int e = idx / S, s = idx - e * S;
+        if (s < ns) t[s * ldt + e] = load_link<LP, true, double>(blk, g.Vh_pad, e, h0 + s).re;
+    }
+    __syncthreads();
+    double *o = dst + ((size_t)qm * g.Vh_pad + h0) * dd;
+    for (int idx = threadIdx.x; idx < ns * dd; idx += 256) o[idx] = t[(idx / dd) * ldt + idx % dd];
 }
 
 bsm_status launch_gauge_to_block64(const Geom &g, int d, const void *U_rep64, double *U_block, hipStream_t st) {
-    dim3 grid((g.Vh_pad + 255) / 256, 8);
+    if (d > 15) return fail(BSM_ERR_ARG, "block links: d_R above 15");
+    dim3 grid((g.Vh_pad + 31) / 32, 8);
     k_gauge_to_block64<BSM_F64><<<grid, 256, 0, st>>>(g, d, (const char *)U_rep64, U_block);
     BSM_HIP(hipGetLastError());
     return BSM_OK;

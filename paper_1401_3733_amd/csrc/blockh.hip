@@ -328,28 +328,46 @@ bsm_status blockh_autotune(bsm_ctx ctx, int d, const __half *U_blockh, char *scr
 
 // --------------------------------------------------------------- layouts
 // one thread per (site, parity * 4 + mu): both orientations of the link
+// 32 sites per workgroup: link elements read plane by plane into LDS
+// ([site][i * d + j]), then both orientations written contiguously two
+// halves per thread, the rows padded to kpad columns and the link to dk
+// halves with zeros
 template <int LP>
 __global__ __launch_bounds__(256) void k_gauge_to_blockh(Geom g, int d, const char *src, __half *dst) {
-    const uint32_t h = blockIdx.x * 256 + threadIdx.x;
+    constexpr int S = 32;
+    __shared__ float t[S * 225];
+    const uint32_t h0 = blockIdx.x * S;
     const int qm = blockIdx.y;
-    if (h >= (uint32_t)g.Vh_pad) return;
+    const int dd = d * d, ldt = dd | 1;   // odd row stride: no LDS bank conflicts
+    const int ns = min(S, (int)((uint32_t)g.Vh_pad - h0));
     const int kp = blockh_kpad(d), dk = blockh_link_halves(d);
     const char *blk = src + (size_t)qm * link_block_bytes(LP, true, d, g.Vh_pad);
-    __half *o0 = dst + ((size_t)qm * g.Vh_pad + h) * dk;
-    __half *o1 = dst + ((size_t)(8 + qm) * g.Vh_pad + h) * dk;
-    for (int i = 0; i < d; i++)
-        for (int k = 0; k < kp; k++) {
-            const float u = k < d ? (float)load_link<LP, true, float>(blk, g.Vh_pad, i * d + k, h).re : 0.f;
-            const float ut = k < d ? (float)load_link<LP, true, float>(blk, g.Vh_pad, k * d + i, h).re : 0.f;
-            o0[i * kp + k] = __float2half_rn(u);
-            o1[i * kp + k] = __float2half_rn(ut);
+    for (int idx = threadIdx.x; idx < S * dd; idx += 256) {
+        const int e = idx / S, s = idx - e * S;
+        if (s < ns) t[s * ldt + e] = (float)load_link<LP, true, float>(blk, g.Vh_pad, e, h0 + s).re;
+    }
+    __syncthreads();
+    __half2 *o0 = (__half2 *)(dst + ((size_t)qm * g.Vh_pad + h0) * dk);
+    __half2 *o1 = (__half2 *)(dst + ((size_t)(8 + qm) * g.Vh_pad + h0) * dk);
+    for (int idx = threadIdx.x; idx < ns * dk / 2; idx += 256) {
+        const int pos = 2 * idx, s = pos / dk, e = pos - s * dk;
+        float u[2], ut[2];
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            const int i = (e + c) / kp, k = (e + c) - i * kp;
+            const bool in = i < d && k < d;
+            u[c] = in ? t[s * ldt + i * d + k] : 0.f;
+            ut[c] = in ? t[s * ldt + k * d + i] : 0.f;
         }
-    for (int e = d * kp; e < dk; e++) o0[e] = o1[e] = __float2half_rn(0.f);   // line padding
+        o0[idx] = __floats2half2_rn(u[0], u[1]);
+        o1[idx] = __floats2half2_rn(ut[0], ut[1]);
+    }
 }
 
 bsm_status launch_gauge_to_blockh(const Geom &g, int d, int link_prec, const void *U_rep, __half *U_blockh,
                                   hipStream_t st) {
-    dim3 grid((g.Vh_pad + 255) / 256, 8);
+    if (d > 15) return fail(BSM_ERR_ARG, "block links: d_R above 15");
+    dim3 grid((g.Vh_pad + 31) / 32, 8);
     switch (link_prec) {
     case BSM_F64: k_gauge_to_blockh<BSM_F64><<<grid, 256, 0, st>>>(g, d, (const char *)U_rep, U_blockh); break;
     case BSM_F32: k_gauge_to_blockh<BSM_F32><<<grid, 256, 0, st>>>(g, d, (const char *)U_rep, U_blockh); break;
