@@ -837,6 +837,7 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
     std::vector<bsm_status> status(n, BSM_ERR_NOT_CONVERGED);
     std::vector<double> prev(kNR, 0.0);
     for (int r = 0; r < n; r++) prev[r] = rr[r];
+    unsigned waiting = 0;   // RHS whose recomputed residual met the trigger, waiting for the others
     while (active > 0 && it < B.prm->max_iter) {
         BSM_HIP(hipGraphLaunch(B.graph, st));
         it += B.K;
@@ -848,7 +849,14 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
                 if (hmask[r]) mx = std::max(mx, hs[B_RR * kNR + r] / B.rhs_norm2[r]);
             fprintf(stderr, "[batched] it %d active %d max rel normal residual^2 %.3e\n", it, active, mx);
         }
-        unsigned upd = 0;
+        // Every block operation serves all 16 columns, so retiring one RHS
+        // early saves nothing.  An RHS whose recomputed residual met its
+        // trigger waits (no further reliable updates) for the others; the
+        // FP64 true residuals are taken once every RHS still running claims
+        // convergence, and when they all claim it on their recurrence
+        // residuals, before the FP64 normal residual (four FP64 block hops),
+        // which only those that miss tol then need.
+        unsigned upd = 0, claim = waiting, running = 0;
         std::vector<double> before(kNR, 0.0);
         for (int r = 0; r < n; r++) {
             if (!hmask[r]) continue;
@@ -863,20 +871,52 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
                 status[r] = BSM_ERR_NONFINITE;
                 hmask[r] = 0;
                 active--;
+                waiting &= ~(1u << r);
+                claim &= ~(1u << r);
                 continue;
             }
+            running |= 1u << r;
             const double rnow = hs[B_RR * kNR + r];
             before[r] = B.K >= 2 ? hs[(B_HIST + B.K - 2) * kNR + r] : prev[r];
             prev[r] = rnow;
-            if (rnow < delta2 * maxrr[r] || rnow <= trig[r] * trig[r] * B.rhs_norm2[r]) upd |= 1u << r;
+            if ((waiting >> r) & 1u) continue;
+            const bool reached = rnow <= trig[r] * trig[r] * B.rhs_norm2[r];
+            if (reached) claim |= 1u << r;
+            if (rnow < delta2 * maxrr[r] || reached) upd |= 1u << r;
         }
-        if (upd) {
+        const unsigned early = (running && claim == running) ? running : 0;
+        if (upd || early) {
             // fold every x_lo into x64 (exact bookkeeping for all RHS), then
             // replace the residual of the selected RHS by the FP64 one
             TRY(launch_std_block(g, d, n, all, B.x, B.full64, 0, B.xlo, 1, st));
             BSM_HIP(hipMemsetAsync(B.xlo, 0, B.bbB, st));
-            TRY(refresh(upd));
+            auto judge = [&](unsigned sel) -> bsm_status {
+                TRY(true_residuals(sel));
+                for (int r = 0; r < n; r++) {
+                    if (!((sel >> r) & 1u)) continue;
+                    if (trace_enabled())
+                        fprintf(stderr, "[batched]   rhs %d check: true residual %.3e (trigger %.1e)\n", r, res[r],
+                                trig[r]);
+                    if (res[r] <= B.prm->tol) {
+                        status[r] = BSM_OK;
+                        hmask[r] = 0;
+                        active--;
+                        upd &= ~(1u << r);
+                    } else {
+                        trig[r] *= 0.3;
+                        restarts[r]++;
+                    }
+                }
+                waiting = 0;
+                return BSM_OK;
+            };
+            if (early) {
+                TRY(judge(early));
+                for (int r = 0; r < n; r++)   // those that missed tol take the reliable update now
+                    if (((early >> r) & 1u) && hmask[r]) upd |= 1u << r;
+            }
             unsigned chk = 0;
+            if (upd) TRY(refresh(upd));
             for (int r = 0; r < n; r++) {
                 if (!((upd >> r) & 1u)) continue;
                 if (trace_enabled())
@@ -892,24 +932,13 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
                 hs[B_RR * kNR + r] = rr[r];
                 maxrr[r] = rr[r];
                 prev[r] = rr[r];
-                if (rr[r] <= trig[r] * trig[r] * B.rhs_norm2[r]) chk |= 1u << r;
+                if (rr[r] <= trig[r] * trig[r] * B.rhs_norm2[r] && !((early >> r) & 1u)) chk |= 1u << r;
             }
-            if (chk) TRY(true_residuals(chk));
-            for (int r = 0; r < n; r++) {
-                if ((chk >> r) & 1u) {
-                    if (trace_enabled())
-                        fprintf(stderr, "[batched]   rhs %d check: true residual %.3e (trigger %.1e)\n", r, res[r],
-                                trig[r]);
-                    if (res[r] <= B.prm->tol) {
-                        status[r] = BSM_OK;
-                        hmask[r] = 0;
-                        active--;
-                    } else {
-                        trig[r] *= 0.3;
-                        restarts[r]++;
-                    }
-                }
-            }
+            unsigned still = 0;
+            for (int r = 0; r < n; r++)
+                if (hmask[r]) still |= 1u << r;
+            if (chk && (chk | waiting) == still) TRY(judge(still));
+            else waiting |= chk;
             // only |r|^2 and beta change on the host (rows of the updated RHS;
             // the others carry the values just read back)
             BSM_HIP(hipMemcpyAsync(B.scal + B_RR * kNR, hs + B_RR * kNR, kNR * 8, hipMemcpyHostToDevice, st));
@@ -918,13 +947,16 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
             BSM_HIP(hipStreamSynchronize(st));
         }
     }
-    // unconverged RHS: fold the last FP32 part in and report the true residual
+    // RHS still running at max_iter: fold the last FP32 part in and judge
+    // them by their true residual (a check deferred for the others may pass)
     if (active > 0) {
         TRY(launch_std_block(g, d, n, all, B.x, B.full64, 0, B.xlo, 1, st));
         unsigned left = 0;
         for (int r = 0; r < n; r++)
             if (hmask[r]) left |= 1u << r;
         TRY(true_residuals(left));
+        for (int r = 0; r < n; r++)
+            if (((left >> r) & 1u) && status[r] != BSM_ERR_NONFINITE && res[r] <= B.prm->tol) status[r] = BSM_OK;
     }
     bsm_status worst = BSM_OK;
     for (int r = 0; r < n; r++) {
