@@ -838,6 +838,8 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
     std::vector<double> prev(kNR, 0.0);
     for (int r = 0; r < n; r++) prev[r] = rr[r];
     unsigned waiting = 0;   // RHS whose recomputed residual met the trigger, waiting for the others
+    int waited = 0;         // replays since the first of them started waiting
+    constexpr int kMaxWait = 4;   // then they are judged alone (their recurrence keeps shrinking)
     while (active > 0 && it < B.prm->max_iter) {
         BSM_HIP(hipGraphLaunch(B.graph, st));
         it += B.K;
@@ -885,7 +887,9 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
             if (rnow < delta2 * maxrr[r] || reached) upd |= 1u << r;
         }
         const unsigned early = (running && claim == running) ? running : 0;
-        if (upd || early) {
+        waited = waiting ? waited + 1 : 0;
+        const unsigned overdue = (!early && waited > kMaxWait) ? waiting : 0;
+        if (upd || early || overdue) {
             // fold every x_lo into x64 (exact bookkeeping for all RHS), then
             // replace the residual of the selected RHS by the FP64 one
             TRY(launch_std_block(g, d, n, all, B.x, B.full64, 0, B.xlo, 1, st));
@@ -910,10 +914,11 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
                 waiting = 0;
                 return BSM_OK;
             };
-            if (early) {
-                TRY(judge(early));
+            if (early || overdue) {
+                const unsigned sel = early ? early : overdue;
+                TRY(judge(sel));
                 for (int r = 0; r < n; r++)   // those that missed tol take the reliable update now
-                    if (((early >> r) & 1u) && hmask[r]) upd |= 1u << r;
+                    if (((sel >> r) & 1u) && hmask[r]) upd |= 1u << r;
             }
             unsigned chk = 0;
             if (upd) TRY(refresh(upd));
@@ -932,7 +937,7 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
                 hs[B_RR * kNR + r] = rr[r];
                 maxrr[r] = rr[r];
                 prev[r] = rr[r];
-                if (rr[r] <= trig[r] * trig[r] * B.rhs_norm2[r] && !((early >> r) & 1u)) chk |= 1u << r;
+                if (rr[r] <= trig[r] * trig[r] * B.rhs_norm2[r] && !(((early | overdue) >> r) & 1u)) chk |= 1u << r;
             }
             unsigned still = 0;
             for (int r = 0; r < n; r++)

@@ -115,6 +115,39 @@ def test_batched_solve_adjoint(n_rhs):
         assert rel(xs[r], xo) <= 1e-9
 
 
+@pytest.mark.parametrize("prec", ["f32", "f16s"])
+def test_batched_solve_widely_spread_kappas(prec):
+    """Light and heavy members in one block (kappa 0.01 ... 0.125): the light
+    ones meet their trigger replays before the heavy ones and wait (at most a
+    few replays, then judged alone); every member must still meet tol and
+    match the oracle."""
+    note(f"batched solve spread kappas {prec}")
+    lat = gen.Lattice(8, 4, 4, 6)
+    Uf = gen.gauge_links(lat, 4, "haar", 725)
+    S = Setup(lat, 4, "adj", Uf, prec="f64")
+    UR = oracle.represent(Uf, "adj").real.astype(np.complex128)
+    kappas = [0.01, 0.02, 0.04] + list(np.linspace(0.10, 0.125, 13))
+    n_rhs = len(kappas)
+    b = gen.gaussian_spinor(lat, 15, 726, n_rhs=n_rhs)
+    bb = S.pack(b, n_rhs=n_rhs)
+    import torch
+    x = torch.zeros_like(bb)
+    d = S.desc if prec == "f32" else _half_desc(4)   # an F64 descriptor runs the FP32 recurrence
+    prm = bsm.solver_params(0.1, 1e-10, schur=True, check_every=2)
+    status, stats = S.ctx.bsm_batched_solve(d, S.U, prm, kappas, bb, x)
+    xs = S.unpack(x, n_rhs=n_rhs).reshape(b.shape)
+    print([s["iters"] for s in stats], [s["reliable_updates"] for s in stats], flush=True)
+    assert status == 0
+    for r in range(n_rhs):
+        assert stats[r]["converged"]
+        tr = oracle.true_residual(lat, UR, kappas[r], b[r], xs[r])
+        assert tr <= 1e-10, (r, tr)
+        assert abs(tr - stats[r]["true_rel_res"]) < 1e-12
+    for r in (0, n_rhs - 1):
+        xo, _ = oracle.solve(lat, UR, kappas[r], b[r], tol=1e-13, schur=True)
+        assert rel(xs[r], xo) <= 1e-9
+
+
 def test_batched_solve_complex_links_fallback():
     note("batched solve fund fallback")
     lat = gen.Lattice(8, 4, 4, 4)
