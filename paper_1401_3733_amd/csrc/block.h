@@ -133,9 +133,10 @@ struct BlockHop64Args {
     const double *U;
     const double2 *in[2];
     const double2 *x[2];
+    const double2 *y[2];
     double2 *out[2];
-    double a[kNR], b[kNR];   // out_r = a_r x_r + b_r H in_r
-    int use_x;
+    double a[kNR], b[kNR], c[kNR];   // out_r = a_r x_r + b_r H in_r (+ c_r y_r with use_y)
+    int use_x, use_y;
     int dagger;
     int p0, np;
     BlockTile tile;          // site order (block_tile_for)
@@ -148,7 +149,6 @@ bsm_status launch_gauge_to_block64(const Geom &g, int d, const void *U_rep64, do
 // mode 2: the parity block at std_off of the RHS selected in sel = block (std64 is written)
 bsm_status launch_block64_io(const Geom &g, int d, int n_rhs, unsigned sel, const char *std64, size_t std_stride,
                              size_t std_off, double2 *block, float2 *block32, int mode, hipStream_t st);
-bsm_status block64_sub(const Geom &g, int d, double2 *out, const double2 *a, const double2 *b, hipStream_t st);
 // per-RHS |v|^2 into dst[16] (device), partials: block64_norm_parts * 16 doubles
 bsm_status block64_norms(const Geom &g, int d, const double2 *v, double *partials, double *dst, hipStream_t st);
 int block64_norm_parts(const Geom &g, int d);

@@ -119,17 +119,25 @@ void k_hop_block64(Geom g, BlockHop64Args a, int nblk) {
     hop_dir_block64<1, D>(g, a, c, p, h, r, q, eta, acc);
     hop_dir_block64<2, D>(g, a, c, p, h, r, q, eta, acc);
     hop_dir_block64<3, D>(g, a, c, p, h, r, q, eta, acc);
-    const double ar = a.a[r], br = a.b[r];
+    const double ar = a.a[r], br = a.b[r], cr = a.c[r];
     double2 *o = a.out[p] + (size_t)h * SITE;
-    // x first, every load unconditional (rows i >= D read row D - 1 and are
-    // not stored): a load inside the divergent i < D test is waited for there
-    double2 xv[4][4];
+    // x (and y) first, every load unconditional (rows i >= D read row D - 1
+    // and are not stored): a load inside the divergent i < D test is waited
+    // for there
+    double2 xv[4][4], yv[4][4];
     if (a.use_x) {
         const double2 *x = a.x[p] + (size_t)h * SITE;
 #pragma unroll
         for (int v = 0; v < 4; v++)
 #pragma unroll
             for (int s = 0; s < 4; s++) xv[v][s] = x[(size_t)(min(q + 4 * v, D - 1) * 4 + s) * kNR + r];
+    }
+    if (a.use_y) {
+        const double2 *y = a.y[p] + (size_t)h * SITE;
+#pragma unroll
+        for (int v = 0; v < 4; v++)
+#pragma unroll
+            for (int s = 0; s < 4; s++) yv[v][s] = y[(size_t)(min(q + 4 * v, D - 1) * 4 + s) * kNR + r];
     }
 #pragma unroll
     for (int v = 0; v < 4; v++) {
@@ -142,6 +150,10 @@ void k_hop_block64(Geom g, BlockHop64Args a, int nblk) {
                 if (a.use_x) {
                     re = fma(ar, xv[v][s].x, re);
                     im = fma(ar, xv[v][s].y, im);
+                }
+                if (a.use_y) {
+                    re = fma(cr, yv[v][s].x, re);
+                    im = fma(cr, yv[v][s].y, im);
                 }
                 o[e] = make_double2(re, im);
             }
@@ -223,14 +235,6 @@ bsm_status launch_block64_io(const Geom &g, int d, int n_rhs, unsigned sel, cons
     return BSM_OK;
 }
 
-// out = a - b (all slots), per-RHS |out|^2 partials when partials != null
-__global__ __launch_bounds__(256) void k_block64_sub(size_t n, double2 *out, const double2 *a, const double2 *b) {
-    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
-        const double2 x = a[e], y = b[e];
-        out[e] = make_double2(x.x - y.x, x.y - y.y);
-    }
-}
-
 // padding sites (h >= Vh) are skipped: operator outputs never write them
 __global__ __launch_bounds__(256) void k_block64_norm(size_t n, size_t live, const double2 *v, double *partials) {
     double nrm = 0;
@@ -268,12 +272,6 @@ static int block64_grid(const Geom &g, int d) {
     const size_t n = (size_t)g.Vh_pad * d * 4 * kNR;
     size_t nb = (n + 255) / 256;
     return (int)(nb < 4096 ? nb : 4096);
-}
-
-bsm_status block64_sub(const Geom &g, int d, double2 *out, const double2 *a, const double2 *b, hipStream_t st) {
-    k_block64_sub<<<block64_grid(g, d), 256, 0, st>>>((size_t)g.Vh_pad * d * 4 * kNR, out, a, b);
-    BSM_HIP(hipGetLastError());
-    return BSM_OK;
 }
 
 bsm_status block64_norms(const Geom &g, int d, const double2 *v, double *partials, double *dst, hipStream_t st) {

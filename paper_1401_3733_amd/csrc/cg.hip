@@ -627,6 +627,37 @@ static bsm_status block_op64(BlockSolve &B, int dagger, const double2 *in, doubl
     return launch_hop_block64(B.g, B.d, c, B.st);
 }
 
+// out = y - M in (Schur: M = 1 - kappa_r^2 H_eo H_oe), the subtraction in the
+// second hop's epilogue
+static bsm_status block_res64(BlockSolve &B, const double2 *in, const double2 *y, double2 *out) {
+    BlockHop64Args a{};
+    a.U = B.Ublk64;
+    a.dagger = 0;
+    if (B.plan().tiled) a.tile = block_tile_for(B.g);
+    a.xchunk = B.plan().xchunk;
+    a.np = 1;
+    a.p0 = 1;
+    a.in[1] = in;
+    a.out[1] = B.T1;
+    for (int r = 0; r < kNR; r++) { a.a[r] = 0.0; a.b[r] = 1.0; }
+    TRY(launch_hop_block64(B.g, B.d, a, B.st));
+    BlockHop64Args c = a;
+    c.p0 = 0;
+    c.in[0] = B.T1;
+    c.x[0] = in;
+    c.y[0] = y;
+    c.out[0] = out;
+    c.use_x = 1;
+    c.use_y = 1;
+    for (int r = 0; r < kNR; r++) {
+        const double k = r < B.n ? B.kappas[r] : 0.0;
+        c.a[r] = r < B.n ? -1.0 : 0.0;
+        c.b[r] = k * k;
+        c.c[r] = r < B.n ? 1.0 : 0.0;
+    }
+    return launch_hop_block64(B.g, B.d, c, B.st);
+}
+
 // one CG iteration on the block fields: p = r + beta p ; t = M p ; alpha ;
 // q = M^dag t ; x += alpha p ; r -= alpha q ; beta, |r|^2 -> history slot k
 static bsm_status block_iteration(BlockSolve &B, int k) {
@@ -713,6 +744,28 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
         }
         return launch_hop_block64(g, d, a, st);
     };
+    // out = y - xin + kappa_r H in on the parity p0 (a residual of D)
+    auto res64 = [&](int p0, const double2 *in, const double2 *xin, const double2 *y, double2 *out) -> bsm_status {
+        BlockHop64Args a{};
+        a.U = B.Ublk64;
+        a.dagger = 0;
+        a.np = 1;
+        a.p0 = p0;
+        a.in[p0] = in;
+        a.x[p0] = xin;
+        a.y[p0] = y;
+        a.out[p0] = out;
+        a.use_x = 1;
+        a.use_y = 1;
+        if (B.plan().tiled) a.tile = block_tile_for(g);
+        a.xchunk = B.plan().xchunk;
+        for (int r = 0; r < kNR; r++) {
+            a.a[r] = r < n ? -1.0 : 0.0;
+            a.b[r] = r < n ? B.kappas[r] : 0.0;
+            a.c[r] = r < n ? 1.0 : 0.0;
+        }
+        return launch_hop_block64(g, d, a, st);
+    };
     // ---- right-hand sides on the FP64 block operator, every RHS at once:
     //      |b_r|^2, bhat_e = b_e + kappa_r H_eo b_o, |M_r^dag bhat_r|^2
     {
@@ -737,8 +790,7 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
     //      (FP64 block operator: every RHS at once, sharing the link loads)
     auto refresh = [&](unsigned sel) -> bsm_status {
         TRY(launch_block64_io(g, d, n, all, B.x, B.full64, 0, B.X64, nullptr, 0, st));
-        TRY(block_op64(B, 0, B.X64, B.T2));                 // M x
-        TRY(block64_sub(g, d, B.T2, B.BH64, B.T2, st));      // bhat - M x
+        TRY(block_res64(B, B.X64, B.BH64, B.T2));           // bhat - M x
         TRY(block_op64(B, 1, B.T2, B.X64));                 // M^dag (...)
         TRY(block64_norms(g, d, B.X64, B.partials, B.presum, st));
         double h16[kNR];
@@ -758,12 +810,10 @@ static bsm_status solve_block(BlockSolve &B, bsm_solver_stats *stats) {
         TRY(launch_block64_io(g, d, n, all, B.b, B.full64, off_o, B.T2, nullptr, 0, st));    // b_o
         TRY(hop64(1, B.X64, B.T2, 1.0, B.T1));                                              // x_o
         TRY(launch_block64_io(g, d, n, sel, B.x, B.full64, off_o, B.T1, nullptr, 2, st));    // x_o -> x
-        TRY(hop64(1, B.X64, B.T1, -1.0, B.T3));                                             // (D x)_o
-        TRY(block64_sub(g, d, B.T2, B.T2, B.T3, st));
-        TRY(block64_norms(g, d, B.T2, B.partials, B.presum, st));
-        TRY(launch_block64_io(g, d, n, all, B.b, B.full64, 0, B.T3, nullptr, 0, st));        // b_e
-        TRY(hop64(0, B.T1, B.X64, -1.0, B.X64));                                            // (D x)_e, in place
-        TRY(block64_sub(g, d, B.T3, B.T3, B.X64, st));
+        TRY(res64(1, B.X64, B.T1, B.T2, B.T3));                                             // r_o
+        TRY(block64_norms(g, d, B.T3, B.partials, B.presum, st));
+        TRY(launch_block64_io(g, d, n, all, B.b, B.full64, 0, B.T2, nullptr, 0, st));        // b_e
+        TRY(res64(0, B.T1, B.X64, B.T2, B.T3));                                             // r_e
         TRY(block64_norms(g, d, B.T3, B.partials, B.presum + kNR, st));
         double h32[2 * kNR];
         BSM_HIP(hipMemcpyAsync(h32, B.presum, sizeof h32, hipMemcpyDeviceToHost, st));
