@@ -36,6 +36,7 @@
 #include <vector>
 
 #include "blas.h"
+#include "block.h"
 #include "dispatch.h"
 #include "solver.h"
 #include "spinor_io.h"
@@ -221,9 +222,10 @@ extern "C" bsm_status bsm_shifted_solve(bsm_ctx ctx, const bsm_field_desc *desc,
     const size_t coef_bytes = (size_t)n * kMsCoefRow * sizeof(double);
     int L = kMsChunk;
     void *work = nullptr;
+    size_t work_bytes = 0;
     for (;;) {
-        const size_t need = (3 + (size_t)L + 1 + n) * full + (coef_bytes + 255) / 256 * 256;
-        const bsm_status ws = ctx_work(ctx, need, &work);
+        work_bytes = (3 + (size_t)L + 1 + n) * full + (coef_bytes + 255) / 256 * 256;
+        const bsm_status ws = ctx_work(ctx, work_bytes, &work);
         if (ws == BSM_OK) break;
         (void)hipGetLastError();   // the failed allocation's error is not this solve's
         if (L == 1) return ws;
@@ -373,13 +375,70 @@ extern "C" bsm_status bsm_shifted_solve(bsm_ctx ctx, const bsm_field_desc *desc,
     for (int i = 0; i < n; i++) {
         char *xi = X + i * full;
         TRY(blas_axpby(g, d, 2, Vec{xi, BSM_F64}, 1.0 / kappas[i], Vec{xi, BSM_F64}, 0.0, none, nullptr, st));
-        Op o{};
-        o.ctx = ctx; o.g = g; o.d = d; o.real = real; o.schur = false; o.kappa = kappas[i];
-        o.U = U_rep64; o.sprec = BSM_F64; o.lprec = lc; o.partials = ctx->partials;
-        double res = INFINITY;
-        if (!broke || !((active >> i) & 1u)) TRY(true_residual_full(o, (const char *)b, xi, tfull, bnorm2, &res, st));
+    }
+    std::vector<double> res(n, INFINITY);
+    // With real links (d_R 3, 8, 15) and 6 to 16 members, the 16-RHS FP64
+    // block operator forms every member's residual at once in the scratch the
+    // iteration no longer needs: the links are read once for all members, not
+    // once per member.  r_e = b_e - x_e + kappa H_eo x_o, likewise r_o.
+    auto rnd = [](size_t v) { return (v + 255) / 256 * 256; };
+    const size_t bb64 = block64_parity_bytes(g, d), lk64 = block64_link_bytes(g, d);
+    const size_t nparts = (size_t)block64_norm_parts(g, d) * kNR;
+    const size_t need_blk = rnd(lk64) + 3 * rnd(bb64) + rnd(nparts * sizeof(double)) + rnd(2 * kNR * sizeof(double));
+    const bool by_block = real && !link_is_otf(lc) && (d == 3 || d == 8 || d == 15) && n >= 6 && n <= kNR &&
+                          need_blk <= work_bytes;
+    if (by_block) {
+        char *w = (char *)work;
+        auto take = [&](size_t bytes) { char *q = w; w += rnd(bytes); return q; };
+        double *Ub = (double *)take(lk64);
+        double2 *XE = (double2 *)take(bb64), *XO = (double2 *)take(bb64), *BT = (double2 *)take(bb64);
+        double *bparts = (double *)take(nparts * sizeof(double));
+        double *dst = (double *)take(2 * kNR * sizeof(double));
+        const unsigned all = (1u << n) - 1;
+        TRY(launch_gauge_to_block64(g, d, U_rep64, Ub, st));
+        TRY(launch_block64_io(g, d, n, all, X, full, 0, XE, nullptr, 0, st));
+        TRY(launch_block64_io(g, d, n, all, X, full, bb, XO, nullptr, 0, st));
+        auto parity = [&](int p0, const double2 *in, const double2 *xin, size_t b_off, double *nrm) -> bsm_status {
+            // b of this parity for every member (stride 0), then the residual over it
+            TRY(launch_block64_io(g, d, n, all, (const char *)b, 0, b_off, BT, nullptr, 0, st));
+            BlockHop64Args a{};
+            a.U = Ub;
+            a.np = 1;
+            a.p0 = p0;
+            a.in[p0] = in;
+            a.x[p0] = xin;
+            a.y[p0] = BT;    // read before the same site's output is stored
+            a.out[p0] = BT;
+            a.use_x = 1;
+            a.use_y = 1;
+            for (int r = 0; r < kNR; r++) {
+                a.a[r] = r < n ? -1.0 : 0.0;
+                a.b[r] = r < n ? kappas[r] : 0.0;
+                a.c[r] = r < n ? 1.0 : 0.0;
+            }
+            TRY(launch_hop_block64(g, d, a, st));
+            return block64_norms(g, d, BT, bparts, nrm, st);
+        };
+        TRY(parity(0, XO, XE, 0, dst));
+        TRY(parity(1, XE, XO, bb, dst + kNR));
+        double h2[2 * kNR];
+        BSM_HIP(hipMemcpyAsync(h2, dst, sizeof h2, hipMemcpyDeviceToHost, st));
+        BSM_HIP(hipStreamSynchronize(st));
+        for (int i = 0; i < n; i++) {
+            const double rn = h2[i] + h2[kNR + i];
+            res[i] = bnorm2 > 0 ? std::sqrt(rn / bnorm2) : std::sqrt(rn);
+        }
+    } else {
+        for (int i = 0; i < n; i++) {
+            Op o{};
+            o.ctx = ctx; o.g = g; o.d = d; o.real = real; o.schur = false; o.kappa = kappas[i];
+            o.U = U_rep64; o.sprec = BSM_F64; o.lprec = lc; o.partials = ctx->partials;
+            TRY(true_residual_full(o, (const char *)b, X + i * full, tfull, bnorm2, &res[i], st));
+        }
+    }
+    for (int i = 0; i < n; i++) {
         stats[i].iters = iters[i];
-        stats[i].true_rel_res = res;
+        stats[i].true_rel_res = (!broke || !((active >> i) & 1u)) ? res[i] : INFINITY;
     }
     // members that missed tol: plain CG (it reuses the context scratch this
     // solver's fields were carved from, so only caller memory is used here)
