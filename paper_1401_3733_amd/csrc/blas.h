@@ -27,6 +27,12 @@ bsm_status blas_cg_update(const Geom &g, int d, int nblk, Vec x, Vec p, Vec r, V
 // p = r + scal[ib] * p
 bsm_status blas_cg_xpay(const Geom &g, int d, int nblk, Vec p, Vec r, const double *scal, int ib,
                         hipStream_t st);
+// p_out = r + scal[ib] * p_in
+bsm_status blas_cg_xpay_to(const Geom &g, int d, int nblk, Vec p_out, Vec p_in, Vec r, const double *scal, int ib,
+                           hipStream_t st);
+// x += sum_k alphas[k] p_k, p_k = ring slot (slot0 + k) % ring of pbase (slots pstride bytes apart)
+bsm_status blas_x_flush(const Geom &g, int d, int nblk, Vec x, const char *pbase, int pprec, size_t pstride,
+                        int ring, int slot0, int kn, const double *alphas, hipStream_t st);
 
 // dst[0] = sum of n partials (fixed order)
 bsm_status reduce_into(const double *partials, int n, double *dst, hipStream_t st);
@@ -37,6 +43,7 @@ bsm_status reduce_into(const double *partials, int n, double *dst, hipStream_t s
 bsm_status cg_scalars(const double *partials, int n, double *scal, int op, int it, hipStream_t st);
 
 // device scalar slots
-enum { S_RR = 0, S_PAP = 1, S_ALPHA = 2, S_BETA = 3, S_TMP = 4, S_TMP2 = 5, S_HIST = 64 };
+enum { S_RR = 0, S_PAP = 1, S_ALPHA = 2, S_BETA = 3, S_TMP = 4, S_TMP2 = 5, S_AHIST = 16, S_HIST = 64 };
+constexpr int kAlphaHist = S_HIST - S_AHIST;   // alpha of each iteration of a chunk (cg_scalars op 0, it >= 0)
 
 }  // namespace bsm

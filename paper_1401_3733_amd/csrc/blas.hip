@@ -167,31 +167,38 @@ __global__ __launch_bounds__(256) void k_dot(SiteIter it, const void *A, const v
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-// x += alpha p ; r -= alpha q ; partials |r|^2   (x, r in F64 or F32)
+// x += alpha p ; r -= alpha q ; partials |r|^2   (x, r in F64 or F32; x null:
+// r only, the solution is formed later from the kept directions)
 template <int D, int PX, int PP, int PR, int PQ>
 __global__ __launch_bounds__(256) void k_cg_update(SiteIter it, void *x, const void *p, void *r,
                                                    const void *q, const double *scal, int ia,
                                                    double *partials) {
     const double alpha = scal[ia];
+    const bool hx = x != nullptr;
     double nrm = 0;
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < it.n; i += gridDim.x * 256) {
         int b; uint32_t h;
         site_of(i, it.S, b, h);
         if (h >= it.live) continue;
-        Field<PX, D> fx; fx.open(x, b, h, it.S);
-        Field<PP, D> fp; fp.open(p, b, h, it.S);
+        Field<PX, D> fx;
+        Field<PP, D> fp;
+        if (hx) {
+            fx.open(x, b, h, it.S);
+            fp.open(p, b, h, it.S);
+        }
         Field<PR, D> fr; fr.open(r, b, h, it.S);
         Field<PQ, D> fq; fq.open(q, b, h, it.S);
 #pragma unroll
         for (int k = 0; k < D; k++) {
             double vx[8], vp[8], vr[8], vq[8];
-            fx.load(h, k, vx); fp.load(h, k, vp); fr.load(h, k, vr); fq.load(h, k, vq);
+            if (hx) { fx.load(h, k, vx); fp.load(h, k, vp); }
+            fr.load(h, k, vr); fq.load(h, k, vq);
 #pragma unroll
             for (int c = 0; c < 8; c++) {
-                vx[c] = fma(alpha, vp[c], vx[c]);
+                if (hx) vx[c] = fma(alpha, vp[c], vx[c]);
                 vr[c] = fma(-alpha, vq[c], vr[c]);
             }
-            fx.store(h, k, vx);
+            if (hx) fx.store(h, k, vx);
             if constexpr (PR == BSM_F32) {
 #pragma unroll
                 for (int c = 0; c < 8; c++) { double t = (double)(float)vr[c]; nrm += t * t; }
@@ -206,22 +213,23 @@ __global__ __launch_bounds__(256) void k_cg_update(SiteIter it, void *x, const v
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-// p = r + beta p
+// p = r + beta p_in  (p_in = p in place)
 template <int D, int PP, int PR>
 __global__ __launch_bounds__(256) void k_cg_xpay(SiteIter it, void *p, const void *r, const double *scal,
-                                                 int ib) {
+                                                 int ib, const void *p_in) {
     const double beta = scal[ib];
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < it.n; i += gridDim.x * 256) {
         int b; uint32_t h;
         site_of(i, it.S, b, h);
         if (h >= it.live) continue;
         Field<PP, D> fp; fp.open(p, b, h, it.S);
+        Field<PP, D> fi; fi.open(p_in, b, h, it.S);
         Field<PR, D> fr; fr.open(r, b, h, it.S);
         float buf[PP == BSM_F16S ? 8 * D : 1];
 #pragma unroll
         for (int k = 0; k < D; k++) {
             double vp[8], vr[8];
-            fp.load(h, k, vp); fr.load(h, k, vr);
+            fi.load(h, k, vp); fr.load(h, k, vr);
 #pragma unroll
             for (int c = 0; c < 8; c++) vp[c] = fma(beta, vp[c], vr[c]);
             if constexpr (PP == BSM_F16S) {
@@ -340,11 +348,11 @@ struct CgByD {
         } else {
             // p = r + beta p
             if (p.prec == BSM_F64 && r.prec == BSM_F64)
-                k_cg_xpay<D, BSM_F64, BSM_F64><<<nb, 256, 0, st>>>(it, p.ptr, r.ptr, scal, ib);
+                k_cg_xpay<D, BSM_F64, BSM_F64><<<nb, 256, 0, st>>>(it, p.ptr, r.ptr, scal, ib, x.ptr ? x.ptr : p.ptr);
             else if (p.prec == BSM_F32 && r.prec == BSM_F32)
-                k_cg_xpay<D, BSM_F32, BSM_F32><<<nb, 256, 0, st>>>(it, p.ptr, r.ptr, scal, ib);
+                k_cg_xpay<D, BSM_F32, BSM_F32><<<nb, 256, 0, st>>>(it, p.ptr, r.ptr, scal, ib, x.ptr ? x.ptr : p.ptr);
             else if (p.prec == BSM_F16S && r.prec == BSM_F32)
-                k_cg_xpay<D, BSM_F16S, BSM_F32><<<nb, 256, 0, st>>>(it, p.ptr, r.ptr, scal, ib);
+                k_cg_xpay<D, BSM_F16S, BSM_F32><<<nb, 256, 0, st>>>(it, p.ptr, r.ptr, scal, ib, x.ptr ? x.ptr : p.ptr);
             else
                 return fail(BSM_ERR_UNSUPPORTED, "cg_xpay precision combination");
         }
@@ -362,6 +370,63 @@ bsm_status blas_cg_xpay(const Geom &g, int d, int nblk, Vec p, Vec r, const doub
                         hipStream_t st) {
     Vec none{nullptr, BSM_F64};
     return dispatch_d<CgByD>(d, g, nblk, none, p, r, none, scal, 0, (double *)nullptr, st, 1, ib);
+}
+
+bsm_status blas_cg_xpay_to(const Geom &g, int d, int nblk, Vec p_out, Vec p_in, Vec r, const double *scal, int ib,
+                           hipStream_t st) {
+    if (p_in.prec != p_out.prec) return fail(BSM_ERR_ARG, "cg_xpay: p_in and p_out differ in precision");
+    Vec none{nullptr, BSM_F64};
+    // the kernel takes p_in through the (otherwise unused) x slot
+    return dispatch_d<CgByD>(d, g, nblk, p_in, p_out, r, none, scal, 0, (double *)nullptr, st, 1, ib);
+}
+
+// x += sum_k alphas[k] p_k over kn kept directions, p_k the ring slot
+// (slot0 + k) % ring, slots pstride bytes apart
+template <int D, int PX, int PP>
+__global__ __launch_bounds__(256) void k_x_flush(SiteIter it, void *x, const char *pbase, size_t pstride, int ring,
+                                                 int slot0, int kn, const double *alphas) {
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < it.n; i += gridDim.x * 256) {
+        int b; uint32_t h;
+        site_of(i, it.S, b, h);
+        if (h >= it.live) continue;
+        Field<PX, D> fx; fx.open(x, b, h, it.S);
+        for (int k = 0; k < D; k++) {
+            double vx[8];
+            fx.load(h, k, vx);
+            for (int j = 0; j < kn; j++) {
+                Field<PP, D> fp; fp.open(pbase + (size_t)((slot0 + j) % ring) * pstride, b, h, it.S);
+                double vp[8];
+                fp.load(h, k, vp);
+                const double a = alphas[j];
+#pragma unroll
+                for (int c = 0; c < 8; c++) vx[c] = fma(a, vp[c], vx[c]);
+            }
+            fx.store(h, k, vx);
+        }
+    }
+}
+
+template <int D>
+struct XFlushByD {
+    static bsm_status run(const Geom &g, int nblk, Vec x, const char *pbase, int pprec, size_t pstride, int ring,
+                          int slot0, int kn, const double *alphas, hipStream_t st) {
+        SiteIter it = iter_of(g, nblk);
+        const int nb = blas_blocks(g, nblk);
+        if (x.prec == BSM_F32 && pprec == BSM_F32)
+            k_x_flush<D, BSM_F32, BSM_F32><<<nb, 256, 0, st>>>(it, x.ptr, pbase, pstride, ring, slot0, kn, alphas);
+        else if (x.prec == BSM_F32 && pprec == BSM_F16S)
+            k_x_flush<D, BSM_F32, BSM_F16S><<<nb, 256, 0, st>>>(it, x.ptr, pbase, pstride, ring, slot0, kn, alphas);
+        else
+            return fail(BSM_ERR_UNSUPPORTED, "x_flush precision combination");
+        BSM_HIP(hipGetLastError());
+        return BSM_OK;
+    }
+};
+
+bsm_status blas_x_flush(const Geom &g, int d, int nblk, Vec x, const char *pbase, int pprec, size_t pstride,
+                        int ring, int slot0, int kn, const double *alphas, hipStream_t st) {
+    if (kn <= 0) return BSM_OK;
+    return dispatch_d<XFlushByD>(d, g, nblk, x, pbase, pprec, pstride, ring, slot0, kn, alphas, st);
 }
 
 // ------------------------------------------------------------- reductions
@@ -385,6 +450,7 @@ __global__ __launch_bounds__(256) void k_cg_scalars(const double *partials, int 
         double rr = scal[S_RR];
         double al = rr / s;
         scal[S_ALPHA] = (s > 0 && isfinite(al)) ? al : 0.0;
+        if (it >= 0 && it < kAlphaHist) scal[S_AHIST + it] = scal[S_ALPHA];
     } else if (op == 1) {
         double rr = scal[S_RR];
         double be = s / rr;

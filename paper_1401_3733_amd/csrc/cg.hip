@@ -300,11 +300,17 @@ static bsm_status solve_mixed(Solver &S, int inner_prec, int link_prec, const vo
     size_t vlo = nb * spinor_block_bytes(inner_prec, d, g.Vh_pad);
     size_t vacc = nb * spinor_block_bytes(acc_prec, d, g.Vh_pad);
     size_t base = Solver::work_bytes64(g, d, S.schur);
+    // K iterations per chunk; the chunk's directions p are kept (a ring of
+    // K + 1) and x_lo takes sum_k alpha_k p_k once at the chunk's end rather
+    // than alpha p every iteration
+    const int hist_cap = kScalars - S_HIST;
+    const int K = std::max(1, std::min(S.prm->check_every > 0 ? S.prm->check_every : 8, kAlphaHist));
+    const int ring = K + 1;
     void *work = nullptr;
-    TRY(ctx_work(S.ctx, base + 3 * vlo + 2 * vacc + spinor_block_bytes(inner_prec, d, g.Vh_pad), &work));
+    TRY(ctx_work(S.ctx, base + (ring + 2) * vlo + 2 * vacc + spinor_block_bytes(inner_prec, d, g.Vh_pad), &work));
     TRY(S.setup(work));
     char *w = (char *)work + base;
-    char *p = w; w += vlo;
+    char *pring = w; w += ring * vlo;
     char *t = w; w += vlo;
     char *q = w; w += vlo;
     char *xlo = w; w += vacc;
@@ -314,9 +320,9 @@ static bsm_status solve_mixed(Solver &S, int inner_prec, int link_prec, const vo
     double *scal = S.ctx->scal;
     double *hs = S.ctx->host_scal;
     Vec X64{S.x, BSM_F64}, R64{S.r64, BSM_F64};
-    Vec P{p, inner_prec}, Q{q, inner_prec}, XL{xlo, acc_prec}, RL{rlo, acc_prec};
+    auto Pslot = [&](int i) { return Vec{pring + (size_t)(i % ring) * vlo, inner_prec}; };
+    Vec Q{q, inner_prec}, XL{xlo, acc_prec}, RL{rlo, acc_prec};
     Vec none{nullptr, BSM_F64};
-    const int hist_cap = kScalars - S_HIST;
     const double delta2 = S.prm->delta > 0 ? S.prm->delta * S.prm->delta : 0.01;
 
     // r64 = M^dag (bhat - M x64), |r64|^2 ; r_lo = r64 ; p = r_lo ; x_lo = 0
@@ -334,7 +340,6 @@ static bsm_status solve_mixed(Solver &S, int inner_prec, int link_prec, const vo
     // 32^3 x 64 (K = 1 / 8 / 16): two-index F16+scale with F16 links
     // 0.167 / 0.130 / 0.125 s (fewer reliable updates), fundamental
     // 0.123 / 0.119 / 0.121 s (K = 16 adds iterations).
-    const int K = std::max(1, std::min(S.prm->check_every > 0 ? S.prm->check_every : 8, hist_cap));
     double trig = S.prm->tol;
     int it = 0, restarts = 0, updates = 0;
     double res = INFINITY;
@@ -351,7 +356,7 @@ static bsm_status solve_mixed(Solver &S, int inner_prec, int link_prec, const vo
     };
     TRY(reliable(&rr));
     BSM_HIP(hipMemsetAsync(xlo, 0, vacc, st));
-    BSM_HIP(hipMemsetAsync(p, 0, vlo, st));
+    BSM_HIP(hipMemsetAsync(pring, 0, ring * vlo, st));
     TRY(restart_from_true(rr));
     double maxrr = rr;
     for (;;) {
@@ -360,15 +365,18 @@ static bsm_status solve_mixed(Solver &S, int inner_prec, int link_prec, const vo
         while (!check && it < S.prm->max_iter) {
             const int k0 = it, kn = std::min(K, S.prm->max_iter - it);
             for (int k = 0; k < kn; k++) {
-                TRY(blas_cg_xpay(g, d, nb, P, RL, scal, S_BETA, st));
+                const Vec P = Pslot(it);
+                TRY(blas_cg_xpay_to(g, d, nb, P, Pslot(it + ring - 1), RL, scal, S_BETA, st));
                 int np = 0;
-                TRY(op_apply(lo, 0, p, t, true, &np, st));
-                TRY(cg_scalars(S.ctx->partials, np, scal, 0, 0, st));
+                TRY(op_apply(lo, 0, P.ptr, t, true, &np, st));
+                TRY(cg_scalars(S.ctx->partials, np, scal, 0, k, st));   // alpha_k kept for x
                 TRY(op_apply(lo, 1, t, q, false, nullptr, st));
-                TRY(blas_cg_update(g, d, nb, XL, P, RL, Q, scal, S_ALPHA, S.ctx->partials, st));
+                TRY(blas_cg_update(g, d, nb, Vec{nullptr, acc_prec}, P, RL, Q, scal, S_ALPHA, S.ctx->partials, st));
                 TRY(cg_scalars(S.ctx->partials, blas_blocks(g, nb), scal, 1, (it + 1) % hist_cap, st));
                 it++;
             }
+            // x_lo += sum_k alpha_k p_k over this chunk's directions
+            TRY(blas_x_flush(g, d, nb, XL, pring, inner_prec, vlo, ring, k0 % ring, kn, scal + S_AHIST, st));
             for (int k = k0 + 1; k <= it; k++) {
                 const int sl = k % hist_cap;
                 BSM_HIP(hipMemcpyAsync(hs + S_HIST + sl, scal + S_HIST + sl, sizeof(double), hipMemcpyDeviceToHost,
