@@ -277,7 +277,9 @@ typedef struct {
  * <= tol, otherwise iteration continues with the trigger tightened by 0.3.
  * Both run check_every iterations between host checks (check_every <= 0:
  * 8); MIXED decides its reliable updates there, from the |r|^2 of every
- * iteration of the chunk.
+ * iteration of the chunk, keeps the chunk's search directions (at most 48
+ * iterations per chunk; check_every + 1 inner-precision fields of scratch)
+ * and adds them to its low-precision solution once per chunk.
  * Synchronous: returns when done, with stats filled in even on failure. */
 bsm_status bsm_cg_solve(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_rep,
                         const void *U_rep64, const bsm_solver_params *params, const void *b,
