@@ -182,7 +182,7 @@ bsm_status bsm_dslash_eo(bsm_ctx ctx, const bsm_field_desc *desc, const void *U_
  *   order 2: as order 0 without the per-XCD regrouping;
  *   order 3: column sweep: one thread per spatial site over tchunk
  *            consecutive time slices, time neighbours reused from registers
- *            (d_R <= 6);
+ *            (d_R <= 6; stored or fundamental links);
  *   order 4: XCD bands: each of the 8 XCDs owns 1/8 of the 256-site tiles
  *            of every time slice and walks its band t-major, so time
  *            neighbours are re-read from its own L2 (tchunk ignored).

@@ -73,9 +73,9 @@ bsm_status ctx_solver_stream(bsm_ctx ctx, hipStream_t *out) {
 
 int hop_blocks(const Geom &g) { return (g.Vh + 255) / 256; }
 
-static bool plan_fits(const Geom &g, const HopPlan &p, int d, bool otf = false) {
+static bool plan_fits(const Geom &g, const HopPlan &p, int d, bool /*otf*/ = false) {
     if (p.order == 0 || p.order == 2) return true;
-    if (p.order == 3 && (d > kColMaxD || otf)) return false;
+    if (p.order == 3 && d > kColMaxD) return false;
     int64_t S3 = (int64_t)g.Vh / g.L[0];
     if (p.order == 4) return S3 % (256 * kXcds) == 0;
     return p.tchunk >= 1 && S3 % 256 == 0 && g.L[0] % p.tchunk == 0;

@@ -358,8 +358,10 @@ __global__ __launch_bounds__(256) void k_hop_otf(
 // kept in a two-deep register ring.  Workgroups cover 256 consecutive s with
 // the spatial tile fastest, so the spatial neighbours of a time slice are
 // read by workgroups running at the same time, from contiguous memory.
-template <int D, bool REAL, int SP, int LP>
-__global__ __launch_bounds__(256) void k_hop_col(Geom g, HopArgs a, int nblk) {
+// RN != 0: fundamental links, the representation formed on the fly in the
+// time hops as in hop_dir_otf (and there for the spatial directions).
+template <int D, bool REAL, int SP, int LP, int RN>
+__device__ inline void hop_col_body(const Geom &g, const HopArgs &a, int nblk) {
     using T = typename Compute<SP>::T;
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
     const int pi = lb >= (uint32_t)nblk ? 1 : 0;
@@ -371,7 +373,7 @@ __global__ __launch_bounds__(256) void k_hop_col(Geom g, HopArgs a, int nblk) {
     const uint32_t s = (bl - chunk * ntile) * 256 + threadIdx.x;
     const int T0 = (int)chunk * a.tchunk;
     const int LT = g.L[0];
-    const size_t lblk = link_block_bytes(LP, REAL, D, g.Vh_pad);
+    const size_t lblk = RN ? link_block_bytes(LP, false, otf_n(RN), g.Vh_pad) : link_block_bytes(LP, REAL, D, g.Vh_pad);
     const char *in = (const char *)a.in[p];
     const char *U = (const char *)a.U;
     const T eta = a.dagger ? (T)-1 : (T)1;
@@ -404,38 +406,85 @@ __global__ __launch_bounds__(256) void k_hop_col(Geom g, HopArgs a, int nblk) {
         const uint32_t hp = (uint32_t)tp * S3 + s;
         const uint32_t hm = (uint32_t)(t == 0 ? LT - 1 : t - 1) * S3 + s;
         cx<T> nb0[D], nb1[D];
-        {
-            cx<T> sp[4 * D], f0[D], f1[D];
-            load_spinor<SP, D, T>(in, g.Vh_pad, hp, sp);
-            const char *blk = link_block<0, false>(U, lblk, p);
-            LinkRegs<D, REAL, LP, true, T> L;
-            L.load(blk, g.Vh_pad, h);
-            project<0, D, T>(sp, eta, f0, f1);
-            project<0, D, T>(sp, -eta, nb0, nb1);
-            const T wf = (apt && t + 1 == LT) ? (T)-1 : (T)1;
-            hop_half<0, D, REAL, LP, false, T>(g, L, blk, h, eta, wf, f0, f1, acc);
-        }
-        {
-            const T wb = (apt && t == 0) ? (T)-1 : (T)1;
-            const char *blk = link_block<0, true>(U, lblk, p);
-            LinkRegs<D, REAL, LP, true, T> L;
-            L.load(blk, g.Vh_pad, hm);
-            hop_half<0, D, REAL, LP, true, T>(g, L, blk, hm, -eta, wb, r0a, r0b, acc);
+        const T wf = (apt && t + 1 == LT) ? (T)-1 : (T)1;
+        const T wb = (apt && t == 0) ? (T)-1 : (T)1;
+        if constexpr (RN != 0) {
+            constexpr int N = otf_n(RN);
+            constexpr bool NT = (BSM_LINK_NT >> SP) & 1;
+            {
+                cx<T> sp[4 * D], f0[D], f1[D], g0[D], g1[D];
+                load_spinor<SP, D, T>(in, g.Vh_pad, hp, sp);
+                const char *blk = link_block<0, false>(U, lblk, p);
+                cx<T> u[N * N];
+#pragma unroll
+                for (int e = 0; e < N * N; e++) u[e] = load_link<LP, false, T, NT>(blk, g.Vh_pad, e, h);
+                project<0, D, T>(sp, eta, f0, f1);
+                project<0, D, T>(sp, -eta, nb0, nb1);
+                rep_apply<RN, false, T>(u, f0, g0);
+                rep_apply<RN, false, T>(u, f1, g1);
+                reconstruct<0, D, T>(acc, eta, wf, g0, g1);
+                otf_pin<SP, RN>(acc);
+            }
+            {
+                cx<T> g0[D], g1[D];
+                const char *blk = link_block<0, true>(U, lblk, p);
+                cx<T> u[N * N];
+#pragma unroll
+                for (int e = 0; e < N * N; e++) u[e] = load_link<LP, false, T, NT>(blk, g.Vh_pad, e, hm);
+                rep_apply<RN, true, T>(u, r0a, g0);
+                rep_apply<RN, true, T>(u, r0b, g1);
+                reconstruct<0, D, T>(acc, -eta, wb, g0, g1);
+                otf_pin<SP, RN>(acc);
+            }
+        } else {
+            {
+                cx<T> sp[4 * D], f0[D], f1[D];
+                load_spinor<SP, D, T>(in, g.Vh_pad, hp, sp);
+                const char *blk = link_block<0, false>(U, lblk, p);
+                LinkRegs<D, REAL, LP, true, T> L;
+                L.load(blk, g.Vh_pad, h);
+                project<0, D, T>(sp, eta, f0, f1);
+                project<0, D, T>(sp, -eta, nb0, nb1);
+                hop_half<0, D, REAL, LP, false, T>(g, L, blk, h, eta, wf, f0, f1, acc);
+            }
+            {
+                const char *blk = link_block<0, true>(U, lblk, p);
+                LinkRegs<D, REAL, LP, true, T> L;
+                L.load(blk, g.Vh_pad, hm);
+                hop_half<0, D, REAL, LP, true, T>(g, L, blk, hm, -eta, wb, r0a, r0b, acc);
+            }
         }
 #pragma unroll
         for (int i = 0; i < D; i++) {
             r0a[i] = r1a[i]; r0b[i] = r1b[i];
             r1a[i] = nb0[i]; r1b[i] = nb1[i];
         }
-        hop_dir<1, D, REAL, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
-        hop_dir<2, D, REAL, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
-        hop_dir<3, D, REAL, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
+        if constexpr (RN != 0) {
+            hop_dir_otf<1, RN, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
+            hop_dir_otf<2, RN, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
+            hop_dir_otf<3, RN, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
+        } else {
+            hop_dir<1, D, REAL, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
+            hop_dir<2, D, REAL, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
+            hop_dir<3, D, REAL, SP, LP, T>(g, c, p, h, U, lblk, in, eta, acc);
+        }
         nrm += hop_epilogue<D, SP, T>(g, a, p, h, acc);
     }
     if (a.norm_partials) {
         double sum = block_sum_256(nrm);
         if (threadIdx.x == 0) a.norm_partials[lb] = sum;
     }
+}
+
+template <int D, bool REAL, int SP, int LP>
+__global__ __launch_bounds__(256) void k_hop_col(Geom g, HopArgs a, int nblk) {
+    hop_col_body<D, REAL, SP, LP, 0>(g, a, nblk);
+}
+
+// the column sweep with fundamental links
+template <int D, int SP, int LP, int RN>
+__global__ __launch_bounds__(256) void k_hop_col_otf(Geom g, HopArgs a, int nblk) {
+    hop_col_body<D, false, SP, LP, RN>(g, a, nblk);
 }
 
 // Launch for one (spinor precision, link precision, d_R); the definitions are
@@ -650,16 +699,21 @@ bsm_status hop_run(const Geom &g, bool real, const HopArgs &a, hipStream_t st) {
 }
 
 // fundamental links, representation RN formed on the fly (one thread per
-// site; no colour split and no column sweep)
+// site, or the column sweep for d_R <= 6; no colour split)
 template <int SP, int LP, int RN>
 bsm_status hop_run_otf(const Geom &g, const HopArgs &a, hipStream_t st) {
-    if (a.wide > 0 || a.order == 3) return fail(BSM_ERR_ARG, "on-the-fly hop: plan not available");
+    constexpr int D = otf_dim(RN);
+    if (a.wide > 0 || (a.order == 3 && D > kColMaxD)) return fail(BSM_ERR_ARG, "on-the-fly hop: plan not available");
     const int grid = hop_grid(g, a);
     const int nblk = grid / a.np;
     if (a.norm_partials && (int64_t)grid > a.norm_cap)
         return fail(BSM_ERR_ARG, "fused-norm hop needs " + std::to_string(grid) + " reduction slots, " +
                                      std::to_string(a.norm_cap) + " available");
-    k_hop_otf<otf_dim(RN), SP, LP, RN><<<grid, 256, 0, st>>>(g, a, nblk);
+    if (a.order == 3) {
+        if constexpr (D <= kColMaxD) k_hop_col_otf<D, SP, LP, RN><<<grid, 256, 0, st>>>(g, a, nblk);
+    } else {
+        k_hop_otf<D, SP, LP, RN><<<grid, 256, 0, st>>>(g, a, nblk);
+    }
     BSM_HIP(hipGetLastError());
     return BSM_OK;
 }

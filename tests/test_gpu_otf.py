@@ -188,3 +188,63 @@ def test_otf_refused_where_links_must_be_stored():
     with pytest.raises(bsm.BsmError) as e:
         S.ctx.bsm_batched_solve(d64, U64, bsm.solver_params(0.1), [0.1], b, torch.zeros_like(b))
     assert e.value.status == bsm.ERR_ARG
+
+
+COL = [(2, "sym"), (3, "sym"), (3, "asym"), (4, "asym"), (2, "adj")]   # d_R <= 6
+
+
+@pytest.mark.parametrize("tchunk", [1, 3, 6])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 1e-6)])
+@pytest.mark.parametrize("N,rep", COL)
+def test_otf_column_plan_matches_oracle(N, rep, prec, tol, tchunk):
+    """The column sweep (plan 3) with fundamental links: each thread walks
+    tchunk time slices of one spatial site, reusing the time neighbours from
+    registers.  T = 6 with antiperiodic time: the chunk that starts at t = 0
+    and the one that wraps to it both cross the boundary."""
+    d = oracle.rep_dim(N, rep)
+    note(f"otf column plan N={N} {rep} {prec} tchunk={tchunk}")
+    lat = gen.Lattice(6, 8, 8, 8, bc=(-1, 1, 1, 1))      # LX*LY*LZ/2 = 256: one tile per time slice
+    Uf = gen.gauge_links(lat, N, "haar", 840 + N)
+    S = Setup(lat, N, rep, Uf, prec=prec, fundamental_links=True)
+    S.ctx.bsm_set_hop_plan(S.desc, 3, tchunk)
+    assert S.ctx.bsm_get_hop_plan(S.desc)["order"] == 3
+    UR = _rep_links(Uf, rep)
+    par = oracle.parity_mask(lat)
+    psi = gen.gaussian_spinor(lat, d, 841)
+    xf = gen.gaussian_spinor(lat, d, 842)
+    inp, xin = S.pack(psi), S.pack(xf)
+    for p in (0, 1):
+        for dag in (0, 1):
+            out = S.ctx.new_spinor(S.desc)
+            S.ctx.bsm_dslash_eo(S.desc, S.U, p, dag, 0.7, S.block(xin, p), -0.3, S.block(inp, 1 - p),
+                                S.block(out, p))
+            got = S.unpack(out)
+            ref = 0.7 * xf - 0.3 * oracle.hop(lat, UR, psi, dagger=bool(dag), parity=p)
+            m = par == p
+            err = rel(got[m], ref[m])
+            assert err <= tol, (p, dag, err)
+            assert np.all(got[~m] == 0)
+
+
+@pytest.mark.parametrize("link_prec", ["f32", "f16s"])
+@pytest.mark.parametrize("N,rep", [(3, "sym"), (4, "asym")])
+def test_otf_column_plan_f16_spinors_equal_site_plan(N, rep, link_prec):
+    """FP16 spinors: the column sweep performs the same per-site arithmetic as
+    the one-thread-per-site plan (same hops, same order), so the two agree to
+    FP32 rounding of the accumulation."""
+    d = oracle.rep_dim(N, rep)
+    note(f"otf column plan f16s N={N} {rep} links {link_prec}")
+    lat = gen.Lattice(6, 8, 8, 8, bc=(-1, 1, 1, 1))
+    Uf = gen.gauge_links(lat, N, "haar", 850 + N)
+    S = Setup(lat, N, rep, Uf, prec="f16s", link_prec=link_prec, fundamental_links=True)
+    psi = gen.gaussian_spinor(lat, d, 851)
+    inp = S.pack(psi)
+    outs = []
+    for order, tchunk in ((0, 1), (3, 2), (3, 6)):
+        S.ctx.bsm_set_hop_plan(S.desc, order, tchunk)
+        out = S.ctx.new_spinor(S.desc)
+        for p in (0, 1):
+            S.ctx.bsm_dslash_eo(S.desc, S.U, p, 0, 0.0, S.block(inp, p), 1.0, S.block(inp, 1 - p), S.block(out, p))
+        outs.append(S.unpack(out))
+    for o in outs[1:]:
+        assert rel(o, outs[0]) <= 2e-3      # F16 output codes: one unit in the last place at most
